@@ -1,0 +1,259 @@
+"""The CPU oracle checked against what the paper and the mathematics fix.
+
+Each test pins a part of the oracle to something other than itself:
+  exact tiny tori (state vector and double-layer network, Eq. Tred)  -> nested network, impurities
+  D = 1 product states (Neel -1/4, uniform +1/4 per bond)             -> whole sweep + energy
+  hand-built singlet products (columnar, orthogonal dimers)          -> sweep + energy at D = 2
+  decoupled vertical chains (transfer-matrix closed form)            -> sweep with correlations
+  truncated SVD of rho = N S^T computed directly                      -> projectors (Eqs. PQ, QRSVD)
+  central finite differences and the scale-invariance identity       -> gradient (Eq. AD)
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.adjoint import Projectors, energy_after_sweeps, energy_and_grad, detach_env
+from oracle.ctmrg import CTM, bond_projectors
+from oracle.exact import bond_expectation, brute_rdm, double_layer_rdm, nested_rdm
+from oracle.rdm import energy, pair_rdm, plaquette_rdm
+
+H = synth.heisenberg_bond()
+
+
+# --- nested network on exact tori ----------------------------------------
+
+@pytest.mark.parametrize("pattern,n_t,seed", [([[0, 1], [2, 3]], 4, 0), ([[0, 1, 0], [1, 0, 1]], 2, 1)])
+def test_nested_torus_equals_state_vector(pattern, n_t, seed):
+    A = synth.site_tensors(n_t, 2, 2, seed, "uniform")
+    Lx, Ly = len(pattern[0]), len(pattern)
+    pairs = [[(0, 0), (1, 0)], [(0, 0), (0, 1)], [(0, 0), (1, 1)], [(1, 0), (0, 1)]]
+    for sites in pairs:
+        ref = brute_rdm(A, pattern, sites)
+        assert torch.allclose(nested_rdm(A, pattern, sites), ref, rtol=0, atol=1e-14 * ref.abs().max())
+        assert torch.allclose(double_layer_rdm(A, pattern, sites), ref, rtol=0, atol=1e-14 * ref.abs().max())
+
+
+def test_nested_torus_single_site_norm():
+    A = synth.site_tensors(4, 2, 2, 3, "normal")
+    pattern = [[0, 1], [2, 3]]
+    psi = brute_rdm(A, pattern, [(1, 1)])
+    nested = nested_rdm(A, pattern, [(1, 1)])
+    assert torch.allclose(psi, nested, rtol=1e-13, atol=0)
+
+
+# --- closed forms ------------------------------------------------------------
+
+def _bloch(v):
+    v = np.asarray(v, float) / np.linalg.norm(v)
+    return np.array([2 * v[0] * v[1], 0.0, v[0] ** 2 - v[1] ** 2])
+
+
+def test_neel_product_state():
+    A = synth.product_state_tensors([[1.0, 0.0], [0.0, 1.0]])
+    c = CTM(A, [[0, 1], [1, 0]], chi=2)
+    c.run(3)
+    E = energy(c, H, synth.heisenberg_terms(2, 2)).item()
+    assert abs(E - (-0.5)) < 1e-13          # -1/4 per bond, two bonds per site
+
+
+def test_uniform_product_state():
+    A = synth.product_state_tensors([[0.6, 0.8]])
+    c = CTM(A, [[0]], chi=4)
+    c.run(3)
+    assert abs(energy(c, H, synth.heisenberg_terms(1, 1)).item() - 0.5) < 1e-13
+
+
+def test_random_product_states_bond_by_bond():
+    rng = np.random.default_rng(4)
+    v = rng.uniform(-1, 1, (4, 2))
+    A = synth.product_state_tensors(v)
+    pattern = [[0, 1], [2, 3]]
+    c = CTM(A, pattern, chi=3)
+    c.run(2)
+    n = [_bloch(x) / 2 for x in v]
+    site = {(0, 0): 0, (1, 0): 1, (0, 1): 2, (1, 1): 3}
+    for (px, py) in site:
+        rho = plaquette_rdm(c.sites, c.env, px, py)
+        members = [(px, py), ((px + 1) % 2, py), (px, (py + 1) % 2), ((px + 1) % 2, (py + 1) % 2)]
+        for a in range(4):
+            for b in range(a + 1, 4):
+                got = torch.einsum("ji,ij->", torch.as_tensor(H), pair_rdm(rho, a, b)) / torch.trace(rho)
+                want = n[site[members[a]]] @ n[site[members[b]]]
+                assert abs(got.item() - want) < 1e-13
+
+
+def test_columnar_dimers_exact_plaquette():
+    A0 = synth.columnar_dimer_tensors()
+    A = synth.gauge_transform(A0, [[0, 1]], 1)
+    c = CTM(A, [[0, 1]], chi=8)
+    c.run(8)
+    assert abs(energy(c, H, synth.heisenberg_terms(2, 1)).item() + 0.375) < 1e-13
+    pat4 = [[[0, 1][x % 2] for x in range(4)] for _ in range(4)]
+    for p in [(0, 0), (1, 0)]:
+        rho = plaquette_rdm(c.sites, c.env, *p)
+        rho = rho / torch.trace(rho)
+        ex = brute_rdm(A0, pat4, [p, (p[0] + 1, p[1]), (p[0], p[1] + 1), (p[0] + 1, p[1] + 1)]).reshape(16, 16)
+        assert torch.allclose(rho, ex / torch.trace(ex), atol=1e-13, rtol=0)
+
+
+def test_orthogonal_dimers_energy():
+    A0 = synth.orthogonal_dimer_tensors()
+    pattern = [[0, 1], [2, 3]]
+    pat4 = [[pattern[y % 2][x % 2] for x in range(4)] for y in range(4)]
+    # the hand-built state really is the orthogonal-dimer product (brute force on a 4x4 torus)
+    assert abs(bond_expectation(brute_rdm(A0, pat4, [(0, 0), (1, 1)]).reshape(2, 2, 2, 2), H) + 0.75) < 1e-14
+    assert abs(bond_expectation(brute_rdm(A0, pat4, [(2, 1), (1, 2)]).reshape(2, 2, 2, 2), H) + 0.75) < 1e-14
+    A = synth.gauge_transform(A0, pattern, 2)
+    for J_nn in (0.7, 0.8):
+        c = CTM(A, pattern, chi=8)
+        c.run(10)
+        E = energy(c, H, synth.shastry_sutherland_terms(J_nn, 1.0)).item()
+        assert abs(E + 0.375) < 1e-12            # -3/8 J_dimer: an exact eigenstate of Eq. SSM
+
+
+def test_orthogonal_dimers_full_rdm_from_generic_start():
+    A0 = synth.orthogonal_dimer_tensors()
+    pattern = [[0, 1], [2, 3]]
+    pat4 = [[pattern[y % 2][x % 2] for x in range(4)] for y in range(4)]
+    A = synth.gauge_transform(A0, pattern, 2)
+    env0 = synth.random_env_flat(8, 2, 2, 2, 2, seed=0)
+    c = CTM(A, pattern, chi=8, env0=env0)
+    c.run(30)
+    for p in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+        rho = plaquette_rdm(c.sites, c.env, *p)
+        rho = rho / torch.trace(rho)
+        ex = brute_rdm(A0, pat4, [p, (p[0] + 1, p[1]), (p[0], p[1] + 1), (p[0] + 1, p[1] + 1)]).reshape(16, 16)
+        assert torch.allclose(rho, ex / torch.trace(ex), atol=1e-12, rtol=0)
+
+
+def _chain_exact(A):
+    """Infinite vertical MPS: vertical S.S from the transfer matrix, horizontal = <S>.<S>."""
+    M = A[0][:, 0, :, 0, :]                                   # M[s, u, d]
+    T = np.einsum("sud,svf->uvdf", M, M).reshape(4, 4)
+    w, vr = np.linalg.eig(T)
+    i = np.argmax(abs(w))
+    lam, r = w[i].real, vr[:, i].real
+    wl, vl = np.linalg.eig(T.T)
+    l = vl[:, np.argmax(abs(wl))].real
+    sx, _, sz = synth.spin_half_ops()
+
+    def one(O):      # <O> = sum O[b, k] rho[k, b]
+        return l @ np.einsum("bk,kud,bvf->uvdf", O, M, M).reshape(4, 4) @ r / (lam * (l @ r))
+
+    h = H.reshape(2, 2, 2, 2)
+    ev = 0.0
+    for k1 in range(2):
+        for k2 in range(2):
+            for b1 in range(2):
+                for b2 in range(2):
+                    X = np.kron(M[k1], M[b1]) @ np.kron(M[k2], M[b2])
+                    ev += h[b1, b2, k1, k2] * (l @ X @ r)
+    ev /= lam ** 2 * (l @ r)
+    eh = one(sx) ** 2 + one(sz) ** 2
+    return eh, ev
+
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_decoupled_vertical_chains(seed):
+    A = synth.vertical_chain_tensors(seed)
+    eh, ev = _chain_exact(A)
+    env0 = synth.random_env_flat(8, 2, 2, 1, 1, seed=1)
+    c = CTM(A, [[0]], chi=8, env0=env0)
+    c.run(300, tol=1e-12)
+    rho = plaquette_rdm(c.sites, c.env, 0, 0)
+    Ht = torch.as_tensor(H)
+    got_h = (torch.einsum("ji,ij->", Ht, pair_rdm(rho, 0, 1)) / torch.trace(rho)).item()
+    got_v = (torch.einsum("ji,ij->", Ht, pair_rdm(rho, 0, 2)) / torch.trace(rho)).item()
+    assert abs(got_h - eh) < 1e-9 and abs(got_v - ev) < 1e-9
+    assert abs(energy(c, H, synth.heisenberg_terms(1, 1)).item() - (eh + ev)) < 1e-9
+
+
+# --- projectors ----------------------------------------------------------------
+
+@pytest.mark.parametrize("m,kd,chi", [(20, 12, 6), (12, 20, 6), (16, 16, 16), (16, 16, 5)])
+def test_projectors_give_truncated_svd_of_rho(m, kd, chi):
+    g = torch.Generator().manual_seed(m * 100 + kd)
+    N = torch.randn(m, kd, generator=g, dtype=torch.float64)
+    S = torch.randn(m, kd, generator=g, dtype=torch.float64)
+    P, Q, s = bond_projectors(N, S, chi, 1e-12)
+    approx = N @ P @ Q.T @ S.T
+    u, sv, vh = np.linalg.svd((N @ S.T).numpy())
+    k = min(chi, len(s))
+    best = (u[:, :k] * sv[:k]) @ vh[:k]
+    assert np.allclose(approx.numpy(), best, atol=1e-10 * sv[0], rtol=0)
+    # P, Q equal S^T V_rho Lambda^-1/2 and N^T U_rho Lambda^-1/2 up to a common sign per column
+    Pd = S.numpy().T @ vh[:k].T / np.sqrt(sv[:k])
+    Qd = N.numpy().T @ u[:, :k] / np.sqrt(sv[:k])
+    sign = np.sign(np.sum(P.numpy() * Pd, axis=0))
+    assert np.allclose(P.numpy(), Pd * sign, atol=1e-9 * abs(Pd).max())
+    assert np.allclose(Q.numpy(), Qd * sign, atol=1e-9 * abs(Qd).max())
+
+
+def test_projector_derivative_matches_library_autograd():
+    g = torch.Generator().manual_seed(5)
+    for (m, kd, chi) in [(12, 8, 5), (8, 12, 5), (10, 10, 4)]:
+        N = torch.randn(m, kd, generator=g, dtype=torch.float64, requires_grad=True)
+        S = torch.randn(m, kd, generator=g, dtype=torch.float64, requires_grad=True)
+        Wp = torch.randn(kd, chi, generator=g, dtype=torch.float64)
+        Wq = torch.randn(kd, chi, generator=g, dtype=torch.float64)
+        P, Q, _ = Projectors.apply(N, S, chi, 1e-12, 1e-12)
+        a = torch.autograd.grad((P * Wp).sum() + (Q * Wq).sum(), (N, S))
+        P2, Q2, _ = bond_projectors(N, S, chi, 1e-12)
+        b = torch.autograd.grad((P2 * Wp).sum() + (Q2 * Wq).sum(), (N, S))
+        for x, y in zip(a, b):
+            assert torch.allclose(x, y, atol=1e-11 * y.abs().max(), rtol=0)
+
+
+# --- gradient -------------------------------------------------------------------
+
+def test_gradient_central_differences_and_scale_identity():
+    cfg = synth.CONFIGS["heis_d2_chi8"]
+    A = synth.config_tensors(cfg, 1)
+    c = CTM(A, cfg["pattern"], chi=8)
+    c.run(80)
+    terms = synth.config_terms(cfg)
+    E, g, _ = energy_and_grad(A, cfg["pattern"], 8, c.env, 2, H, terms)
+    At = torch.as_tensor(A)
+    assert abs((g * At).sum().item()) < 1e-12     # E is invariant under A -> c A
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for _ in range(5):
+        ix = tuple(int(rng.integers(0, n)) for n in A.shape)
+        Ap, Am = At.clone(), At.clone()
+        Ap[ix] += h
+        Am[ix] -= h
+        Ep = energy_after_sweeps(Ap, cfg["pattern"], 8, detach_env(c.env), 2, H, terms)[0].item()
+        Em = energy_after_sweeps(Am, cfg["pattern"], 8, detach_env(c.env), 2, H, terms)[0].item()
+        fd = (Ep - Em) / (2 * h)
+        assert abs(fd - g[ix].item()) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_product_state_gradient_closed_form():
+    """D = 1 uniform state: E = 2 |<S>|^2 per site with <S> from the Bloch vector; dE/dv in closed form."""
+    v = np.array([0.6, 0.3])
+    A = synth.product_state_tensors([v])
+    c = CTM(A, [[0]], chi=2)
+    c.run(2)
+    E, g, _ = energy_and_grad(A, [[0]], 2, c.env, 1, H, synth.heisenberg_terms(1, 1))
+    n2 = v @ v
+    # E = 2 * (1/4)|n|^2 with n = (2 v0 v1, v0^2 - v1^2)/|v|^2 ; |n| = 1 for any real v, so E = 1/2, dE/dv = 0
+    assert abs(E - 0.5) < 1e-13
+    assert g.abs().max().item() < 1e-12
+    # Neel pair: E = -1/2 independent of the (real) states' norm, gradient orthogonal to each tensor
+    A2 = synth.product_state_tensors([[0.9, 0.1], [0.2, -0.7]])
+    c2 = CTM(A2, [[0, 1], [1, 0]], chi=2)
+    c2.run(2)
+    E2, g2, _ = energy_and_grad(A2, [[0, 1], [1, 0]], 2, c2.env, 1, H, synth.heisenberg_terms(2, 2))
+    v0, v1 = np.array([0.9, 0.1]), np.array([0.2, -0.7])
+    n0, n1 = _bloch(v0), _bloch(v1)
+    assert abs(E2 - 0.5 * (n0 @ n1)) < 1e-13      # two bonds per site, each <S>.<S> = n0.n1/4
+
+    def jac(v):      # d n / d v for n = (2 v0 v1, 0, v0^2 - v1^2) / |v|^2
+        q = v @ v
+        nx, nz = 2 * v[0] * v[1] / q, (v[0] ** 2 - v[1] ** 2) / q
+        return np.array([[2 * v[1] / q - nx * 2 * v[0] / q, 2 * v[0] / q - nx * 2 * v[1] / q],
+                         [0.0, 0.0],
+                         [2 * v[0] / q - nz * 2 * v[0] / q, -2 * v[1] / q - nz * 2 * v[1] / q]])
+    assert np.allclose(g2[0, :, 0, 0, 0, 0].numpy(), 0.5 * jac(v0).T @ n1, atol=1e-12)
+    assert np.allclose(g2[1, :, 0, 0, 0, 0].numpy(), 0.5 * jac(v1).T @ n0, atol=1e-12)
