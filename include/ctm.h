@@ -1,0 +1,140 @@
+/* C ABI of the single-layer (nested) CTMRG library for MI355X (gfx950).
+ *
+ * Method: arXiv:2512.14414, "Single-layer framework of variational tensor
+ * network states".  The norm <Psi|Psi> of an iPEPS is contracted as one nested
+ * single-layer network (Sec. II B, Eq. XY, Fig. NTN): the ket tensor A and the
+ * bra tensor A* are absorbed into the corner (C) and edge (T) tensors one
+ * layer at a time, on a nested cell of 2Lx x 2Ly sites (Sec. II C).  The
+ * environment is computed by multi-site CTMRG (Fig. CTMRG) with projectors
+ * from a QR decomposition of the two halves of a 2x2 cluster followed by a
+ * truncated SVD (Eqs. PQ, QRSVD); the energy per site is E = <H>/<Psi|Psi>
+ * (Eq. ExpH) from 2x2 reduced density matrices with opened physical lines
+ * (the impurity tensors of Sec. II B); the gradient is the reverse-mode
+ * derivative of that chain (Eq. AD), shortened as proposed in Sec. IV.
+ *
+ * Conventions
+ * -----------
+ * Site tensors: n_tensors real tensors A_t[s][l][u][r][d] (C order, float64),
+ *   physical index s of dimension d, virtual legs l, u, r, d of dimension D.
+ * Unit cell: Lx columns x Ly rows of PEPS sites; pattern[y*Lx + x] is the
+ *   tensor index at column x, row y (rows grow downward).
+ * Terms: a ctm_term (px, py, a, b, coef) is the bond operator H_bond acting on
+ *   sites a and b (0 = top-left, 1 = top-right, 2 = bottom-left, 3 =
+ *   bottom-right) of the plaquette whose top-left site is (px, py); the energy
+ *   per site is (1/(Lx*Ly)) * sum coef * <H_bond>_ab.
+ * H_bond: d^2 x d^2 row-major matrix H[(s_a s_b)][(s_a' s_b')] on the host.
+ * Environment layout ("flat env", float64): the nested positions (I, J) of the
+ *   2Ly x 2Lx cell in row-major order; for each, C1, C2, C3, C4 (chi x chi)
+ *   then T1, T2, T3, T4 (chi x leg x chi).  Legs are listed counter-clockwise
+ *   around the site: C1[down][right], C2[left][down], C3[up][left],
+ *   C4[right][up], T1[left][s][right], T2[up][s][down], T3[right][s][left],
+ *   T4[down][s][up]; the s leg of T1/T2/T3/T4 is the up/right/down/left leg
+ *   of the nested site at (I, J).  Nested site kinds: K (ket, legs D, D, D*d,
+ *   D) at (even, even), Y (D*d, D, D, D*d) at (even, odd), X (D, D, D, D) at
+ *   (odd, even), B (bra, D, D*d, D, D) at (odd, odd); a fused leg is (virtual
+ *   index major, physical index minor).
+ *
+ * Memory: every pointer documented as "device" is a HIP device pointer on the
+ * current device; "host" pointers are ordinary host memory.  The caller owns
+ * all buffers it passes; the library copies what it keeps.  Work is queued on
+ * the stream given to ctm_init (a hipStream_t passed as void*, NULL for the
+ * default stream); calls that return host values synchronise that stream.
+ *
+ * Errors: every call returns CTM_OK (0), a warning (> 0) or an error (< 0).
+ * ctm_last_error gives the message.  After an error the context stays valid.
+ * A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ctm_ctx ctm_ctx;
+
+enum {
+  CTM_OK = 0,
+  CTM_ENOTCONV = 1,      /* warning: max_sweeps reached before delta < tol (results still written) */
+  CTM_EINVAL = -1,       /* invalid argument */
+  CTM_ENOMEM = -2,       /* device allocation failed */
+  CTM_EHIP = -3,         /* HIP runtime or kernel launch error */
+  CTM_ESOLVER = -4,      /* QR or SVD reported failure (rocSOLVER info != 0) */
+  CTM_ENONFINITE = -5    /* NaN or Inf found in the environment or the result */
+};
+
+enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16 = 2 };
+
+typedef struct {
+  int px, py;    /* plaquette: top-left PEPS site, 0 <= px < Lx, 0 <= py < Ly */
+  int a, b;      /* two distinct sites of the plaquette, 0..3 */
+  double coef;   /* weight of <H_bond>_ab in the energy per site times Lx*Ly */
+} ctm_term;
+
+/* Create a context for site tensors A (device, n_tensors*d*D^4 float64, copied)
+ * and set the sites-derived starting environment: every C and T is the
+ * neighbouring nested site with its outward legs summed over all indices.
+ * precision: CTM_FP64 (all contractions FP64), CTM_FP32 (environment and
+ * contractions FP32) or CTM_BF16 (environment FP32, contraction operands
+ * rounded to bfloat16, FP32 accumulation).  In every mode the projector QR and
+ * SVD (Eq. QRSVD), the projector weights, the norms and the energy sum are
+ * FP64.  Requires d >= 1, D >= 1, chi >= D*d, Lx, Ly >= 1, pattern ids in
+ * [0, n_tensors).  On error *out is NULL. */
+int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
+             int n_tensors, int precision, void* stream);
+
+/* Replace the site tensors (device, same shape as in ctm_init); the environment is kept. */
+int ctm_set_tensors(ctm_ctx* ctx, const double* A);
+
+/* Restore the sites-derived starting environment of ctm_init. */
+int ctm_reset_env(ctm_ctx* ctx);
+
+/* Number of float64 values of the flat environment layout. */
+int64_t ctm_env_size(const ctm_ctx* ctx);
+
+/* Copy the environment in from / out to a device float64 buffer of ctm_env_size values. */
+int ctm_set_env(ctm_ctx* ctx, const double* env);
+int ctm_get_env(ctm_ctx* ctx, double* env);
+
+/* CTMRG iterations (Sec. II C): each sweep is a left, right, up and down move;
+ * a move has 2Lx (left/right) or 2Ly (up/down) column steps, and each step
+ * computes the projectors of all rows (Eqs. PQ, QRSVD) and then updates
+ * C1, T4, C4 of the next column (Fig. CTMRG b) with Frobenius normalisation.
+ * If tol > 0, after each sweep delta = max over corners of the L1 distance of
+ * the normalised singular-value spectra to the previous sweep, and the loop
+ * stops once delta < tol; returns CTM_ENOTCONV if max_sweeps is reached
+ * first.  sweeps_done and delta (host, may be NULL) receive the count and the
+ * last delta (delta is -1 when tol <= 0). */
+int ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done, double* delta);
+
+/* Energy per site (Eq. ExpH) from the current environment: for every plaquette
+ * named by a term, the 2x2 reduced density matrix rho (d^4 x d^4, ket indices
+ * of the four sites as row, bra indices as column, Sec. II B impurities) is
+ * contracted; <H>_ab = sum H[(b_a b_b)][(k_a k_b)] rho_ab[(k_a k_b)][(b_a b_b)] / Tr rho.
+ * H_bond and terms are host arrays; E (host) receives the result. */
+int ctm_energy(ctm_ctx* ctx, const double* H_bond, int n_terms, const ctm_term* terms, double* E);
+
+/* Plaquette density matrices of the last ctm_energy call, copied to a host
+ * buffer of n * d^8 float64 values in the order of first appearance of the
+ * plaquettes in the term list; n (host) receives the count. */
+int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
+
+/* Options (key, value):
+ *   "svd_cutoff"  relative cutoff below which s^(-1/2) is set to zero (default 1e-12)
+ *   "lorentz_eta" relative Lorentzian width of the SVD derivative (default 1e-12)
+ *   "check_finite" 1 to test the environment for NaN/Inf after every sweep (default 1) */
+int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
+
+/* Message of the last error of this context (or of the last failed ctm_init if ctx is NULL). */
+const char* ctm_last_error(const ctm_ctx* ctx);
+
+/* Release the context and its device memory (NULL is allowed). */
+void ctm_free(ctm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTM_H */

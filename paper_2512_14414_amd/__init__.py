@@ -1,0 +1,6 @@
+"""Single-layer (nested) CTMRG for iPEPS on MI355X (arXiv:2512.14414).
+
+The computation lives in libctm.so (HIP kernels for gfx950, C ABI in
+include/ctm.h); ``CTM`` is its thin Python binding.
+"""
+from .binding import CTM, CTMError, EXPORTED, LIB, LIB_PATH, PRECISIONS  # noqa: F401

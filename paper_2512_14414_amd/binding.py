@@ -1,0 +1,154 @@
+"""ctypes binding of libctm.so (include/ctm.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+stream; every step of the computation runs in the library's HIP kernels.
+There is no fallback: if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctm.so")
+
+CTM_OK, CTM_ENOTCONV = 0, 1
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+class CTMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ctm error {code}: {msg}")
+        self.code = code
+
+
+class Term(ctypes.Structure):
+    _fields_ = [("px", ctypes.c_int), ("py", ctypes.c_int), ("a", ctypes.c_int), ("b", ctypes.c_int),
+                ("coef", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2512_14414_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    sig = {
+        "ctm_init": (I, [ctypes.POINTER(P), P, I, I, I, I, I, ctypes.POINTER(I), I, I, P]),
+        "ctm_set_tensors": (I, [P, P]),
+        "ctm_reset_env": (I, [P]),
+        "ctm_env_size": (I64, [P]),
+        "ctm_set_env": (I, [P, P]),
+        "ctm_get_env": (I, [P, P]),
+        "ctm_sweep": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "ctm_energy": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D)]),
+        "ctm_last_rdms": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
+        "ctm_set_option": (I, [P, ctypes.c_char_p, D]),
+        "ctm_last_error": (ctypes.c_char_p, [P]),
+        "ctm_free": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype, f.argtypes = res, args
+    return lib
+
+
+LIB = _load()
+EXPORTED = ("ctm_init", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
+            "ctm_sweep", "ctm_energy", "ctm_last_rdms", "ctm_set_option", "ctm_last_error", "ctm_free")
+
+
+def _terms(terms):
+    arr = (Term * max(1, len(terms)))()
+    for i, (px, py, a, b, coef) in enumerate(terms):
+        arr[i] = Term(px, py, a, b, coef)
+    return arr
+
+
+def _dptr(t: torch.Tensor, dtype=torch.float64):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA tensor of dtype %s" % dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class CTM:
+    """A CTMRG context on the current GPU (one per set of site tensors)."""
+
+    def __init__(self, A, pattern, chi, precision="fp64", stream=None):
+        A = torch.as_tensor(A, dtype=torch.float64)
+        if not A.is_cuda:
+            A = A.cuda()
+        self.A = A.contiguous()
+        n_t, d, D = self.A.shape[0], self.A.shape[1], self.A.shape[2]
+        self.d, self.D, self.chi = d, D, chi
+        self.Ly, self.Lx = len(pattern), len(pattern[0])
+        self.pattern = pattern
+        flat = (ctypes.c_int * (self.Lx * self.Ly))(*[pattern[y][x] for y in range(self.Ly) for x in range(self.Lx)])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        rc = LIB.ctm_init(ctypes.byref(self._h), _dptr(self.A), d, D, chi, self.Lx, self.Ly, flat, n_t,
+                          PRECISIONS[precision], ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != CTM_OK:
+            raise CTMError(rc, LIB.ctm_last_error(None).decode())
+
+    def _check(self, rc, allow=(CTM_OK,)):
+        if rc not in allow:
+            raise CTMError(rc, LIB.ctm_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if self._h:
+            LIB.ctm_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tensors(self, A):
+        self.A = torch.as_tensor(A, dtype=torch.float64).cuda().contiguous()
+        self._check(LIB.ctm_set_tensors(self._h, _dptr(self.A)))
+
+    def reset_env(self):
+        self._check(LIB.ctm_reset_env(self._h))
+
+    def env_size(self):
+        return int(LIB.ctm_env_size(self._h))
+
+    def get_env(self):
+        out = torch.empty(self.env_size(), dtype=torch.float64, device=self.A.device)
+        self._check(LIB.ctm_get_env(self._h, _dptr(out)))
+        return out
+
+    def set_env(self, env):
+        env = torch.as_tensor(env, dtype=torch.float64).to(self.A.device).contiguous()
+        if env.numel() != self.env_size():
+            raise ValueError("environment has the wrong size")
+        self._check(LIB.ctm_set_env(self._h, _dptr(env)))
+
+    def sweep(self, max_sweeps, tol=0.0):
+        n, dl = ctypes.c_int(), ctypes.c_double()
+        rc = self._check(LIB.ctm_sweep(self._h, max_sweeps, tol, ctypes.byref(n), ctypes.byref(dl)),
+                         allow=(CTM_OK, CTM_ENOTCONV))
+        return n.value, dl.value, rc == CTM_OK
+
+    def energy(self, H, terms):
+        H = (ctypes.c_double * 16)(*[float(v) for v in torch.as_tensor(H, dtype=torch.float64).reshape(-1).tolist()])
+        E = ctypes.c_double()
+        self._check(LIB.ctm_energy(self._h, H, len(terms), _terms(terms), ctypes.byref(E)))
+        return E.value
+
+    def last_rdms(self, capacity=16):
+        d8 = self.d ** 8
+        buf = (ctypes.c_double * (capacity * d8))()
+        n = ctypes.c_int()
+        self._check(LIB.ctm_last_rdms(self._h, buf, capacity, ctypes.byref(n)))
+        k = min(n.value, capacity)
+        d4 = self.d ** 4
+        return torch.tensor(list(buf[: k * d8]), dtype=torch.float64).reshape(k, d4, d4)
+
+    def set_option(self, key, value):
+        self._check(LIB.ctm_set_option(self._h, key.encode(), float(value)))

@@ -1,0 +1,780 @@
+// Nested single-layer CTMRG on one MI355X: context, moves, energy and C ABI.
+//
+// Method: arXiv:2512.14414, Sec. II C (multi-site CTMRG on the nested cell,
+// Fig. CTMRG, Eqs. PQ and QRSVD), Sec. II B (nested network, Eq. XY; impurity
+// tensors for local operators) and Eq. ExpH (energy).
+//
+// Frames.  The right, up and down moves are the left move of the lattice
+// turned by two, one and three quarter turns counter-clockwise.  Environment
+// legs are listed counter-clockwise around each site (see include/ctm.h), so
+// a quarter turn maps the tensors C2, C3, C4, C1 and T2, T3, T4, T1 of a
+// position onto C1, C2, C3, C4 and T1, T2, T3, T4 of the turned position
+// without moving any data; only the site tensors are stored once per frame.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ctm.h"
+#include "engine.h"
+#include "kernels.h"
+
+using namespace ctm;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+#define RB_CHECK(expr)                                                                                    \
+  do {                                                                                                    \
+    rocblas_status s_ = (expr);                                                                           \
+    if (s_ != rocblas_status_success) throw Error(CTM_ESOLVER, std::string(#expr) + ": rocblas status " + \
+                                                               std::to_string((int)s_));                  \
+  } while (0)
+
+struct SiteRef {
+  void* p = nullptr;
+  int64_t dim[4] = {0, 0, 0, 0};   // l, u, r, d
+};
+
+// Unique one-character labels for named bonds.
+struct Labels {
+  std::map<std::string, char> m;
+  char next = 33;
+  char operator()(const std::string& name) {
+    auto it = m.find(name);
+    if (it != m.end()) return it->second;
+    if (next > 126) throw Error(CTM_EINVAL, "label pool exhausted");
+    char c = next++;
+    m[name] = c;
+    return c;
+  }
+};
+
+}  // namespace
+
+struct ctm_ctx {
+  Dev dev;
+  rocblas_handle blas = nullptr;
+  int d = 0, D = 0, chi = 0, Lx = 0, Ly = 0, nt = 0, prec = 0, NY = 0, NX = 0;
+  std::vector<int> pattern;
+  int st = T_F64;                 // storage type of sites and environment
+  int mode = ctmk::MODE_F64;      // matrix-core path for float contractions
+  DBuf A64;                       // float64 copy of the site tensors
+  DBuf site_buf;
+  std::vector<SiteRef> frames[4];
+  DBuf env;
+  std::vector<int64_t> slot_off, slot_leg;
+  int64_t env_elems = 0;
+  double cutoff = 1e-12, eta = 1e-12;
+  int check_finite = 1;
+  DBuf spec_prev, spec_cur, dscal;   // spectra and a few device scalars
+  bool have_prev = false;
+  DBuf rdm_buf;
+  int n_rdm = 0;
+  DBuf flag;                      // int flags: [0] non-finite, [1..] solver info
+  std::string err;
+
+  int ny(int f) const { return (f & 1) ? NX : NY; }
+  int nx(int f) const { return (f & 1) ? NY : NX; }
+  int kind(int I, int J) const { return (I & 1) * 2 + (J & 1); }   // 0 K, 1 Y, 2 X, 3 B
+  void leg_dims(int I, int J, int64_t* l) const {
+    int64_t Dd = (int64_t)D * d;
+    switch (kind(I, J)) {
+      case 0: l[0] = D; l[1] = D; l[2] = Dd; l[3] = D; break;
+      case 1: l[0] = Dd; l[1] = D; l[2] = D; l[3] = Dd; break;
+      case 2: l[0] = D; l[1] = D; l[2] = D; l[3] = D; break;
+      default: l[0] = D; l[1] = Dd; l[2] = D; l[3] = D; break;
+    }
+  }
+  // frame-f position -> frame-0 position
+  void to_orig(int f, int I, int J, int& oi, int& oj) const {
+    int rows = ny(f);
+    for (int t = 0; t < f; ++t) {
+      int i = J, j = rows - 1 - I;
+      I = i; J = j;
+      rows = (rows == NY) ? NX : NY;   // rows of the previous frame
+    }
+    oi = I; oj = J;
+  }
+  SiteRef site(int f, int I, int J) const {
+    int a = ny(f), b = nx(f);
+    I = ((I % a) + a) % a; J = ((J % b) + b) % b;
+    return frames[f][(size_t)I * b + J];
+  }
+  TRef site_t(int f, int I, int J, const std::string& lab) const {
+    SiteRef s = site(f, I, J);
+    return view(s.p, st, {s.dim[0], s.dim[1], s.dim[2], s.dim[3]}, lab);
+  }
+  // environment tensor ``slot`` (0..3 = C1..C4, 4..7 = T1..T4) of frame-f position (I, J)
+  TRef slot(int f, int I, int J, int k, const std::string& lab) const {
+    int a = ny(f), b = nx(f);
+    I = ((I % a) + a) % a; J = ((J % b) + b) % b;
+    int oi, oj;
+    to_orig(f, I, J, oi, oj);
+    int ok = ((k & 3) + f) % 4 + (k & 4);
+    size_t idx = ((size_t)oi * NX + oj) * 8 + ok;
+    char* base = (char*)env.p + slot_off[idx] * type_size(st);
+    if (k < 4) return view(base, st, {chi, chi}, lab);
+    return view(base, st, {chi, slot_leg[idx], chi}, lab);
+  }
+};
+
+namespace {
+
+void build_layout(ctm_ctx* c) {
+  c->slot_off.assign((size_t)c->NY * c->NX * 8, 0);
+  c->slot_leg.assign((size_t)c->NY * c->NX * 8, 0);
+  int64_t off = 0;
+  for (int I = 0; I < c->NY; ++I)
+    for (int J = 0; J < c->NX; ++J) {
+      int64_t l[4];
+      c->leg_dims(I, J, l);
+      const int64_t tleg[4] = {l[1], l[2], l[3], l[0]};   // T1 up, T2 right, T3 down, T4 left
+      for (int k = 0; k < 8; ++k) {
+        size_t idx = ((size_t)I * c->NX + J) * 8 + k;
+        c->slot_off[idx] = off;
+        if (k < 4) off += (int64_t)c->chi * c->chi;
+        else {
+          c->slot_leg[idx] = tleg[k - 4];
+          off += (int64_t)c->chi * tleg[k - 4] * c->chi;
+        }
+      }
+    }
+  c->env_elems = off;
+}
+
+// Dense nested sites of every frame from the float64 site tensors.
+void build_sites(ctm_ctx* c) {
+  Dev& dev = c->dev;
+  const int d = c->d, D = c->D;
+  const int64_t Dd = (int64_t)D * d, n4 = (int64_t)D * D * D * D;
+  // host-built delta tensors X[l,u,r,d] = d(l,r) d(u,d) and Y[(l,s),u,r,(d,s')] = d(l,r) d(u,d) d(s,s')
+  std::vector<double> X(n4, 0.0), Y((size_t)Dd * D * D * Dd, 0.0);
+  for (int l = 0; l < D; ++l)
+    for (int u = 0; u < D; ++u) X[((size_t)(l * D + u) * D + l) * D + u] = 1.0;
+  for (int l = 0; l < D; ++l)
+    for (int s = 0; s < d; ++s)
+      for (int u = 0; u < D; ++u) {
+        int64_t li = (int64_t)l * d + s, di = (int64_t)u * d + s;
+        Y[((size_t)(li * D + u) * D + l) * Dd + di] = 1.0;
+      }
+  DBuf xy(&dev, (X.size() + Y.size()) * 8);
+  HIP_CHECK(hipMemcpyAsync(xy.p, X.data(), X.size() * 8, hipMemcpyHostToDevice, dev.stream));
+  HIP_CHECK(hipMemcpyAsync((double*)xy.p + X.size(), Y.data(), Y.size() * 8, hipMemcpyHostToDevice, dev.stream));
+  TRef Xt = view(xy.p, T_F64, {D, D, D, D}, "lurd");
+  TRef Yt = view((double*)xy.p + X.size(), T_F64, {Dd, D, D, Dd}, "lurd");
+
+  // per frame: K_t, B_t for each tensor, X, Y  (each d*D^4 or D^4 or d^2 D^4 elements)
+  const int64_t nk = (int64_t)d * n4, ny_ = (int64_t)d * d * n4;
+  const int64_t per_frame = 2 * c->nt * nk + n4 + ny_;
+  if (!c->site_buf.p) c->site_buf = DBuf(&dev, (size_t)(4 * per_frame) * type_size(c->st));
+  char* base = (char*)c->site_buf.p;
+  const size_t es = type_size(c->st);
+  const std::string lurd = "lurd";
+  for (int f = 0; f < 4; ++f) {
+    std::string rl;
+    for (int i = 0; i < 4; ++i) rl += lurd[(i + f) % 4];   // new axis i = old axis (i+f) mod 4
+    auto rot_dims = [&](const int64_t* od, int64_t* nd) {
+      for (int i = 0; i < 4; ++i) nd[i] = od[(i + f) % 4];
+    };
+    char* fb = base + (size_t)f * per_frame * es;
+    std::vector<SiteRef> K(c->nt), B(c->nt);
+    SiteRef Xr, Yr;
+    for (int t = 0; t < c->nt; ++t) {
+      TRef At = view((double*)c->A64.p + t * nk, T_F64, {d, D, D, D, D}, "slurd");
+      // K[l,u,(r s),d] and B[l,(u s),r,d]
+      int64_t kd0[4] = {D, D, Dd, D}, bd0[4] = {D, Dd, D, D}, nd[4];
+      // K in frame 0 as a 5-axis view over a temporary, then rotated
+      Tmp k0(&dev, T_F64, {D, D, D, d, D}, "lursd");
+      copy_into(dev, k0.t, At);
+      Tmp b0(&dev, T_F64, {D, D, d, D, D}, "lusrd");
+      copy_into(dev, b0.t, At);
+      rot_dims(kd0, nd);
+      K[t].p = fb + (size_t)(2 * t) * nk * es;
+      std::memcpy(K[t].dim, nd, sizeof(nd));
+      copy_into(dev, view(K[t].p, c->st, {nd[0], nd[1], nd[2], nd[3]}, rl),
+                view(k0.buf.p, T_F64, {kd0[0], kd0[1], kd0[2], kd0[3]}, lurd));
+      rot_dims(bd0, nd);
+      B[t].p = fb + (size_t)(2 * t + 1) * nk * es;
+      std::memcpy(B[t].dim, nd, sizeof(nd));
+      copy_into(dev, view(B[t].p, c->st, {nd[0], nd[1], nd[2], nd[3]}, rl),
+                view(b0.buf.p, T_F64, {bd0[0], bd0[1], bd0[2], bd0[3]}, lurd));
+    }
+    {
+      int64_t xd0[4] = {D, D, D, D}, yd0[4] = {Dd, D, D, Dd}, nd[4];
+      rot_dims(xd0, nd);
+      Xr.p = fb + (size_t)(2 * c->nt) * nk * es;
+      std::memcpy(Xr.dim, nd, sizeof(nd));
+      copy_into(dev, view(Xr.p, c->st, {nd[0], nd[1], nd[2], nd[3]}, rl), Xt);
+      rot_dims(yd0, nd);
+      Yr.p = fb + ((size_t)(2 * c->nt) * nk + n4) * es;
+      std::memcpy(Yr.dim, nd, sizeof(nd));
+      copy_into(dev, view(Yr.p, c->st, {nd[0], nd[1], nd[2], nd[3]}, rl), Yt);
+    }
+    int a = c->ny(f), b = c->nx(f);
+    c->frames[f].assign((size_t)a * b, SiteRef());
+    for (int I = 0; I < a; ++I)
+      for (int J = 0; J < b; ++J) {
+        int oi, oj;
+        c->to_orig(f, I, J, oi, oj);
+        int t = c->pattern[(size_t)(oi / 2) * c->Lx + (oj / 2)];
+        SiteRef s;
+        switch (c->kind(oi, oj)) {
+          case 0: s = K[t]; break;
+          case 1: s = Yr; break;
+          case 2: s = Xr; break;
+          default: s = B[t]; break;
+        }
+        c->frames[f][(size_t)I * b + J] = s;
+      }
+  }
+}
+
+// Sites-derived starting environment (frame 0): each tensor is the nested
+// neighbour with its outward legs summed over all indices.
+void init_env(ctm_ctx* c) {
+  Dev& dev = c->dev;
+  fill(dev, view(c->env.p, c->st, {c->env_elems}, "e"), 0.0);
+  int64_t mx = (int64_t)c->D * c->d;
+  Tmp ones(&dev, c->st, {mx, mx}, "pq");
+  fill(dev, ones.t, 1.0);
+  for (int I = 0; I < c->NY; ++I)
+    for (int J = 0; J < c->NX; ++J) {
+      auto nb = [&](int di, int dj, const std::string& lab) { return c->site_t(0, I + di, J + dj, lab); };
+      auto one = [&](const TRef& s, const std::string& which) {
+        std::vector<int64_t> dd;
+        for (char ch : which) dd.push_back(s.dim[s.lab.find(ch)]);
+        TRef o = ones.t;
+        o.dim = dd;
+        o.str = dd.size() == 2 ? std::vector<int64_t>{mx, 1} : std::vector<int64_t>{1};
+        o.lab = which;
+        return o;
+      };
+      auto put = [&](int k, const TRef& src, const std::string& out_lab, const std::string& sum) {
+        TRef dst = c->slot(0, I, J, k, out_lab);
+        // the chi legs of the slot keep only the first (actual) indices
+        TRef sub = dst;
+        for (size_t q = 0; q < out_lab.size(); ++q) sub.dim[q] = src.dim[src.lab.find(out_lab[q])];
+        contract(dev, c->st == T_F64 ? ctmk::MODE_F64 : ctmk::MODE_F32, sub, src, one(src, sum));
+      };
+      put(0, nb(-1, -1, "lurd"), "dr", "lu");
+      put(1, nb(-1, 1, "lurd"), "ld", "ur");
+      put(2, nb(1, 1, "lurd"), "ul", "rd");
+      put(3, nb(1, -1, "lurd"), "ru", "ld");
+      put(4, nb(-1, 0, "lurd"), "ldr", "u");
+      put(5, nb(0, 1, "lurd"), "uld", "r");
+      put(6, nb(1, 0, "lurd"), "rul", "d");
+      put(7, nb(0, -1, "lurd"), "dru", "l");
+    }
+  c->have_prev = false;
+}
+
+// ---------------------------------------------------------------------------
+// Projectors of the cut between rows I and I+1 at column step J of frame f
+// (Fig. CTMRG c, Eqs. PQ and QRSVD).  P and Q are written as float64
+// [(chi-leg, site-leg), chi] matrices; the site leg is the down leg of (I, J).
+void projectors(ctm_ctx* c, int f, int I, int J, double* P, double* Q) {
+  Dev& dev = c->dev;
+  const int64_t chi = c->chi;
+  const int m = c->mode;
+  // upper-left quadrant: C1 T1 T4 s at (I, J)  ->  UL[c, r, e, z]
+  TRef sUL = c->site_t(f, I, J, "yxrz");
+  Tmp X1(&dev, c->st, {chi, sUL.dim[1], chi}, "axc");
+  contract(dev, m, X1.t, c->slot(f, I, J, 0, "ab"), c->slot(f, I, J, 4, "bxc"));
+  Tmp X2(&dev, c->st, {chi, sUL.dim[0], sUL.dim[1], chi}, "eyxc");
+  contract(dev, m, X2.t, c->slot(f, I, J, 7, "eya"), X1.t);
+  Tmp UL(&dev, c->st, {chi, sUL.dim[2], chi, sUL.dim[3]}, "crez");
+  contract(dev, m, UL.t, X2.t, sUL);
+  // upper-right quadrant: T1 C2 T2 s at (I, J+1)  ->  UR[c, h, l, w]
+  TRef sUR = c->site_t(f, I, J + 1, "lxyw");
+  Tmp Y1(&dev, c->st, {chi, sUR.dim[1], chi}, "cxg");
+  contract(dev, m, Y1.t, c->slot(f, I, J + 1, 4, "cxf"), c->slot(f, I, J + 1, 1, "fg"));
+  Tmp Y2(&dev, c->st, {chi, sUR.dim[1], sUR.dim[2], chi}, "cxyh");
+  contract(dev, m, Y2.t, Y1.t, c->slot(f, I, J + 1, 5, "gyh"));
+  Tmp UR(&dev, c->st, {chi, chi, sUR.dim[0], sUR.dim[3]}, "chlw");
+  contract(dev, m, UR.t, Y2.t, sUR);
+  // lower-left quadrant: T4 C4 T3 s at (I+1, J)  ->  DL[c, e, x, r]
+  TRef sDL = c->site_t(f, I + 1, J, "yxrw");
+  Tmp Z1(&dev, c->st, {chi, sDL.dim[0], chi}, "bye");
+  contract(dev, m, Z1.t, c->slot(f, I + 1, J, 3, "ba"), c->slot(f, I + 1, J, 7, "aye"));
+  Tmp Z2(&dev, c->st, {chi, sDL.dim[3], sDL.dim[0], chi}, "cwye");
+  contract(dev, m, Z2.t, c->slot(f, I + 1, J, 6, "cwb"), Z1.t);
+  Tmp DL(&dev, c->st, {chi, chi, sDL.dim[1], sDL.dim[2]}, "cexr");
+  contract(dev, m, DL.t, Z2.t, sDL);
+  // lower-right quadrant: T2 C3 T3 s at (I+1, J+1)  ->  DR[h, c, l, v]
+  TRef sDR = c->site_t(f, I + 1, J + 1, "lvyw");
+  Tmp W1(&dev, c->st, {chi, sDR.dim[2], chi}, "hyf");
+  contract(dev, m, W1.t, c->slot(f, I + 1, J + 1, 5, "hyg"), c->slot(f, I + 1, J + 1, 2, "gf"));
+  Tmp W2(&dev, c->st, {chi, sDR.dim[2], sDR.dim[3], chi}, "hywc");
+  contract(dev, m, W2.t, W1.t, c->slot(f, I + 1, J + 1, 6, "fwc"));
+  Tmp DR(&dev, c->st, {chi, chi, sDR.dim[0], sDR.dim[1]}, "hclv");
+  contract(dev, m, DR.t, W2.t, sDR);
+
+  // half systems N[(h w), (e z)] and S[(h v), (e x)] (Eq. QRSVD), in float64
+  const int64_t zdim = sUL.dim[3], wdim = sUR.dim[3], vdim = sDR.dim[1], xdim = sDL.dim[1];
+  if (zdim != xdim || wdim != vdim) throw Error(CTM_EINVAL, "inconsistent nested bond dimensions");
+  const int64_t kd = chi * zdim, mn = chi * wdim;
+  DBuf Nb(&dev, (size_t)mn * kd * 8), Sb(&dev, (size_t)mn * kd * 8);
+  {
+    TRef Nv = view(Nb.p, T_F64, {chi, wdim, chi, zdim}, "hwez");
+    TRef Sv = view(Sb.p, T_F64, {chi, vdim, chi, xdim}, "hvex");
+    if (c->st == T_F64) {
+      contract(dev, m, Nv, UR.t, relabel(UL.t, "clez"));
+      contract(dev, m, Sv, DR.t, relabel(DL.t, "cexl"));
+    } else {
+      Tmp N32(&dev, c->st, {chi, wdim, chi, zdim}, "hwez");
+      contract(dev, m, N32.t, UR.t, relabel(UL.t, "clez"));
+      copy_into(dev, Nv, N32.t);
+      Tmp S32(&dev, c->st, {chi, vdim, chi, xdim}, "hvex");
+      contract(dev, m, S32.t, DR.t, relabel(DL.t, "cexl"));
+      copy_into(dev, Sv, S32.t);
+    }
+  }
+  // N (row-major mn x kd) is the column-major kd x mn matrix N^T; its LQ
+  // factorisation N^T = L Q gives R_n = L^T (and likewise for S).
+  const int64_t r = std::min(kd, mn);
+  DBuf tau(&dev, (size_t)r * 8 * 2), Ln(&dev, (size_t)kd * r * 8), Ls(&dev, (size_t)kd * r * 8);
+  RB_CHECK(rocsolver_dgelqf(c->blas, (rocblas_int)kd, (rocblas_int)mn, (double*)Nb.p, (rocblas_int)kd, (double*)tau.p));
+  RB_CHECK(rocsolver_dgelqf(c->blas, (rocblas_int)kd, (rocblas_int)mn, (double*)Sb.p, (rocblas_int)kd,
+                            (double*)tau.p + r));
+  HIP_CHECK(ctmk::launch_extract_lower((const double*)Nb.p, kd, kd, 0, (double*)Ln.p, r, 0, 1, dev.stream));
+  HIP_CHECK(ctmk::launch_extract_lower((const double*)Sb.p, kd, kd, 0, (double*)Ls.p, r, 0, 1, dev.stream));
+  // M = R_n R_s^T = L_n^T L_s  (column-major r x r)
+  DBuf Mb(&dev, (size_t)r * r * 8), U(&dev, (size_t)r * r * 8), Vt(&dev, (size_t)r * r * 8), Sv(&dev, (size_t)r * 8),
+      E(&dev, (size_t)r * 8), w(&dev, (size_t)chi * 8);
+  TRef Lnv{Ln.p, T_F64, {kd, r}, {1, kd}, "ai"};
+  TRef Lsv{Ls.p, T_F64, {kd, r}, {1, kd}, "aj"};
+  contract(dev, m, TRef{Mb.p, T_F64, {r, r}, {1, r}, "ij"}, Lnv, Lsv);
+  int* info = (int*)c->flag.p + 2;
+  RB_CHECK(rocsolver_dgesvd(c->blas, rocblas_svect_singular, rocblas_svect_singular, (rocblas_int)r, (rocblas_int)r,
+                            (double*)Mb.p, (rocblas_int)r, (double*)Sv.p, (double*)U.p, (rocblas_int)r, (double*)Vt.p,
+                            (rocblas_int)r, (double*)E.p, rocblas_outofplace, info));
+  HIP_CHECK(ctmk::launch_flag_or(info, (int*)c->flag.p + 1, dev.stream));
+  HIP_CHECK(ctmk::launch_svd_weights((const double*)Sv.p, r, r, (double*)w.p, chi, c->cutoff, 1, dev.stream));
+  // P = R_s^T V w = L_s V w,  Q = R_n^T U w = L_n U w  (row-major kd x chi)
+  TRef Vv{Vt.p, T_F64, {r, chi}, {r, 1}, "ik"};
+  TRef Uv{U.p, T_F64, {r, chi}, {1, r}, "ik"};
+  contract(dev, m, view(P, T_F64, {kd, chi}, "ak"), relabel(Lsv, "ai"), Vv, 1.0, 0, (const double*)w.p);
+  contract(dev, m, view(Q, T_F64, {kd, chi}, "ak"), Lnv, Uv, 1.0, 0, (const double*)w.p);
+}
+
+// One left move in frame f (Fig. CTMRG b): for every column step J, the
+// projectors of all rows, then C1, T4, C4 of column J+1 for all rows.
+void left_move(ctm_ctx* c, int f) {
+  Dev& dev = c->dev;
+  const int a = c->ny(f), b = c->nx(f);
+  const int64_t chi = c->chi, maxkd = chi * c->D * c->d;
+  const int m = c->mode;
+  DBuf P64(&dev, (size_t)a * maxkd * chi * 8), Q64(&dev, (size_t)a * maxkd * chi * 8);
+  DBuf Pst, Qst;
+  if (c->st != T_F64) {
+    Pst = DBuf(&dev, (size_t)a * maxkd * chi * 4);
+    Qst = DBuf(&dev, (size_t)a * maxkd * chi * 4);
+  }
+  for (int J = 0; J < b; ++J) {
+    std::vector<int64_t> zd(a);
+    for (int I = 0; I < a; ++I) {
+      zd[I] = c->site(f, I, J).dim[3];
+      double* P = (double*)P64.p + (size_t)I * maxkd * chi;
+      double* Q = (double*)Q64.p + (size_t)I * maxkd * chi;
+      projectors(c, f, I, J, P, Q);
+      if (c->st != T_F64) {
+        int64_t n = chi * zd[I] * chi;
+        copy_into(dev, view((float*)Pst.p + (size_t)I * maxkd * chi, T_F32, {n}, "q"), view(P, T_F64, {n}, "q"));
+        copy_into(dev, view((float*)Qst.p + (size_t)I * maxkd * chi, T_F32, {n}, "q"), view(Q, T_F64, {n}, "q"));
+      }
+    }
+    auto PQ = [&](DBuf& B64, DBuf& Bst, int I, const std::string& lab) {
+      int Ii = ((I % a) + a) % a;
+      void* base = c->st == T_F64 ? (void*)((double*)B64.p + (size_t)Ii * maxkd * chi)
+                                  : (void*)((float*)Bst.p + (size_t)Ii * maxkd * chi);
+      return view(base, c->st, {chi, zd[Ii], chi}, lab);
+    };
+    ctmk::NormList L;
+    std::memset(&L, 0, sizeof(L));
+    int cnt = 0;
+    for (int I = 0; I < a; ++I) {
+      TRef s = c->site_t(f, I, J, "yxrz");
+      // C1' = [C1 T1] P_{I-1}
+      Tmp X1(&dev, c->st, {chi, s.dim[1], chi}, "axc");
+      contract(dev, m, X1.t, c->slot(f, I, J, 0, "ab"), c->slot(f, I, J, 4, "bxc"));
+      TRef C1n = c->slot(f, I, J + 1, 0, "kc");
+      contract(dev, m, C1n, PQ(P64, Pst, I - 1, "axk"), X1.t);
+      // T4' = Q_{I-1}^T [T4 s] P_I
+      Tmp G1(&dev, c->st, {chi, chi, s.dim[1], s.dim[2], s.dim[3]}, "eaxrz");
+      contract(dev, m, G1.t, c->slot(f, I, J, 7, "eya"), s);
+      Tmp G2(&dev, c->st, {chi, chi, s.dim[2], s.dim[3]}, "emrz");
+      contract(dev, m, G2.t, PQ(Q64, Qst, I - 1, "axm"), G1.t);
+      TRef T4n = c->slot(f, I, J + 1, 7, "krm");
+      contract(dev, m, T4n, PQ(P64, Pst, I, "ezk"), G2.t);
+      // C4' = [C4 T3] Q_I
+      Tmp V1(&dev, c->st, {chi, s.dim[3], chi}, "cwa");
+      contract(dev, m, V1.t, c->slot(f, I, J, 6, "cwb"), c->slot(f, I, J, 3, "ba"));
+      TRef C4n = c->slot(f, I, J + 1, 3, "ck");
+      contract(dev, m, C4n, V1.t, PQ(Q64, Qst, I, "awk"));
+      for (const TRef* t : {&C1n, &T4n, &C4n}) {
+        if (cnt == ctmk::NORM_MAX) {
+          HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, dev.stream));
+          cnt = 0;
+        }
+        L.ptr[cnt] = t->p;
+        L.n[cnt] = t->numel();
+        ++cnt;
+      }
+    }
+    HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, dev.stream));
+  }
+}
+
+const int MOVE_FRAMES[4] = {0, 2, 1, 3};   // left, right, up, down
+
+// Normalised corner spectra of the environment and their L1 change.
+double spectra_delta(ctm_ctx* c) {
+  Dev& dev = c->dev;
+  const int64_t chi = c->chi;
+  const int count = c->NY * c->NX * 4;
+  DBuf Cs(&dev, (size_t)count * chi * chi * 8), sv(&dev, (size_t)count * chi * 8), E(&dev, (size_t)count * chi * 8);
+  DBuf infos(&dev, (size_t)count * sizeof(int));
+  for (int p = 0; p < c->NY * c->NX; ++p)
+    for (int k = 0; k < 4; ++k) {
+      TRef src = view((char*)c->env.p + c->slot_off[(size_t)p * 8 + k] * type_size(c->st), c->st, {chi, chi}, "ab");
+      copy_into(dev, view((double*)Cs.p + (size_t)(p * 4 + k) * chi * chi, T_F64, {chi, chi}, "ab"), src);
+    }
+  RB_CHECK(rocsolver_dgesvd_strided_batched(c->blas, rocblas_svect_none, rocblas_svect_none, (rocblas_int)chi,
+                                            (rocblas_int)chi, (double*)Cs.p, (rocblas_int)chi, chi * chi,
+                                            (double*)sv.p, chi, nullptr, 1, 0, nullptr, 1, 0, (double*)E.p, chi,
+                                            rocblas_outofplace, (int*)infos.p, count));
+  if (!c->spec_cur.p) {
+    c->spec_cur = DBuf(&dev, (size_t)count * chi * 8);
+    c->spec_prev = DBuf(&dev, (size_t)count * chi * 8);
+  }
+  HIP_CHECK(ctmk::launch_spectra_delta((const double*)sv.p, chi, chi, (double*)c->spec_cur.p,
+                                       c->have_prev ? (const double*)c->spec_prev.p : nullptr, count,
+                                       (double*)c->dscal.p, dev.stream));
+  double delta = 0;
+  HIP_CHECK(hipMemcpyAsync(&delta, c->dscal.p, 8, hipMemcpyDeviceToHost, dev.stream));
+  HIP_CHECK(hipStreamSynchronize(dev.stream));
+  std::swap(c->spec_cur, c->spec_prev);
+  bool first = !c->have_prev;
+  c->have_prev = true;
+  return first ? 1e300 : delta;
+}
+
+void check_flags(ctm_ctx* c) {
+  int h[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(h, c->flag.p, sizeof(h), hipMemcpyDeviceToHost, c->dev.stream));
+  HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+  HIP_CHECK(hipMemsetAsync(c->flag.p, 0, 2 * sizeof(int), c->dev.stream));
+  if (h[0]) throw Error(CTM_ENONFINITE, "non-finite value in the environment");
+  if (h[1]) throw Error(CTM_ESOLVER, "SVD did not converge (rocsolver info " + std::to_string(h[1]) + ")");
+}
+
+// ---------------------------------------------------------------------------
+// 2x2 reduced density matrix of the plaquette with top-left PEPS site (px, py)
+// (impurity tensors of Sec. II B).  The nested block is rows 2py..2py+3 and
+// columns 2px..2px+3 with its border environment.  The four Y tensors are
+// cut: the ket end of the physical line stays with the fused leg coming from
+// K, the bra end is exposed on the B below.  X and cut Y tensors are pure
+// relabellings of legs.  The left half (boundary column and nested columns 0,
+// 1) and the right half (boundary column and columns 3, 2) are grown column
+// by column and joined.  Result: rho[(k_TL k_TR k_BL k_BR), (b_TL b_TR b_BL b_BR)].
+void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
+  Dev& dev = c->dev;
+  const int m = c->mode;
+  const int64_t D = c->D, d = c->d;
+  const int r0 = 2 * py, c0 = 2 * px;
+  Labels Lb;
+  auto H = [&](int r, int cc) { return Lb("H" + std::to_string(r) + "," + std::to_string(cc)); };     // bond right of (r,cc)
+  auto Hd = [&](int r, int cc) { return Lb("Hd" + std::to_string(r) + "," + std::to_string(cc)); };   // D part of a fused bond
+  auto V = [&](int r, int cc) { return Lb("V" + std::to_string(r) + "," + std::to_string(cc)); };     // bond below (r,cc)
+  auto chL = [&](int i) { return Lb("cL" + std::to_string(i)); };
+  auto chR = [&](int i) { return Lb("cR" + std::to_string(i)); };
+  auto chT = [&](int i) { return Lb("cT" + std::to_string(i)); };
+  auto chB = [&](int i) { return Lb("cB" + std::to_string(i)); };
+  const char* names[4] = {"TL", "TR", "BL", "BR"};
+  auto kO = [&](int s) { return Lb(std::string("k") + names[s]); };
+  auto bO = [&](int s) { return Lb(std::string("b") + names[s]); };
+  auto site_of = [&](int r, int cc) { return (r / 2) * 2 + (cc / 2); };   // 0 TL, 1 TR, 2 BL, 3 BR
+  auto str = [](std::initializer_list<char> l) { return std::string(l); };
+
+  auto env = [&](int r, int cc, int k, const std::string& lab) { return c->slot(0, r0 + r, c0 + cc, k, lab); };
+  auto site = [&](int r, int cc, const std::string& lab) { return c->site_t(0, r0 + r, c0 + cc, lab); };
+
+  struct State { Tmp t; };
+  auto absorb = [&](Tmp& S, const TRef& X) {
+    std::string out;
+    for (char ch : S.t.lab) if (X.lab.find(ch) == std::string::npos) out += ch;
+    std::vector<int64_t> dims;
+    for (char ch : out) dims.push_back(S.t.dim[S.t.lab.find(ch)]);
+    for (size_t q = 0; q < X.lab.size(); ++q)
+      if (S.t.lab.find(X.lab[q]) == std::string::npos) { out += X.lab[q]; dims.push_back(X.dim[q]); }
+    Tmp R(&dev, c->st, dims, out);
+    contract(dev, m, R.t, S.t, X);
+    S = std::move(R);
+  };
+  auto rename = [&](Tmp& S, char from, char to) {
+    size_t i = S.t.lab.find(from);
+    if (i == std::string::npos) throw Error(CTM_EINVAL, "rdm: missing label");
+    S.t.lab[i] = to;
+  };
+
+  // ---- left half
+  Tmp Ls(&dev, c->st, {(int64_t)c->chi, (int64_t)c->chi}, str({chL(0), chT(0)}));
+  copy_into(dev, Ls.t, env(0, 0, 0, str({chL(0), chT(0)})));
+  for (int r = 0; r < 4; ++r) absorb(Ls, env(r, 0, 7, str({chL(r + 1), H(r, -1), chL(r)})));
+  absorb(Ls, env(3, 0, 3, str({chB(0), chL(4)})));
+  for (int cc = 0; cc < 2; ++cc) {
+    absorb(Ls, env(0, cc, 4, str({chT(cc), V(-1, cc), chT(cc + 1)})));
+    for (int r = 0; r < 4; ++r) {
+      int k = c->kind(r0 + r, c0 + cc);
+      if (k == 0) {                                       // K: dense
+        absorb(Ls, site(r, cc, str({H(r, cc - 1), V(r - 1, cc), H(r, cc), V(r, cc)})));
+      } else if (k == 2) {                                // X: relabel
+        rename(Ls, H(r, cc - 1), H(r, cc));
+        rename(Ls, V(r - 1, cc), V(r, cc));
+      } else if (k == 1) {                                // cut Y: split the fused leg from K
+        Ls.t = split_axis(Ls.t, H(r, cc - 1), D, d, H(r, cc), kO(site_of(r, cc)));
+        rename(Ls, V(r - 1, cc), V(r, cc));
+      } else {                                            // B: bra end of the line exposed
+        TRef Bt = site(r, cc, "lurd");
+        Bt = split_axis(Bt, 'u', D, d, 'U', 'S');
+        Bt = relabel(Bt, str({H(r, cc - 1), V(r - 1, cc), bO(site_of(r - 1, cc)), H(r, cc), V(r, cc)}));
+        absorb(Ls, Bt);
+      }
+    }
+    absorb(Ls, env(3, cc, 6, str({chB(cc + 1), V(3, cc), chB(cc)})));
+  }
+  // ---- right half
+  Tmp Rs(&dev, c->st, {(int64_t)c->chi, (int64_t)c->chi}, str({chT(4), chR(0)}));
+  copy_into(dev, Rs.t, env(0, 3, 1, str({chT(4), chR(0)})));
+  for (int r = 0; r < 4; ++r) absorb(Rs, env(r, 3, 5, str({chR(r), H(r, 3), chR(r + 1)})));
+  absorb(Rs, env(3, 3, 2, str({chR(4), chB(4)})));
+  for (int cc = 3; cc >= 2; --cc) {
+    absorb(Rs, env(0, cc, 4, str({chT(cc), V(-1, cc), chT(cc + 1)})));
+    for (int r = 0; r < 4; ++r) {
+      int k = c->kind(r0 + r, c0 + cc);
+      if (k == 0) {                                       // K: fused right leg split, physical index open
+        TRef Kt = site(r, cc, "lurd");
+        Kt = split_axis(Kt, 'r', D, d, 'R', 'S');
+        Kt = relabel(Kt, str({H(r, cc - 1), V(r - 1, cc), Hd(r, cc), kO(site_of(r, cc)), V(r, cc)}));
+        absorb(Rs, Kt);
+      } else if (k == 2) {                                // X
+        rename(Rs, H(r, cc), H(r, cc - 1));
+        rename(Rs, V(r - 1, cc), V(r, cc));
+      } else if (k == 1) {                                // cut Y: hand the ket line to the K on the left
+        rename(Rs, H(r, cc), Hd(r, cc - 1));
+        rename(Rs, V(r - 1, cc), V(r, cc));
+      } else {                                            // B
+        TRef Bt = site(r, cc, "lurd");
+        Bt = split_axis(Bt, 'u', D, d, 'U', 'S');
+        Bt = relabel(Bt, str({H(r, cc - 1), V(r - 1, cc), bO(site_of(r - 1, cc)), H(r, cc), V(r, cc)}));
+        absorb(Rs, Bt);
+      }
+    }
+    absorb(Rs, env(3, cc, 6, str({chB(cc + 1), V(3, cc), chB(cc)})));
+  }
+  // ---- join
+  std::string ol = str({kO(0), kO(1), kO(2), kO(3), bO(0), bO(1), bO(2), bO(3)});
+  std::vector<int64_t> od(8, d);
+  if (c->st == T_F64) {
+    contract(dev, m, view(rho_out, T_F64, od, ol), Ls.t, Rs.t);
+  } else {
+    Tmp r32(&dev, c->st, od, ol);
+    contract(dev, m, r32.t, Ls.t, Rs.t);
+    copy_into(dev, view(rho_out, T_F64, od, ol), r32.t);
+  }
+}
+
+int fail(ctm_ctx* c, const Error& e) {
+  if (c) c->err = e.what();
+  else g_init_error = e.what();
+  return e.code;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
+             int n_tensors, int precision, void* stream) {
+  if (!out) { g_init_error = "out is NULL"; return CTM_EINVAL; }
+  *out = nullptr;
+  ctm_ctx* c = nullptr;
+  try {
+    if (!A || !pattern || d < 1 || D < 1 || Lx < 1 || Ly < 1 || n_tensors < 1)
+      throw Error(CTM_EINVAL, "invalid dimensions or NULL pointer");
+    if ((int64_t)chi < (int64_t)D * d) throw Error(CTM_EINVAL, "chi must be at least D*d");
+    if (precision < CTM_FP64 || precision > CTM_BF16) throw Error(CTM_EINVAL, "unknown precision");
+    for (int i = 0; i < Lx * Ly; ++i)
+      if (pattern[i] < 0 || pattern[i] >= n_tensors) throw Error(CTM_EINVAL, "pattern id out of range");
+    c = new ctm_ctx();
+    c->dev.stream = (hipStream_t)stream;
+    c->d = d; c->D = D; c->chi = chi; c->Lx = Lx; c->Ly = Ly; c->nt = n_tensors; c->prec = precision;
+    c->NY = 2 * Ly; c->NX = 2 * Lx;
+    c->pattern.assign(pattern, pattern + Lx * Ly);
+    c->st = precision == CTM_FP64 ? T_F64 : T_F32;
+    c->mode = precision == CTM_BF16 ? ctmk::MODE_BF16 : (precision == CTM_FP32 ? ctmk::MODE_F32 : ctmk::MODE_F64);
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) throw Error(CTM_EHIP, "rocblas_create_handle failed");
+    RB_CHECK(rocblas_set_stream(c->blas, c->dev.stream));
+    c->flag = DBuf(&c->dev, 64);
+    c->dscal = DBuf(&c->dev, 64);
+    HIP_CHECK(hipMemsetAsync(c->flag.p, 0, 64, c->dev.stream));
+    int64_t nA = (int64_t)n_tensors * d * D * D * D * D;
+    c->A64 = DBuf(&c->dev, (size_t)nA * 8);
+    HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
+    build_layout(c);
+    c->env = DBuf(&c->dev, (size_t)c->env_elems * type_size(c->st));
+    build_sites(c);
+    init_env(c);
+    HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+    *out = c;
+    return CTM_OK;
+  } catch (const Error& e) {
+    g_init_error = e.what();
+    if (c) ctm_free(c);
+    return e.code;
+  } catch (const std::exception& e) {
+    g_init_error = e.what();
+    if (c) ctm_free(c);
+    return CTM_EHIP;
+  }
+}
+
+int ctm_set_tensors(ctm_ctx* c, const double* A) {
+  if (!c || !A) return CTM_EINVAL;
+  try {
+    int64_t nA = (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D;
+    HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
+    build_sites(c);
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_reset_env(ctm_ctx* c) {
+  if (!c) return CTM_EINVAL;
+  try { init_env(c); return CTM_OK; } catch (const Error& e) { return fail(c, e); }
+}
+
+int64_t ctm_env_size(const ctm_ctx* c) { return c ? c->env_elems : 0; }
+
+int ctm_set_env(ctm_ctx* c, const double* env) {
+  if (!c || !env) return CTM_EINVAL;
+  try {
+    copy_into(c->dev, view(c->env.p, c->st, {c->env_elems}, "e"), view((void*)env, T_F64, {c->env_elems}, "e"));
+    c->have_prev = false;
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_get_env(ctm_ctx* c, double* env) {
+  if (!c || !env) return CTM_EINVAL;
+  try {
+    copy_into(c->dev, view(env, T_F64, {c->env_elems}, "e"), view(c->env.p, c->st, {c->env_elems}, "e"));
+    HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, double* delta) {
+  if (!c || max_sweeps < 0) return CTM_EINVAL;
+  try {
+    double dl = -1.0;
+    int n = 0;
+    for (n = 1; n <= max_sweeps; ++n) {
+      for (int f : MOVE_FRAMES) left_move(c, f);
+      if (c->check_finite)
+        HIP_CHECK(ctmk::launch_nonfinite(c->st, c->env.p, c->env_elems, (int*)c->flag.p, c->dev.stream));
+      if (tol > 0) {
+        dl = spectra_delta(c);
+        check_flags(c);
+        if (dl < tol) break;
+      }
+    }
+    if (n > max_sweeps) n = max_sweeps;
+    if (tol <= 0) check_flags(c);
+    if (sweeps_done) *sweeps_done = n;
+    if (delta) *delta = dl;
+    return (tol > 0 && !(dl < tol)) ? CTM_ENOTCONV : CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_energy(ctm_ctx* c, const double* H_bond, int n_terms, const ctm_term* terms, double* E) {
+  if (!c || !H_bond || (n_terms > 0 && !terms) || !E) return CTM_EINVAL;
+  try {
+    std::vector<std::pair<int, int>> plaq;
+    std::vector<ctmk::EnergyTerm> et(n_terms);
+    for (int i = 0; i < n_terms; ++i) {
+      const ctm_term& t = terms[i];
+      if (t.px < 0 || t.px >= c->Lx || t.py < 0 || t.py >= c->Ly || t.a < 0 || t.a > 3 || t.b < 0 || t.b > 3 || t.a == t.b)
+        throw Error(CTM_EINVAL, "invalid term");
+      int idx = -1;
+      for (size_t q = 0; q < plaq.size(); ++q)
+        if (plaq[q] == std::make_pair(t.px, t.py)) idx = (int)q;
+      if (idx < 0) { idx = (int)plaq.size(); plaq.push_back({t.px, t.py}); }
+      et[i].rho_index = idx; et[i].a = t.a; et[i].b = t.b; et[i].coef = t.coef;
+    }
+    const int64_t d4 = (int64_t)c->d * c->d * c->d * c->d, rsz = d4 * d4;
+    if (plaq.empty()) { *E = 0.0; return CTM_OK; }
+    c->rdm_buf = DBuf(&c->dev, (size_t)plaq.size() * rsz * 8);
+    c->n_rdm = (int)plaq.size();
+    for (size_t q = 0; q < plaq.size(); ++q)
+      plaquette_rdm(c, plaq[q].first, plaq[q].second, (double*)c->rdm_buf.p + q * rsz);
+    DBuf hb(&c->dev, (size_t)c->d * c->d * c->d * c->d * 8), tb(&c->dev, sizeof(ctmk::EnergyTerm) * n_terms);
+    HIP_CHECK(hipMemcpyAsync(hb.p, H_bond, (size_t)d4 * 8, hipMemcpyHostToDevice, c->dev.stream));
+    HIP_CHECK(hipMemcpyAsync(tb.p, et.data(), sizeof(ctmk::EnergyTerm) * n_terms, hipMemcpyHostToDevice, c->dev.stream));
+    HIP_CHECK(ctmk::launch_energy((const double*)c->rdm_buf.p, rsz, (const double*)hb.p,
+                                  (const ctmk::EnergyTerm*)tb.p, n_terms, c->d, 1.0 / (c->Lx * c->Ly),
+                                  (double*)c->dscal.p, nullptr, c->dev.stream));
+    HIP_CHECK(ctmk::launch_nonfinite(T_F64, c->dscal.p, 1, (int*)c->flag.p, c->dev.stream));
+    HIP_CHECK(hipMemcpyAsync(E, c->dscal.p, 8, hipMemcpyDeviceToHost, c->dev.stream));
+    check_flags(c);
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_last_rdms(ctm_ctx* c, double* rho, int capacity, int* n) {
+  if (!c || !rho || !n) return CTM_EINVAL;
+  try {
+    const int64_t d4 = (int64_t)c->d * c->d * c->d * c->d, rsz = d4 * d4;
+    int k = std::min(capacity, c->n_rdm);
+    if (k > 0) HIP_CHECK(hipMemcpyAsync(rho, c->rdm_buf.p, (size_t)k * rsz * 8, hipMemcpyDeviceToHost, c->dev.stream));
+    HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+    *n = c->n_rdm;
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_set_option(ctm_ctx* c, const char* key, double value) {
+  if (!c || !key) return CTM_EINVAL;
+  std::string k(key);
+  if (k == "svd_cutoff" && value >= 0) c->cutoff = value;
+  else if (k == "lorentz_eta" && value >= 0) c->eta = value;
+  else if (k == "check_finite") c->check_finite = value != 0;
+  else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }
+  return CTM_OK;
+}
+
+const char* ctm_last_error(const ctm_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void ctm_free(ctm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->dev.stream);
+  {
+    ctm_ctx* t = c;
+    t->A64.reset(); t->site_buf.reset(); t->env.reset(); t->spec_prev.reset(); t->spec_cur.reset();
+    t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset();
+  }
+  (void)hipStreamSynchronize(c->dev.stream);
+  if (c->blas) rocblas_destroy_handle(c->blas);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+// Contraction planner: labelled tensors -> batched MFMA contraction kernel.
+#include "engine.h"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+namespace ctm {
+
+Counters g_counters;
+
+TRef view(void* p, int type, const std::vector<int64_t>& dims, const std::string& lab) {
+  if (dims.size() != lab.size()) throw Error(-1, "view: labels do not match rank: " + lab);
+  TRef t;
+  t.p = p;
+  t.type = type;
+  t.dim = dims;
+  t.str.assign(dims.size(), 1);
+  for (int i = (int)dims.size() - 2; i >= 0; --i) t.str[i] = t.str[i + 1] * dims[i + 1];
+  t.lab = lab;
+  return t;
+}
+
+TRef relabel(const TRef& t, const std::string& lab) {
+  if (lab.size() != t.lab.size()) throw Error(-1, "relabel: rank mismatch " + t.lab + " -> " + lab);
+  TRef r = t;
+  r.lab = lab;
+  return r;
+}
+
+TRef split_axis(const TRef& t, char label, int64_t a, int64_t b, char lab_major, char lab_minor) {
+  size_t i = t.lab.find(label);
+  if (i == std::string::npos || t.dim[i] != a * b) throw Error(-1, std::string("split_axis: bad axis ") + label);
+  TRef r;
+  r.p = t.p;
+  r.type = t.type;
+  for (size_t j = 0; j < t.lab.size(); ++j) {
+    if (j == i) {
+      r.dim.push_back(a); r.str.push_back(t.str[j] * b); r.lab.push_back(lab_major);
+      r.dim.push_back(b); r.str.push_back(t.str[j]); r.lab.push_back(lab_minor);
+    } else {
+      r.dim.push_back(t.dim[j]); r.str.push_back(t.str[j]); r.lab.push_back(t.lab[j]);
+    }
+  }
+  return r;
+}
+
+void* Dev::alloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMallocAsync(&p, bytes, stream);
+  if (e != hipSuccess) throw Error(e == hipErrorOutOfMemory ? -2 : -3, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  return p;
+}
+
+void Dev::free(void* p) {
+  if (p) (void)hipFreeAsync(p, stream);
+}
+
+namespace {
+
+struct Level {
+  int64_t dim;
+  int64_t s[3];   // strides in A, B, C
+};
+
+struct Group {
+  std::vector<Level> lv;
+  bool in[3];     // which operands carry this group
+};
+
+// Merge neighbouring levels (outer, inner) that are contiguous in every operand of the group.
+void merge(Group& g) {
+  std::vector<Level> out;
+  for (const Level& l : g.lv) {
+    if (!out.empty()) {
+      Level& o = out.back();
+      bool ok = true;
+      for (int q = 0; q < 3; ++q)
+        if (g.in[q] && o.s[q] != l.s[q] * l.dim) ok = false;
+      if (ok) {
+        o.dim *= l.dim;
+        for (int q = 0; q < 3; ++q) o.s[q] = l.s[q];
+        continue;
+      }
+    }
+    out.push_back(l);
+  }
+  g.lv = out;
+}
+
+void fill_group(const Group& g, int64_t& total, int64_t& inner, int64_t* so, int64_t* si) {
+  total = 1;
+  for (auto& l : g.lv) total *= l.dim;
+  for (int q = 0; q < 3; ++q) so[q] = si[q] = 0;
+  if (g.lv.empty()) { inner = 1; return; }
+  const Level& li = g.lv.back();
+  inner = g.lv.size() == 1 ? total : li.dim;
+  for (int q = 0; q < 3; ++q) si[q] = li.s[q];
+  if (g.lv.size() == 2)
+    for (int q = 0; q < 3; ++q) so[q] = g.lv[0].s[q];
+}
+
+struct Plan {
+  Group b, m, n, k;
+  bool ok() const { return b.lv.size() <= 2 && m.lv.size() <= 2 && n.lv.size() <= 2 && k.lv.size() <= 2; }
+};
+
+Plan make_plan(const TRef& C, const TRef& A, const TRef& B) {
+  struct Info { int64_t dim = -1; int64_t s[3] = {0, 0, 0}; bool in[3] = {false, false, false}; };
+  std::map<char, Info> info;
+  const TRef* ops[3] = {&A, &B, &C};
+  for (int q = 0; q < 3; ++q) {
+    const TRef& t = *ops[q];
+    for (size_t i = 0; i < t.lab.size(); ++i) {
+      Info& f = info[t.lab[i]];
+      if (f.in[q]) throw Error(-1, std::string("contract: repeated label ") + t.lab[i]);
+      if (f.dim >= 0 && f.dim != t.dim[i])
+        throw Error(-1, std::string("contract: dimension mismatch for label ") + t.lab[i] + " in " + A.lab + "," +
+                            B.lab + "->" + C.lab);
+      f.dim = t.dim[i];
+      f.s[q] = t.str[i];
+      f.in[q] = true;
+    }
+  }
+  Plan P;
+  auto add = [&](Group& g, char c) {
+    const Info& f = info[c];
+    if (f.dim == 1) return;
+    Level l;
+    l.dim = f.dim;
+    for (int q = 0; q < 3; ++q) l.s[q] = f.s[q];
+    g.lv.push_back(l);
+  };
+  P.b.in[0] = P.b.in[1] = P.b.in[2] = true;
+  P.m.in[0] = true; P.m.in[1] = false; P.m.in[2] = true;
+  P.n.in[0] = false; P.n.in[1] = true; P.n.in[2] = true;
+  P.k.in[0] = true; P.k.in[1] = true; P.k.in[2] = false;
+  for (char c : C.lab) {
+    const Info& f = info[c];
+    if (f.in[0] && f.in[1]) add(P.b, c);
+    else if (f.in[0]) add(P.m, c);
+    else if (f.in[1]) add(P.n, c);
+    else if (f.dim != 1) throw Error(-1, std::string("contract: output label not in inputs: ") + c);
+  }
+  for (char c : A.lab) {
+    const Info& f = info[c];
+    if (f.in[1] && !f.in[2]) add(P.k, c);
+    else if (!f.in[1] && !f.in[2] && f.dim != 1)
+      throw Error(-1, std::string("contract: label only in the first operand: ") + c + " in " + A.lab + "," + B.lab +
+                          "->" + C.lab);
+  }
+  for (char c : B.lab) {
+    const Info& f = info[c];
+    if (!f.in[0] && !f.in[2] && f.dim != 1)
+      throw Error(-1, std::string("contract: label only in the second operand: ") + c);
+  }
+  merge(P.b);
+  merge(P.m);
+  merge(P.n);
+  merge(P.k);
+  return P;
+}
+
+void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A, const TRef& B, double alpha,
+                 int beta, const double* colscale) {
+  ctmk::GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A.p; g.B = B.p; g.C = C.p;
+  int64_t so[3], si[3];
+  fill_group(P.b, g.batch, g.b_in, so, si);
+  g.a_b_o = so[0]; g.a_b_i = si[0]; g.b_b_o = so[1]; g.b_b_i = si[1]; g.c_b_o = so[2]; g.c_b_i = si[2];
+  fill_group(P.m, g.M, g.m_in, so, si);
+  g.a_m_o = so[0]; g.a_m_i = si[0]; g.c_m_o = so[2]; g.c_m_i = si[2];
+  fill_group(P.n, g.N, g.n_in, so, si);
+  g.b_n_o = so[1]; g.b_n_i = si[1]; g.c_n_o = so[2]; g.c_n_i = si[2];
+  fill_group(P.k, g.K, g.k_in, so, si);
+  g.a_k_o = so[0]; g.a_k_i = si[0]; g.b_k_o = so[1]; g.b_k_i = si[1];
+  g.alpha = alpha;
+  g.beta = beta;
+  g.colscale = colscale;
+  if (g.batch > 65535) throw Error(-1, "contract: batch too large");
+  if (((g.M + 63) / 64) * ((g.N + 63) / 64) > 2147483647LL) throw Error(-1, "contract: too many tiles");
+  if (g.K == 0) {   // empty sum
+    if (!beta) fill(dev, C, 0.0);
+    return;
+  }
+  g_counters.launches++;
+  g_counters.flops += 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
+  HIP_CHECK(ctmk::launch_contract(A.type == T_F64 ? ctmk::MODE_F64 : mode, g, dev.stream));
+}
+
+}  // namespace
+
+void contract(Dev& dev, int mode, const TRef& C, const TRef& A, const TRef& B, double alpha, int beta,
+              const double* colscale) {
+  if (A.type != B.type || A.type != C.type) throw Error(-1, "contract: operand types differ");
+  Plan P = make_plan(C, A, B);
+  if (P.ok()) {
+    launch_plan(dev, mode, P, C, A, B, alpha, beta, colscale);
+    return;
+  }
+  // Fall back: transpose the inputs to [batch, m, k] / [batch, k, n] and, if C
+  // still needs more than two levels per group, go through a contiguous result.
+  std::string bl, ml, nl, kl;
+  for (char c : C.lab) {
+    bool ia = A.lab.find(c) != std::string::npos, ib = B.lab.find(c) != std::string::npos;
+    if (ia && ib) bl += c; else if (ia) ml += c; else if (ib) nl += c;
+  }
+  for (char c : A.lab)
+    if (B.lab.find(c) != std::string::npos && C.lab.find(c) == std::string::npos) kl += c;
+  Tmp a2 = permuted(dev, A, bl + ml + kl);
+  Tmp b2 = permuted(dev, B, bl + kl + nl);
+  P = make_plan(C, a2.t, b2.t);
+  if (P.ok()) {
+    launch_plan(dev, mode, P, C, a2.t, b2.t, alpha, beta, colscale);
+    return;
+  }
+  std::vector<int64_t> cd;
+  for (char c : bl + ml + nl) cd.push_back(C.dim[C.lab.find(c)]);
+  Tmp c2(&dev, C.type, cd, bl + ml + nl);
+  P = make_plan(c2.t, a2.t, b2.t);
+  if (!P.ok()) throw Error(-1, "contract: no plan for " + A.lab + "," + B.lab + "->" + C.lab);
+  launch_plan(dev, mode, P, c2.t, a2.t, b2.t, alpha, 0, colscale);
+  copy_into(dev, C, c2.t, beta != 0);
+}
+
+void copy_into(Dev& dev, const TRef& out, const TRef& in, bool accumulate) {
+  if (out.lab.size() != in.lab.size()) throw Error(-1, "copy_into: rank mismatch " + in.lab + " -> " + out.lab);
+  ctmk::PermArgs p;
+  std::memset(&p, 0, sizeof(p));
+  // iterate in the order of ``out``; drop size-1 axes
+  int nd = 0;
+  for (size_t i = 0; i < out.lab.size(); ++i) {
+    size_t j = in.lab.find(out.lab[i]);
+    if (j == std::string::npos) throw Error(-1, "copy_into: label missing " + in.lab + " -> " + out.lab);
+    if (in.dim[j] != out.dim[i]) throw Error(-1, "copy_into: dimension mismatch");
+    if (out.dim[i] == 1) continue;
+    if (nd >= ctmk::PERM_MAX_DIMS) throw Error(-1, "copy_into: too many axes");
+    p.dims[nd] = out.dim[i];
+    p.out_strides[nd] = out.str[i];
+    p.in_strides[nd] = in.str[j];
+    ++nd;
+  }
+  p.ndim = nd;
+  p.accumulate = accumulate ? 1 : 0;
+  HIP_CHECK(ctmk::launch_permute(p, in.type, in.p, out.type, out.p, dev.stream));
+}
+
+Tmp permuted(Dev& dev, const TRef& in, const std::string& lab, int type) {
+  std::vector<int64_t> d;
+  for (char c : lab) {
+    size_t j = in.lab.find(c);
+    if (j == std::string::npos) throw Error(-1, "permuted: label missing");
+    d.push_back(in.dim[j]);
+  }
+  Tmp t(&dev, type < 0 ? in.type : type, d, lab);
+  copy_into(dev, t.t, in);
+  return t;
+}
+
+void fill(Dev& dev, const TRef& t, double v) {
+  HIP_CHECK(ctmk::launch_fill(t.type, t.p, v, t.numel(), dev.stream));
+}
+
+}  // namespace ctm

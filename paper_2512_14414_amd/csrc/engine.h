@@ -1,0 +1,111 @@
+// Host-side contraction engine: labelled device tensors and a planner that
+// maps a two-operand contraction onto the batched MFMA contraction kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace ctm {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(expr)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      throw ::ctm::Error(e_ == hipErrorOutOfMemory ? -2 : -3,                                     \
+                         std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+enum { T_F64 = 0, T_F32 = 1 };
+inline size_t type_size(int t) { return t == T_F64 ? 8 : 4; }
+
+// A strided view of device memory with one character label per axis.
+struct TRef {
+  void* p = nullptr;
+  int type = T_F64;
+  std::vector<int64_t> dim, str;
+  std::string lab;
+  int64_t numel() const {
+    int64_t n = 1;
+    for (auto d : dim) n *= d;
+    return n;
+  }
+};
+
+TRef view(void* p, int type, const std::vector<int64_t>& dims, const std::string& lab);   // row-major
+TRef relabel(const TRef& t, const std::string& lab);
+// Split axis ``label`` (dimension a*b) into two axes (a major, b minor).
+TRef split_axis(const TRef& t, char label, int64_t a, int64_t b, char lab_major, char lab_minor);
+
+// Stream-ordered device memory.
+struct Dev {
+  hipStream_t stream = nullptr;
+  void* alloc(size_t bytes);
+  void free(void* p);
+};
+
+// Owning device buffer released on the stream.
+struct DBuf {
+  Dev* dev = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(Dev* d, size_t b) : dev(d), p(d->alloc(b)), bytes(b) {}
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : dev(o.dev), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    reset();
+    dev = o.dev; p = o.p; bytes = o.bytes; o.p = nullptr;
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p && dev) dev->free(p);
+    p = nullptr;
+  }
+};
+
+// Temporary tensor with a contiguous row-major layout.
+struct Tmp {
+  DBuf buf;
+  TRef t;
+  Tmp() = default;
+  Tmp(Dev* d, int type, const std::vector<int64_t>& dims, const std::string& lab) {
+    int64_t n = 1;
+    for (auto x : dims) n *= x;
+    buf = DBuf(d, (size_t)std::max<int64_t>(n, 1) * type_size(type));
+    t = view(buf.p, type, dims, lab);
+  }
+};
+
+// C = alpha * contraction(A, B) (+ C if beta); labels shared by A and B and
+// absent from C are summed, labels in all three are batched.  ``mode`` picks
+// the matrix-core path for float tensors (ctmk::MODE_F32 or MODE_BF16).
+void contract(Dev& dev, int mode, const TRef& C, const TRef& A, const TRef& B, double alpha = 1.0, int beta = 0,
+              const double* colscale = nullptr);
+
+// out (any strides) = in (any strides) for axes matched by label; converts type.
+void copy_into(Dev& dev, const TRef& out, const TRef& in, bool accumulate = false);
+
+// New contiguous tensor holding ``in`` with its axes in the order ``lab``.
+Tmp permuted(Dev& dev, const TRef& in, const std::string& lab, int type = -1);
+
+void fill(Dev& dev, const TRef& t, double v);   // t must be contiguous
+
+// Count of contraction-kernel launches and their nominal flops, for profiling.
+struct Counters {
+  int64_t launches = 0;
+  double flops = 0;
+};
+extern Counters g_counters;
+
+}  // namespace ctm

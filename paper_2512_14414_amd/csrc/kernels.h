@@ -1,0 +1,67 @@
+// Launch interface of the device kernels (kernels.hip).  Host code of the
+// library only; not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ctmk {
+
+enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
+
+// Batched contraction C[b][m][n] = alpha * sum_k A[b][m][k] * B[b][k][n] (+ C if beta).
+// Every index i of a group of total size X with inner size X_in sits at
+// (i / X_in) * stride_outer + (i % X_in) * stride_inner in each operand.
+// Element types: double (F64 mode) or float (F32 and BF16 modes).
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  void* C;
+  int64_t M, N, K, batch;
+  int64_t m_in, n_in, k_in, b_in;
+  int64_t a_m_o, a_m_i, a_k_o, a_k_i, a_b_o, a_b_i;
+  int64_t b_k_o, b_k_i, b_n_o, b_n_i, b_b_o, b_b_i;
+  int64_t c_m_o, c_m_i, c_n_o, c_n_i, c_b_o, c_b_i;
+  double alpha;
+  int beta;                 // 0: overwrite C, 1: accumulate into C
+  const double* colscale;   // optional factor per n (device, length N)
+};
+
+constexpr int PERM_MAX_DIMS = 10;
+struct PermArgs {
+  int ndim;
+  int accumulate;
+  int64_t dims[PERM_MAX_DIMS];
+  int64_t in_strides[PERM_MAX_DIMS];
+  int64_t out_strides[PERM_MAX_DIMS];
+};
+
+constexpr int NORM_MAX = 64;
+struct NormList {
+  void* ptr[NORM_MAX];
+  int64_t n[NORM_MAX];
+  double* norm_out;         // optional, one value per tensor
+};
+
+struct EnergyTerm {
+  int rho_index;            // which plaquette density matrix
+  int a, b;                 // sites 0..3 of the plaquette
+  double coef;
+};
+
+hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s);
+hipError_t launch_permute(const PermArgs& p, int in_type, const void* in, int out_type, void* out, hipStream_t s);
+hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_normalize(int type, const NormList& L, int count, hipStream_t s);
+hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, double* w, int64_t chi, double cutoff,
+                              int batch, hipStream_t st);
+hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,
+                                int64_t stride_l, int batch, hipStream_t s);
+hipError_t launch_energy(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms, int n_terms,
+                         int d, double inv_sites, double* E_out, double* bond_out, hipStream_t s);
+hipError_t launch_nonfinite(int type, const void* x, int64_t n, int* flag, hipStream_t s);
+hipError_t launch_spectra_delta(const double* sv, int64_t r, int64_t chi, double* cur, const double* prev, int count,
+                                double* delta_out, hipStream_t s);
+
+hipError_t launch_flag_or(const int* src, int* flag, hipStream_t s);
+
+}  // namespace ctmk

@@ -1,0 +1,435 @@
+// Device kernels of the nested-CTMRG library (gfx950 / CDNA4).
+//
+// The central kernel is a tensor contraction written as a batched matrix
+// product C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] (+ C) in which each
+// of the four index groups b, m, n, k may be split into an outer and an inner
+// part with independent strides in every operand.  That covers the corner,
+// half-system, projection and density-matrix contractions of the CTMRG sweep
+// without transposing operands in memory.  The product runs on the matrix
+// cores: v_mfma_f64_16x16x4f64 (FP64 mode), v_mfma_f32_16x16x4f32 (FP32 mode)
+// or v_mfma_f32_16x16x16bf16_1k (BF16 mode: FP32 data rounded to bfloat16 while
+// staged in LDS, FP32 accumulation).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace ctmk {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int64_t split_off(int64_t i, int64_t inner, int64_t so, int64_t si) {
+  int64_t o = i / inner;
+  return o * so + (i - o * inner) * si;
+}
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+constexpr int BM = 64, BN = 64, NT = 256;
+
+template <int MODE> struct Cfg;
+template <> struct Cfg<MODE_F64> { typedef double T; typedef double L; static constexpr int BK = 16; };
+template <> struct Cfg<MODE_F32> { typedef float T; typedef float L; static constexpr int BK = 16; };
+template <> struct Cfg<MODE_BF16> { typedef float T; typedef unsigned short L; static constexpr int BK = 32; };
+
+template <int MODE> __device__ __forceinline__ typename Cfg<MODE>::L to_lds(typename Cfg<MODE>::T v);
+template <> __device__ __forceinline__ double to_lds<MODE_F64>(double v) { return v; }
+template <> __device__ __forceinline__ float to_lds<MODE_F32>(float v) { return v; }
+template <> __device__ __forceinline__ unsigned short to_lds<MODE_BF16>(float v) { return f32_to_bf16_rne(v); }
+
+// One workgroup computes a 64 x 64 tile of C for one batch entry; the four
+// waves each own a 32 x 32 quarter made of 2 x 2 blocks of 16 x 16 MFMA tiles.
+template <int MODE, bool AK, bool BN_FAST>
+__global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
+  typedef typename Cfg<MODE>::T T;
+  typedef typename Cfg<MODE>::L L;
+  constexpr int BK = Cfg<MODE>::BK;
+  __shared__ L As[BK][BM + 4];
+  __shared__ L Bs[BK][BN + 4];
+  __shared__ int64_t a_row[BM], b_col[BN];
+
+  const int tid = threadIdx.x;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t tile = blockIdx.x;
+  const int64_t m0 = (tile / tiles_n) * BM, n0 = (tile % tiles_n) * BN;
+  const int64_t bz = blockIdx.y;
+  const T* A = (const T*)g.A + split_off(bz, g.b_in, g.a_b_o, g.a_b_i);
+  const T* B = (const T*)g.B + split_off(bz, g.b_in, g.b_b_o, g.b_b_i);
+  T* C = (T*)g.C + split_off(bz, g.b_in, g.c_b_o, g.c_b_i);
+
+  if (tid < BM) {
+    int64_t m = m0 + tid;
+    a_row[tid] = m < g.M ? split_off(m, g.m_in, g.a_m_o, g.a_m_i) : -1;
+  } else if (tid < BM + BN) {
+    int64_t n = n0 + tid - BM;
+    b_col[tid - BM] = n < g.N ? split_off(n, g.n_in, g.b_n_o, g.b_n_i) : -1;
+  }
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lq = lane >> 4;
+
+  typedef typename std::conditional<MODE == MODE_F64, d4_t, f4_t>::type acc_t;
+  acc_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+
+  constexpr int PER = BM * BK / NT;   // elements per thread per operand per K step
+  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      int e = tid + i * NT;
+      int kk, mm;
+      if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      int64_t k = k0 + kk;
+      T v = 0;
+      int64_t ro = a_row[mm];
+      if (ro >= 0 && k < g.K) v = A[ro + split_off(k, g.k_in, g.a_k_o, g.a_k_i)];
+      As[kk][mm] = to_lds<MODE>(v);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      int e = tid + i * NT;
+      int kk, nn;
+      if (BN_FAST) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      int64_t k = k0 + kk;
+      T v = 0;
+      int64_t co = b_col[nn];
+      if (co >= 0 && k < g.K) v = B[co + split_off(k, g.k_in, g.b_k_o, g.b_k_i)];
+      Bs[kk][nn] = to_lds<MODE>(v);
+    }
+    __syncthreads();
+    if constexpr (MODE == MODE_F64) {
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        double a0 = As[ks + lq][wm + lr], a1 = As[ks + lq][wm + 16 + lr];
+        double b0 = Bs[ks + lq][wn + lr], b1 = Bs[ks + lq][wn + 16 + lr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else if constexpr (MODE == MODE_F32) {
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        float a0 = As[ks + lq][wm + lr], a1 = As[ks + lq][wm + 16 + lr];
+        float b0 = Bs[ks + lq][wn + lr], b1 = Bs[ks + lq][wn + 16 + lr];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 16) {
+        s4_t a0, a1, b0, b1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int kk = ks + lq * 4 + q;
+          a0[q] = (short)As[kk][wm + lr];
+          a1[q] = (short)As[kk][wm + 16 + lr];
+          b0[q] = (short)Bs[kk][wn + lr];
+          b1[q] = (short)Bs[kk][wn + 16 + lr];
+        }
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // D layout of the 16x16 MFMA tiles: lane l holds rows 4*(l/16)+e, column l%16.
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      int64_t n = n0 + wn + j * 16 + lr;
+      if (n >= g.N) continue;
+      int64_t cn = split_off(n, g.n_in, g.c_n_o, g.c_n_i);
+      double cs = g.colscale ? g.colscale[n] : 1.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t m = m0 + wm + i * 16 + lq * 4 + e;
+        if (m >= g.M) continue;
+        int64_t off = split_off(m, g.m_in, g.c_m_o, g.c_m_i) + cn;
+        T v = (T)(g.alpha * cs * (double)acc[i][j][e]);
+        if (g.beta) v += C[off];
+        C[off] = v;
+      }
+    }
+}
+
+template <int MODE>
+static hipError_t launch_mode(const GemmArgs& g, hipStream_t s) {
+  // all (m, n) tiles of one batch entry along x, batch entries along y
+  dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), (unsigned)g.batch, 1);
+  // choose the fastest-varying index of each staged tile so that loads coalesce
+  bool ak = g.a_k_i == 1 ? true : (g.a_m_i == 1 ? false : true);
+  bool bn = g.b_n_i == 1 ? true : (g.b_k_i == 1 ? false : true);
+  if (ak && bn) contract_kernel<MODE, true, true><<<grid, NT, 0, s>>>(g);
+  else if (ak) contract_kernel<MODE, true, false><<<grid, NT, 0, s>>>(g);
+  else if (bn) contract_kernel<MODE, false, true><<<grid, NT, 0, s>>>(g);
+  else contract_kernel<MODE, false, false><<<grid, NT, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (mode == MODE_F64) return launch_mode<MODE_F64>(g, s);
+  if (mode == MODE_F32) return launch_mode<MODE_F32>(g, s);
+  return launch_mode<MODE_BF16>(g, s);
+}
+
+// ---------------------------------------------------------------------------
+// Strided copy with optional type conversion: out (contiguous, shape dims) is
+// filled from in at offset sum_i idx_i * in_stride_i.
+template <typename TI, typename TO>
+__global__ void permute_kernel(PermArgs p, const TI* __restrict__ in, TO* __restrict__ out, int64_t total) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e, off_in = 0, off_out = 0;
+#pragma unroll
+    for (int i = PERM_MAX_DIMS - 1; i >= 0; --i) {
+      if (i >= p.ndim) continue;
+      int64_t q = r / p.dims[i];
+      int64_t idx = r - q * p.dims[i];
+      r = q;
+      off_in += idx * p.in_strides[i];
+      off_out += idx * p.out_strides[i];
+    }
+    TO v = (TO)in[off_in];
+    if (p.accumulate) out[off_out] += v; else out[off_out] = v;
+  }
+}
+
+static unsigned grid_for(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_permute(const PermArgs& p, int in_type, const void* in, int out_type, void* out, hipStream_t s) {
+  int64_t total = 1;
+  for (int i = 0; i < p.ndim; ++i) total *= p.dims[i];
+  if (total <= 0) return hipSuccess;
+  unsigned gb = grid_for(total);
+  if (in_type == 0 && out_type == 0) permute_kernel<double, double><<<gb, 256, 0, s>>>(p, (const double*)in, (double*)out, total);
+  else if (in_type == 1 && out_type == 1) permute_kernel<float, float><<<gb, 256, 0, s>>>(p, (const float*)in, (float*)out, total);
+  else if (in_type == 0 && out_type == 1) permute_kernel<double, float><<<gb, 256, 0, s>>>(p, (const double*)in, (float*)out, total);
+  else permute_kernel<float, double><<<gb, 256, 0, s>>>(p, (const float*)in, (double*)out, total);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void fill_kernel(T* p, T v, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
+}
+
+hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (type == 0) fill_kernel<double><<<grid_for(n), 256, 0, s>>>((double*)p, v, n);
+  else fill_kernel<float><<<grid_for(n), 256, 0, s>>>((float*)p, (float)v, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Frobenius normalisation of a list of tensors, one workgroup per tensor,
+// sums of squares accumulated in FP64.  Optionally stores the norm.
+template <typename T>
+__global__ __launch_bounds__(256) void normalize_kernel(NormList L) {
+  int t = blockIdx.x;
+  T* x = (T*)L.ptr[t];
+  int64_t n = L.n[t];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) { double v = (double)x[i]; s += v * v; }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double nrm = sqrt(red[0]);
+  if (threadIdx.x == 0 && L.norm_out) L.norm_out[t] = nrm;
+  double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) x[i] = (T)((double)x[i] * inv);
+}
+
+hipError_t launch_normalize(int type, const NormList& L, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (type == 0) normalize_kernel<double><<<count, 256, 0, s>>>(L);
+  else normalize_kernel<float><<<count, 256, 0, s>>>(L);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Projector weights: w_k = s_k^(-1/2) for k < chi when s_k > cutoff * s_0,
+// zero otherwise (pseudo-inverse); batched over ``batch`` spectra of length r.
+__global__ void svd_weights_kernel(const double* s, int64_t r, int64_t stride_s, double* w, int64_t chi,
+                                   double cutoff, int batch) {
+  int b = blockIdx.x;
+  const double* sb = s + b * stride_s;
+  double thr = cutoff * sb[0];
+  for (int64_t k = threadIdx.x; k < chi; k += blockDim.x) {
+    double v = k < r ? sb[k] : 0.0;
+    w[b * chi + k] = (k < r && v > thr) ? 1.0 / sqrt(v) : 0.0;
+  }
+}
+
+hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, double* w, int64_t chi, double cutoff,
+                              int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  svd_weights_kernel<<<batch, 128, 0, st>>>(s, r, stride_s, w, chi, cutoff, batch);
+  return hipGetLastError();
+}
+
+// Lower-trapezoidal factor of an LQ factorisation (column-major rows x cols,
+// leading dimension lda) copied to a dense column-major rows x rcols matrix
+// with the Householder data above the diagonal replaced by zeros.
+__global__ void extract_lower_kernel(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l,
+                                     int64_t rcols, int64_t stride_l, int batch) {
+  int64_t total = rows * rcols;
+  for (int b = 0; b < batch; ++b) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+      int64_t j = e / rows, i = e - j * rows;
+      l[b * stride_l + e] = i >= j ? a[b * stride_a + i + j * lda] : 0.0;
+    }
+  }
+}
+
+hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,
+                                int64_t stride_l, int batch, hipStream_t s) {
+  extract_lower_kernel<<<grid_for(rows * rcols), 256, 0, s>>>(a, rows, lda, stride_a, l, rcols, stride_l, batch);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Energy from plaquette density matrices rho[(k1 k2 k3 k4), (b1 b2 b3 b4)]
+// (d^4 x d^4, row-major, FP64): E = (1/n_sites) sum_t coef_t Tr(h rho_ab)/Tr rho
+// with <h> = sum h[(b_a b_b), (k_a k_b)] rho_ab[(k_a k_b), (b_a b_b)].
+__global__ void energy_kernel(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms,
+                              int n_terms, int d, double inv_sites, double* E_out, double* bond_out) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  int D4 = d * d * d * d;
+  for (int t = threadIdx.x; t < n_terms; t += blockDim.x) {
+    const EnergyTerm tm = terms[t];
+    const double* r = rho + tm.rho_index * rho_stride;
+    double tr = 0.0;
+    for (int i = 0; i < D4; ++i) tr += r[(int64_t)i * D4 + i];
+    double val = 0.0;
+    int dd[4] = {d * d * d, d * d, d, 1};
+    for (int ka = 0; ka < d; ++ka)
+      for (int kb = 0; kb < d; ++kb)
+        for (int ba = 0; ba < d; ++ba)
+          for (int bb = 0; bb < d; ++bb) {
+            double hv = h[(ba * d + bb) * d * d + ka * d + kb];
+            if (hv == 0.0) continue;
+            // partial trace over the two other sites q1 < q2
+            int q1 = -1, q2 = -1;
+            for (int q = 0; q < 4; ++q)
+              if (q != tm.a && q != tm.b) { if (q1 < 0) q1 = q; else q2 = q; }
+            double rab = 0.0;
+            for (int o1 = 0; o1 < d; ++o1)
+              for (int o2 = 0; o2 < d; ++o2) {
+                int ko[4], bo[4];
+                ko[tm.a] = ka; ko[tm.b] = kb; bo[tm.a] = ba; bo[tm.b] = bb;
+                ko[q1] = bo[q1] = o1;
+                ko[q2] = bo[q2] = o2;
+                int ik = 0, ib = 0;
+                for (int q = 0; q < 4; ++q) { ik += ko[q] * dd[q]; ib += bo[q] * dd[q]; }
+                rab += r[(int64_t)ik * D4 + ib];
+              }
+            val += hv * rab;
+          }
+    double bond = val / tr;
+    if (bond_out) bond_out[t] = bond;
+    acc += tm.coef * bond;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *E_out = part[0] * inv_sites;
+}
+
+hipError_t launch_energy(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms, int n_terms,
+                         int d, double inv_sites, double* E_out, double* bond_out, hipStream_t s) {
+  energy_kernel<<<1, 256, 0, s>>>(rho, rho_stride, h, terms, n_terms, d, inv_sites, E_out, bond_out);
+  return hipGetLastError();
+}
+
+// Non-finite detector: sets *flag = 1 if any entry of x is NaN or Inf.
+template <typename T>
+__global__ void nonfinite_kernel(const T* x, int64_t n, int* flag) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double v = (double)x[e];
+    if (!(v == v) || v - v != 0.0) atomicOr(flag, 1);
+  }
+}
+
+hipError_t launch_nonfinite(int type, const void* x, int64_t n, int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (type == 0) nonfinite_kernel<double><<<grid_for(n), 256, 0, s>>>((const double*)x, n, flag);
+  else nonfinite_kernel<float><<<grid_for(n), 256, 0, s>>>((const float*)x, n, flag);
+  return hipGetLastError();
+}
+
+// Spectra test: for each of ``count`` spectra of length r (descending singular
+// values), normalise to unit sum, store, and reduce max_c sum_k |s_k - prev_k|.
+__global__ void spectra_delta_kernel(const double* sv, int64_t r, int64_t chi, double* cur, const double* prev,
+                                     int count, double* delta_out) {
+  __shared__ double best[256];
+  double mx = 0.0;
+  for (int c = threadIdx.x; c < count; c += blockDim.x) {
+    const double* s = sv + (int64_t)c * r;
+    double tot = 0.0;
+    for (int64_t k = 0; k < r; ++k) tot += s[k];
+    double inv = tot > 0.0 ? 1.0 / tot : 0.0;
+    double d = 0.0;
+    for (int64_t k = 0; k < chi; ++k) {
+      double v = k < r ? s[k] * inv : 0.0;
+      cur[(int64_t)c * chi + k] = v;
+      if (prev) d += fabs(v - prev[(int64_t)c * chi + k]);
+    }
+    mx = fmax(mx, d);
+  }
+  best[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) best[threadIdx.x] = fmax(best[threadIdx.x], best[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *delta_out = prev ? best[0] : 1e300;
+}
+
+hipError_t launch_spectra_delta(const double* sv, int64_t r, int64_t chi, double* cur, const double* prev, int count,
+                                double* delta_out, hipStream_t s) {
+  spectra_delta_kernel<<<1, 256, 0, s>>>(sv, r, chi, cur, prev, count, delta_out);
+  return hipGetLastError();
+}
+
+// flag |= (src != 0), for solver status codes that are overwritten by the next call
+__global__ void flag_or_kernel(const int* src, int* flag) {
+  if (threadIdx.x == 0 && *src != 0) atomicOr(flag, 1);
+}
+
+hipError_t launch_flag_or(const int* src, int* flag, hipStream_t s) {
+  flag_or_kernel<<<1, 64, 0, s>>>(src, flag);
+  return hipGetLastError();
+}
+
+}  // namespace ctmk

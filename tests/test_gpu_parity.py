@@ -1,0 +1,154 @@
+"""GPU library (through the C ABI) against the CPU oracle.
+
+The nested CTMRG iteration is chaotic on random tensors until it has
+converged (a relative change of 1e-13 in A reaches order one within a few
+sweeps), so two correct implementations with different rounding agree at
+fixed sweep counts only while the amplification is small.  The parity tests
+therefore compare (i) quantities computed from the same environment (density
+matrices, energies), (ii) one sweep from the same environment (gauge-invariant
+corner spectra and energy), (iii) exactly solvable states and (iv) converged
+runs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.ctmrg import CTM as OCTM, corner_spectra, env_from_flat, env_to_flat, init_env
+from oracle.rdm import energy as oenergy, plaquette_rdm as orho
+
+pytestmark = pytest.mark.gpu
+
+H = synth.heisenberg_bond()
+
+
+@pytest.fixture(scope="module")
+def ctm_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_14414_amd as m
+    return m
+
+
+def gpu_spectra(env_flat, sites, chi):
+    env = env_from_flat(env_flat.cpu(), sites, chi)
+    return corner_spectra(env, chi)
+
+
+CASES = [
+    ("heis_1x1_D2", 1, 2, 8, [[0]], "uniform", 0),
+    ("cell_2x2_D2", 4, 2, 8, [[0, 1], [2, 3]], "uniform", 1),
+    ("cell_2x1_D3", 2, 3, 12, [[0, 1]], "normal", 2),
+]
+
+
+@pytest.mark.parametrize("name,nt,D,chi,pattern,dist,seed", CASES)
+def test_start_environment_matches_oracle(ctm_mod, name, nt, D, chi, pattern, dist, seed):
+    A = synth.site_tensors(nt, 2, D, seed, dist)
+    g = ctm_mod.CTM(A, pattern, chi)
+    o = OCTM(A, pattern, chi)
+    ref = env_to_flat(init_env(o.sites), o.sites, chi)
+    got = g.get_env().cpu()
+    assert got.shape == ref.shape
+    assert torch.allclose(got, ref, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("name,nt,D,chi,pattern,dist,seed", CASES)
+def test_rdm_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dist, seed):
+    A = synth.site_tensors(nt, 2, D, seed, dist)
+    Ly, Lx = len(pattern), len(pattern[0])
+    env0 = synth.random_env_flat(chi, D, 2, Lx, Ly, seed + 10)
+    g = ctm_mod.CTM(A, pattern, chi)
+    g.set_env(torch.tensor(env0))
+    terms = synth.heisenberg_terms(Lx, Ly)
+    E = g.energy(H, terms)
+    rhos = g.last_rdms()
+    o = OCTM(A, pattern, chi, env0=env0)
+    plaqs = []
+    for t in terms:
+        if (t[0], t[1]) not in plaqs:
+            plaqs.append((t[0], t[1]))
+    for i, (px, py) in enumerate(plaqs):
+        ref = orho(o.sites, o.env, px, py)
+        scale = ref.abs().max()
+        assert torch.allclose(rhos[i], ref, rtol=0, atol=1e-12 * scale), (px, py)
+    Eo = oenergy(o, H, terms).item()
+    assert abs(E - Eo) < 1e-11 * max(1.0, abs(Eo))
+
+
+@pytest.mark.parametrize("name,nt,D,chi,pattern,dist,seed", CASES)
+def test_one_sweep_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dist, seed):
+    A = synth.site_tensors(nt, 2, D, seed, dist)
+    Ly, Lx = len(pattern), len(pattern[0])
+    env0 = synth.random_env_flat(chi, D, 2, Lx, Ly, seed + 20)
+    g = ctm_mod.CTM(A, pattern, chi)
+    g.set_env(torch.tensor(env0))
+    g.sweep(1)
+    o = OCTM(A, pattern, chi, env0=env0)
+    o.run(1)
+    sg = gpu_spectra(g.get_env(), o.sites, chi)
+    so = corner_spectra(o.env, chi)
+    assert torch.allclose(sg, so, rtol=0, atol=1e-9)
+    terms = synth.heisenberg_terms(Lx, Ly)
+    E, Eo = g.energy(H, terms), oenergy(o, H, terms).item()
+    assert abs(E - Eo) < 1e-8 * max(1.0, abs(Eo))
+
+
+def test_two_sweeps_from_sites_start(ctm_mod):
+    cfg = synth.CONFIGS["heis_d2_chi8"]
+    A = synth.config_tensors(cfg, 0)
+    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+    g.sweep(2)
+    o = OCTM(A, cfg["pattern"], cfg["chi"])
+    o.run(2)
+    terms = synth.config_terms(cfg)
+    E, Eo = g.energy(H, terms), oenergy(o, H, terms).item()
+    assert abs(E - Eo) < 1e-8 * max(1.0, abs(Eo))
+
+
+def test_neel_and_uniform_product_states(ctm_mod):
+    A = synth.product_state_tensors([[1.0, 0.0], [0.0, 1.0]])
+    g = ctm_mod.CTM(A, [[0, 1], [1, 0]], 2)
+    g.sweep(3)
+    assert abs(g.energy(H, synth.heisenberg_terms(2, 2)) + 0.5) < 1e-13
+    g2 = ctm_mod.CTM(synth.product_state_tensors([[0.6, 0.8]]), [[0]], 2)
+    g2.sweep(3)
+    assert abs(g2.energy(H, synth.heisenberg_terms(1, 1)) - 0.5) < 1e-13
+
+
+def test_dimer_states(ctm_mod):
+    A = synth.gauge_transform(synth.columnar_dimer_tensors(), [[0, 1]], 1)
+    g = ctm_mod.CTM(A, [[0, 1]], 8)
+    g.sweep(8)
+    assert abs(g.energy(H, synth.heisenberg_terms(2, 1)) + 0.375) < 1e-12
+    A = synth.gauge_transform(synth.orthogonal_dimer_tensors(), [[0, 1], [2, 3]], 2)
+    g = ctm_mod.CTM(A, [[0, 1], [2, 3]], 8)
+    g.sweep(10)
+    assert abs(g.energy(H, synth.shastry_sutherland_terms(0.7, 1.0)) + 0.375) < 1e-12
+
+
+def test_vertical_chains_from_generic_start(ctm_mod):
+    from test_oracle_pins import _chain_exact
+    A = synth.vertical_chain_tensors(3)
+    eh, ev = _chain_exact(A)
+    g = ctm_mod.CTM(A, [[0]], 8)
+    g.set_env(torch.tensor(synth.random_env_flat(8, 2, 2, 1, 1, seed=1)))
+    n, delta, ok = g.sweep(300, tol=1e-12)
+    assert abs(g.energy(H, synth.heisenberg_terms(1, 1)) - (eh + ev)) < 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 5e-2)])
+def test_mixed_precision_error_against_fp64_oracle(ctm_mod, precision, tol):
+    cfg = synth.CONFIGS["heis_d2_chi8"]
+    A = synth.config_tensors(cfg, 1)
+    o = OCTM(A, cfg["pattern"], cfg["chi"])
+    o.run(80)
+    env = env_to_flat(o.env, o.sites, cfg["chi"])
+    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"], precision=precision)
+    g.set_env(env)
+    g.sweep(2)
+    o.run(2)
+    terms = synth.config_terms(cfg)
+    err = abs(g.energy(H, terms) - oenergy(o, H, terms).item())
+    print(f"{precision}: |dE| = {err:.3e}")
+    assert err < tol
