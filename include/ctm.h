@@ -122,10 +122,19 @@ int ctm_energy(ctm_ctx* ctx, const double* H_bond, int n_terms, const ctm_term* 
 int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
 
 /* Options (key, value):
- *   "svd_cutoff"  relative cutoff below which s^(-1/2) is set to zero (default 1e-12)
+ *   "svd_cutoff"  relative cutoff below which s^(-1/2) is set to zero (default 1e-10)
  *   "lorentz_eta" relative Lorentzian width of the SVD derivative (default 1e-12)
  *   "check_finite" 1 to test the environment for NaN/Inf after every sweep (default 1) */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
+
+/* Live timing of the MFMA contraction kernel (the corner, half-system,
+ * projection and density-matrix contractions).  Between ctm_profile_begin and
+ * ctm_profile_end every launch of that kernel, by any context of the process,
+ * is bracketed by two HIP events on its stream.  ctm_profile_end (host
+ * outputs, each may be NULL) returns the summed kernel time in milliseconds,
+ * the summed algorithmic flops (2*M*N*K per launch) and the launch count. */
+int ctm_profile_begin(ctm_ctx* ctx);
+int ctm_profile_end(ctm_ctx* ctx, double* kernel_ms, double* kernel_flops, int64_t* launches);
 
 /* Message of the last error of this context (or of the last failed ctm_init if ctx is NULL). */
 const char* ctm_last_error(const ctm_ctx* ctx);

@@ -111,7 +111,7 @@ def detach_env(env):
     return [[{k: v.detach().clone() for k, v in e.items()} for e in row] for row in env]
 
 
-def energy_after_sweeps(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-12, eta=1e-12,
+def energy_after_sweeps(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-10, eta=1e-12,
                         use_checkpoint=True):
     """E(A) after ``n_sweeps`` sweeps from the constant environment ``env0``; differentiable in A.
 
@@ -146,7 +146,7 @@ def energy_after_sweeps(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-12,
     return energy_from_rdms(rdms, H, terms, Lx * Ly), env
 
 
-def energy_and_grad(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-12, eta=1e-12, use_checkpoint=True):
+def energy_and_grad(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-10, eta=1e-12, use_checkpoint=True):
     """(E, dE/dA, final environment) for ``energy_after_sweeps``."""
     A = torch.as_tensor(A, dtype=torch.float64).clone().requires_grad_(True)
     E, env = energy_after_sweeps(A, pattern, chi, detach_env(env0), n_sweeps, H, terms, cutoff, eta, use_checkpoint)

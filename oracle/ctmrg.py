@@ -24,7 +24,9 @@ Readings of points the paper leaves open (all stated in the design doc as well):
   their projectors are exactly rank-deficient and the iteration stays in a
   wrong invariant sector);
 * projectors keep chi' = min(chi, number of singular values of M); singular
-  values below ``cutoff * s_1`` get a zero in place of s^(-1/2);
+  values below ``cutoff * s_1`` (default 1e-10) get a zero in place of
+  s^(-1/2): smaller ones carry directions fixed only by rounding and, with
+  weights s^(-1/2), make even weakly entangled states iterate chaotically;
 * every updated tensor is divided by its Frobenius norm;
 * a sweep is the left, right, up and down moves in that order; the column
   steps of a move go in increasing order in the move's own frame;
@@ -195,7 +197,7 @@ def corner_spectra(env, chi):
 class CTM:
     """Oracle CTMRG state for one set of site tensors."""
 
-    def __init__(self, A, pattern, chi, cutoff=1e-12, env0=None):
+    def __init__(self, A, pattern, chi, cutoff=1e-10, env0=None):
         """``env0``: optional starting environment in the flat layout of ``env_to_flat``;
         by default the sites-derived start of ``init_env`` is used."""
         self.pattern, self.chi, self.cutoff = pattern, chi, cutoff

@@ -45,6 +45,8 @@ def _load():
         "ctm_energy": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D)]),
         "ctm_last_rdms": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
         "ctm_set_option": (I, [P, ctypes.c_char_p, D]),
+        "ctm_profile_begin": (I, [P]),
+        "ctm_profile_end": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "ctm_last_error": (ctypes.c_char_p, [P]),
         "ctm_free": (None, [P]),
     }
@@ -56,7 +58,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("ctm_init", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
-            "ctm_sweep", "ctm_energy", "ctm_last_rdms", "ctm_set_option", "ctm_last_error", "ctm_free")
+            "ctm_sweep", "ctm_energy", "ctm_last_rdms", "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
+            "ctm_last_error", "ctm_free")
 
 
 def _terms(terms):
@@ -149,6 +152,14 @@ class CTM:
         k = min(n.value, capacity)
         d4 = self.d ** 4
         return torch.tensor(list(buf[: k * d8]), dtype=torch.float64).reshape(k, d4, d4)
+
+    def profile_begin(self):
+        self._check(LIB.ctm_profile_begin(self._h))
+
+    def profile_end(self):
+        ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        self._check(LIB.ctm_profile_end(self._h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)))
+        return ms.value, fl.value, n.value
 
     def set_option(self, key, value):
         self._check(LIB.ctm_set_option(self._h, key.encode(), float(value)))

@@ -72,7 +72,7 @@ struct ctm_ctx {
   DBuf env;
   std::vector<int64_t> slot_off, slot_leg;
   int64_t env_elems = 0;
-  double cutoff = 1e-12, eta = 1e-12;
+  double cutoff = 1e-10, eta = 1e-12;
   int check_finite = 1;
   DBuf spec_prev, spec_cur, dscal;   // spectra and a few device scalars
   bool have_prev = false;
@@ -760,6 +760,29 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "check_finite") c->check_finite = value != 0;
   else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }
   return CTM_OK;
+}
+
+int ctm_profile_begin(ctm_ctx* c) {
+  if (!c) return CTM_EINVAL;
+  try {
+    HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+    g_counters.reset_timing();
+    g_counters.timing = true;
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_profile_end(ctm_ctx* c, double* kernel_ms, double* kernel_flops, int64_t* launches) {
+  if (!c) return CTM_EINVAL;
+  try {
+    g_counters.timing = false;
+    double ms = g_counters.collect_ms();
+    if (kernel_ms) *kernel_ms = ms;
+    if (kernel_flops) *kernel_flops = g_counters.flops;
+    if (launches) *launches = g_counters.launches;
+    g_counters.reset_timing();
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
 }
 
 const char* ctm_last_error(const ctm_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }

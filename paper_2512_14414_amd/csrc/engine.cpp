@@ -9,6 +9,33 @@ namespace ctm {
 
 Counters g_counters;
 
+void Counters::reset_timing() {
+  used = 0;
+  launches = 0;
+  flops = 0;
+}
+
+void Counters::record(hipStream_t s, bool start) {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  (void)start;
+  HIP_CHECK(hipEventRecord(pool[used++], s));
+}
+
+double Counters::collect_ms() {
+  double ms = 0;
+  if (used) HIP_CHECK(hipEventSynchronize(pool[used - 1]));
+  for (size_t i = 0; i + 1 < used; i += 2) {
+    float t = 0;
+    HIP_CHECK(hipEventElapsedTime(&t, pool[i], pool[i + 1]));
+    ms += t;
+  }
+  return ms;
+}
+
 TRef view(void* p, int type, const std::vector<int64_t>& dims, const std::string& lab) {
   if (dims.size() != lab.size()) throw Error(-1, "view: labels do not match rank: " + lab);
   TRef t;
@@ -187,7 +214,9 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
   }
   g_counters.launches++;
   g_counters.flops += 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
+  if (g_counters.timing) g_counters.record(dev.stream, true);
   HIP_CHECK(ctmk::launch_contract(A.type == T_F64 ? ctmk::MODE_F64 : mode, g, dev.stream));
+  if (g_counters.timing) g_counters.record(dev.stream, false);
 }
 
 }  // namespace

@@ -101,10 +101,18 @@ Tmp permuted(Dev& dev, const TRef& in, const std::string& lab, int type = -1);
 
 void fill(Dev& dev, const TRef& t, double v);   // t must be contiguous
 
-// Count of contraction-kernel launches and their nominal flops, for profiling.
+// Count of contraction-kernel launches and their algorithmic flops (2 M N K per
+// batch entry).  While ``timing`` is on, every launch is bracketed by a pair
+// of HIP events on the launching stream; ``collect`` then sums their times.
 struct Counters {
   int64_t launches = 0;
   double flops = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  void reset_timing();
+  void record(hipStream_t s, bool start);
+  double collect_ms();
 };
 extern Counters g_counters;
 

@@ -149,7 +149,9 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
     __syncthreads();
   }
 
-  // D layout of the 16x16 MFMA tiles: lane l holds rows 4*(l/16)+e, column l%16.
+  // D layout of the 16x16 MFMA tiles (measured on gfx950): register e of lane l
+  // holds column l%16 and row 4*(l/16)+e for the f32 and bf16 instructions,
+  // row (l/16)+4*e for v_mfma_f64_16x16x4f64.
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -160,7 +162,8 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
       double cs = g.colscale ? g.colscale[n] : 1.0;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        int64_t m = m0 + wm + i * 16 + lq * 4 + e;
+        const int row = MODE == MODE_F64 ? lq + 4 * e : lq * 4 + e;
+        int64_t m = m0 + wm + i * 16 + row;
         if (m >= g.M) continue;
         int64_t off = split_off(m, g.m_in, g.c_m_o, g.c_m_i) + cn;
         T v = (T)(g.alpha * cs * (double)acc[i][j][e]);

@@ -235,3 +235,22 @@ def random_env_flat(chi: int, D: int, d: int, Lx: int, Ly: int, seed: int) -> np
             l, u, r, dn = legs[kind[(I % 2, J % 2)]]
             n += 4 * chi * chi + chi * chi * (u + r + dn + l)
     return np.random.default_rng(seed).uniform(0.0, 1.0, size=n)
+
+
+def near_product_tensors(n_tensors: int, d: int, D: int, seed: int, eps: float = 0.2) -> np.ndarray:
+    """Random site tensors close to a product state (short correlation length).
+
+    A_t = v_t (x) e_0 e_0 e_0 e_0 + eps * G / |G| with G a N(0, 1) tensor, then
+    unit Frobenius norm, with v_t a random unit vector of the physical space.  CTMRG on such states
+    converges in a few sweeps and is well conditioned, which makes them the
+    workload for tight multi-sweep comparisons.
+    """
+    rng = np.random.default_rng(seed)
+    out = np.empty((n_tensors, d, D, D, D, D))
+    for t in range(n_tensors):
+        v = rng.standard_normal(d)
+        g = rng.standard_normal((d, D, D, D, D))
+        a = eps * g / np.linalg.norm(g)
+        a[:, 0, 0, 0, 0] += v / np.linalg.norm(v)
+        out[t] = a / np.linalg.norm(a)
+    return out
