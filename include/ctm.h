@@ -130,8 +130,9 @@ int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 /* Live timing of the MFMA contraction kernel (the corner, half-system,
  * projection and density-matrix contractions).  Between ctm_profile_begin and
  * ctm_profile_end every launch of that kernel, by any context of the process,
- * is bracketed by two HIP events on its stream.  ctm_profile_end (host
- * outputs, each may be NULL) returns the summed kernel time in milliseconds,
+ * is bracketed by two HIP events on its stream.  ctm_profile_end fills three
+ * host arrays of 3 entries each (any may be NULL), indexed by the matrix-core
+ * path 0 = FP64, 1 = FP32, 2 = BF16: the summed kernel time in milliseconds,
  * the summed algorithmic flops (2*M*N*K per launch) and the launch count. */
 int ctm_profile_begin(ctm_ctx* ctx);
 int ctm_profile_end(ctm_ctx* ctx, double* kernel_ms, double* kernel_flops, int64_t* launches);

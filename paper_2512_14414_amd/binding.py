@@ -157,9 +157,10 @@ class CTM:
         self._check(LIB.ctm_profile_begin(self._h))
 
     def profile_end(self):
-        ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        self._check(LIB.ctm_profile_end(self._h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)))
-        return ms.value, fl.value, n.value
+        """{path: (kernel ms, algorithmic flops, launches)} for path in fp64, fp32, bf16."""
+        ms, fl, n = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_int64 * 3)()
+        self._check(LIB.ctm_profile_end(self._h, ms, fl, n))
+        return {k: (ms[i], fl[i], n[i]) for i, k in enumerate(("fp64", "fp32", "bf16"))}
 
     def set_option(self, key, value):
         self._check(LIB.ctm_set_option(self._h, key.encode(), float(value)))

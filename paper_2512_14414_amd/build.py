@@ -16,7 +16,7 @@ def build(verbose: bool = False) -> str:
            "-I", os.path.join(ROOT, "include"),
            *[os.path.join(HERE, s) for s in SOURCES],
            "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib",
-           "-o", OUT + ".tmp"]
+           "-Wl,--no-undefined", "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

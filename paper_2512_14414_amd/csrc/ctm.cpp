@@ -15,6 +15,8 @@
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -74,6 +76,8 @@ struct ctm_ctx {
   int64_t env_elems = 0;
   double cutoff = 1e-10, eta = 1e-12;
   int check_finite = 1;
+  int jacobi_max_sweeps = 40;
+  int last_jacobi_sweeps = 0;
   DBuf spec_prev, spec_cur, dscal;   // spectra and a few device scalars
   bool have_prev = false;
   DBuf rdm_buf;
@@ -277,10 +281,10 @@ void init_env(ctm_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// Projectors of the cut between rows I and I+1 at column step J of frame f
-// (Fig. CTMRG c, Eqs. PQ and QRSVD).  P and Q are written as float64
-// [(chi-leg, site-leg), chi] matrices; the site leg is the down leg of (I, J).
-void projectors(ctm_ctx* c, int f, int I, int J, double* P, double* Q) {
+// Half systems of the cut between rows I and I+1 at column step J of frame f
+// (Fig. CTMRG c): N[(h w), (e z)] from the upper quadrants and S[(h v), (e x)]
+// from the lower ones, written as float64 row-major matrices.
+void half_systems(ctm_ctx* c, int f, int I, int J, double* Nout, double* Sout) {
   Dev& dev = c->dev;
   const int64_t chi = c->chi;
   const int m = c->mode;
@@ -317,52 +321,167 @@ void projectors(ctm_ctx* c, int f, int I, int J, double* P, double* Q) {
   Tmp DR(&dev, c->st, {chi, chi, sDR.dim[0], sDR.dim[1]}, "hclv");
   contract(dev, m, DR.t, W2.t, sDR);
 
-  // half systems N[(h w), (e z)] and S[(h v), (e x)] (Eq. QRSVD), in float64
   const int64_t zdim = sUL.dim[3], wdim = sUR.dim[3], vdim = sDR.dim[1], xdim = sDL.dim[1];
   if (zdim != xdim || wdim != vdim) throw Error(CTM_EINVAL, "inconsistent nested bond dimensions");
-  const int64_t kd = chi * zdim, mn = chi * wdim;
-  DBuf Nb(&dev, (size_t)mn * kd * 8), Sb(&dev, (size_t)mn * kd * 8);
-  {
-    TRef Nv = view(Nb.p, T_F64, {chi, wdim, chi, zdim}, "hwez");
-    TRef Sv = view(Sb.p, T_F64, {chi, vdim, chi, xdim}, "hvex");
-    if (c->st == T_F64) {
-      contract(dev, m, Nv, UR.t, relabel(UL.t, "clez"));
-      contract(dev, m, Sv, DR.t, relabel(DL.t, "cexl"));
-    } else {
-      Tmp N32(&dev, c->st, {chi, wdim, chi, zdim}, "hwez");
-      contract(dev, m, N32.t, UR.t, relabel(UL.t, "clez"));
-      copy_into(dev, Nv, N32.t);
-      Tmp S32(&dev, c->st, {chi, vdim, chi, xdim}, "hvex");
-      contract(dev, m, S32.t, DR.t, relabel(DL.t, "cexl"));
-      copy_into(dev, Sv, S32.t);
+  TRef Nv = view(Nout, T_F64, {chi, wdim, chi, zdim}, "hwez");
+  TRef Sv = view(Sout, T_F64, {chi, vdim, chi, xdim}, "hvex");
+  if (c->st == T_F64) {
+    contract(dev, m, Nv, UR.t, relabel(UL.t, "clez"));
+    contract(dev, m, Sv, DR.t, relabel(DL.t, "cexl"));
+  } else {
+    Tmp N32(&dev, c->st, {chi, wdim, chi, zdim}, "hwez");
+    contract(dev, m, N32.t, UR.t, relabel(UL.t, "clez"));
+    copy_into(dev, Nv, N32.t);
+    Tmp S32(&dev, c->st, {chi, vdim, chi, xdim}, "hvex");
+    contract(dev, m, S32.t, DR.t, relabel(DL.t, "cexl"));
+    copy_into(dev, Sv, S32.t);
+  }
+}
+
+// SVD of the r x r column-major matrices A[b] (stride r*r) by one-sided
+// Jacobi with QR preconditioning: A = Q R (Householder), the columns of
+// X = R^T are rotated until mutually orthogonal, X W = U_X diag(s), so that
+// A = (Q W) diag(s) U_X^T.  Starting from R^T instead of A cuts the number of
+// Jacobi sweeps about threefold on the graded spectra of CTMRG.  Outputs: all
+// r singular values, descending, to sv[b]; the kmax leading left vectors to
+// U[b] and right vectors to Vk[b] (column-major r x kmax).  A is overwritten.
+int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double* sv, double* U, double* Vk) {
+  Dev& dev = c->dev;
+  const int64_t stride = r * r;
+  DBuf X(&dev, (size_t)batch * stride * 8), W(&dev, (size_t)batch * stride * 8), tau(&dev, (size_t)batch * r * 8),
+      rot(&dev, (size_t)batch * sizeof(int)), tiny2(&dev, (size_t)batch * 8);
+  RB_CHECK(rocsolver_dgeqrf_strided_batched(c->blas, (rocblas_int)r, (rocblas_int)r, A, (rocblas_int)r, stride,
+                                            (double*)tau.p, r, batch));
+  HIP_CHECK(ctmk::launch_rt_from_qr(A, (double*)X.p, r, stride, batch, dev.stream));
+  HIP_CHECK(ctmk::launch_identity((double*)W.p, r, stride, batch, dev.stream));
+  HIP_CHECK(ctmk::launch_frob_tiny((const double*)X.p, stride, stride, batch, 2.2e-16, (double*)tiny2.p, dev.stream));
+  const double tol = std::max(1e-15, 2.2e-16 * std::sqrt((double)r));
+  const int64_t rounds = r + (r & 1) - 1;
+  std::vector<int> h(batch);
+  int sweep = 0;
+  for (sweep = 1; sweep <= c->jacobi_max_sweeps; ++sweep) {
+    HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, batch, dev.stream));
+    for (int64_t t = 0; t < rounds; ++t)
+      HIP_CHECK(ctmk::launch_jacobi_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
+                                          (const double*)tiny2.p, (int*)rot.p, dev.stream));
+    HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, batch * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
+    HIP_CHECK(hipStreamSynchronize(dev.stream));
+    bool any = false;
+    for (int b = 0; b < batch; ++b) any |= h[b] != 0;
+    if (!any) break;
+  }
+  if (sweep > c->jacobi_max_sweeps) throw Error(CTM_ESOLVER, "Jacobi SVD did not converge");
+  // normalised columns of X W are the right vectors of A; the columns of W, times Q, the left ones
+  HIP_CHECK(ctmk::launch_jacobi_finish((const double*)X.p, (const double*)W.p, r, stride, batch, kmax, sv, Vk, U,
+                                       dev.stream));
+  for (int b = 0; b < batch; ++b)
+    RB_CHECK(rocsolver_dormqr(c->blas, rocblas_side_left, rocblas_operation_none, (rocblas_int)r, (rocblas_int)kmax,
+                              (rocblas_int)r, A + (size_t)b * stride, (rocblas_int)r, (double*)tau.p + (size_t)b * r,
+                              U + (size_t)b * r * kmax, (rocblas_int)r));
+  c->last_jacobi_sweeps = sweep;
+  return sweep;
+}
+
+// Projectors of every row of column step J of frame f (Eqs. PQ, QRSVD), in
+// float64, written to P64/Q64 + I*maxkd*chi as [(chi-leg, site-leg), chi]
+// matrices (the site leg is the down leg of (I, J)).
+//
+// Rows of equal parity have equal shapes and are handled together.  With
+// N, S of shape mn x kd (rows: right cut, columns: left cut a5a6):
+//  * mn > kd (tall): N^T = L_n Q_n and S^T = L_s Q_s (LQ of the column-major
+//    views, i.e. R = L^T of Eq. QRSVD), M = R_n R_s^T = L_n^T L_s;
+//    P = R_s^T V w = L_s V w, Q = R_n^T U w = L_n U w;
+//  * mn <= kd: the QR would not shrink anything, and rho = N S^T (mn x mn)
+//    has the same singular values as R_n R_s^T with U_rho = Q_n U,
+//    V_rho = Q_s V, so M = rho and P = S^T V_rho w, Q = N^T U_rho w (the
+//    same products as above, since N^T stored row-major is exactly a
+//    column-major kd x mn matrix like L_n).
+// In both cases M is r x r with r = chi*D, and w_k = s_k^(-1/2) for the chi
+// largest s_k above cutoff * s_1 (zero otherwise).
+void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64_t maxkd) {
+  Dev& dev = c->dev;
+  const int a = c->ny(f);
+  const int64_t chi = c->chi;
+  const int m = c->mode;
+  int64_t kd[2] = {0, 0}, mn[2] = {0, 0};
+  int cnt[2] = {0, 0};
+  for (int I = 0; I < a; ++I) {
+    int p = I & 1;
+    kd[p] = chi * c->site(f, I, J).dim[3];
+    mn[p] = chi * c->site(f, I, J + 1).dim[3];
+    cnt[p]++;
+  }
+  const int64_t r = std::min(kd[0], mn[0]);
+  for (int p = 0; p < 2; ++p)
+    if (cnt[p] && std::min(kd[p], mn[p]) != r) throw Error(CTM_EINVAL, "rows of a column step differ in rank bound");
+  DBuf Nb[2], Sb[2], Ln[2], Ls[2], tau[2];
+  for (int p = 0; p < 2; ++p) {
+    if (!cnt[p]) continue;
+    Nb[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * mn[p] * 8);
+    Sb[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * mn[p] * 8);
+  }
+  for (int I = 0; I < a; ++I) {
+    int p = I & 1, b = I >> 1;
+    half_systems(c, f, I, J, (double*)Nb[p].p + (size_t)b * kd[p] * mn[p], (double*)Sb[p].p + (size_t)b * kd[p] * mn[p]);
+  }
+  DBuf Mb(&dev, (size_t)a * r * r * 8), sv(&dev, (size_t)a * r * 8), Uk(&dev, (size_t)a * r * chi * 8),
+      Vk(&dev, (size_t)a * r * chi * 8), w(&dev, (size_t)a * chi * 8);
+  const double* Lf[2] = {nullptr, nullptr};   // column-major kd x r left factors (Q side)
+  const double* Rf[2] = {nullptr, nullptr};   // right factors (P side)
+  for (int p = 0; p < 2; ++p) {
+    if (!cnt[p]) continue;
+    const int64_t sz = kd[p] * mn[p];
+    TRef Mv{(double*)Mb.p + (size_t)p * r * r, T_F64, {cnt[p], r, r}, {2 * r * r, 1, r}, "bij"};
+    // N (rows a1a2, columns a5a6) sits column-major as N^T; its LQ factor L is
+    // R_n^T of the QR of Eq. QRSVD (kd x r, lower trapezoidal).  The QR is taken
+    // also when N is not tall: forming N S^T directly loses the accuracy of the
+    // small kept singular values that the triangular factors preserve.
+    Ln[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * r * 8);
+    Ls[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * r * 8);
+    tau[p] = DBuf(&dev, (size_t)cnt[p] * r * 8 * 2);
+    RB_CHECK(rocsolver_dgelqf_strided_batched(c->blas, (rocblas_int)kd[p], (rocblas_int)mn[p], (double*)Nb[p].p,
+                                              (rocblas_int)kd[p], sz, (double*)tau[p].p, r, cnt[p]));
+    RB_CHECK(rocsolver_dgelqf_strided_batched(c->blas, (rocblas_int)kd[p], (rocblas_int)mn[p], (double*)Sb[p].p,
+                                              (rocblas_int)kd[p], sz, (double*)tau[p].p + (size_t)cnt[p] * r, r,
+                                              cnt[p]));
+    HIP_CHECK(ctmk::launch_extract_lower((const double*)Nb[p].p, kd[p], kd[p], sz, (double*)Ln[p].p, r, kd[p] * r,
+                                         cnt[p], dev.stream));
+    HIP_CHECK(ctmk::launch_extract_lower((const double*)Sb[p].p, kd[p], kd[p], sz, (double*)Ls[p].p, r, kd[p] * r,
+                                         cnt[p], dev.stream));
+    TRef Lnv{Ln[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "bai"};
+    TRef Lsv{Ls[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "baj"};
+    contract(dev, m, Mv, Lnv, Lsv);
+    Lf[p] = (const double*)Ln[p].p;
+    Rf[p] = (const double*)Ls[p].p;
+  }
+  // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
+  jacobi_svd(c, (double*)Mb.p, r, a, chi, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
+  HIP_CHECK(ctmk::launch_svd_weights((const double*)sv.p, r, r, (double*)w.p, chi, c->cutoff, a, dev.stream));
+  for (int I = 0; I < a; ++I) {
+    int p = I & 1, b = I >> 1;
+    const int64_t lfs = kd[p] * r;
+    TRef Lv{(void*)(Lf[p] + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
+    TRef Rv{(void*)(Rf[p] + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
+    TRef Uv{(double*)Uk.p + (size_t)I * r * chi, T_F64, {r, chi}, {1, r}, "ik"};
+    TRef Vv{(double*)Vk.p + (size_t)I * r * chi, T_F64, {r, chi}, {1, r}, "ik"};
+    const double* wI = (const double*)w.p + (size_t)I * chi;
+    contract(dev, m, view(P64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Rv, Vv, 1.0, 0, wI);
+    contract(dev, m, view(Q64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Lv, Uv, 1.0, 0, wI);
+  }
+  if (const char* dump = getenv("CTM_DEBUG_DUMP")) {   // development aid: singular values of each row
+    std::vector<double> h((size_t)a * r);
+    HIP_CHECK(hipMemcpyAsync(h.data(), sv.p, h.size() * 8, hipMemcpyDeviceToHost, dev.stream));
+    HIP_CHECK(hipStreamSynchronize(dev.stream));
+    FILE* fp = fopen(dump, "a");
+    if (fp) {
+      for (int I = 0; I < a; ++I) {
+        fprintf(fp, "f%d J%d I%d sweeps%d", f, J, I, c->last_jacobi_sweeps);
+        for (int64_t k = 0; k < r; ++k) fprintf(fp, " %.17g", h[(size_t)I * r + k]);
+        fprintf(fp, "\n");
+      }
+      fclose(fp);
     }
   }
-  // N (row-major mn x kd) is the column-major kd x mn matrix N^T; its LQ
-  // factorisation N^T = L Q gives R_n = L^T (and likewise for S).
-  const int64_t r = std::min(kd, mn);
-  DBuf tau(&dev, (size_t)r * 8 * 2), Ln(&dev, (size_t)kd * r * 8), Ls(&dev, (size_t)kd * r * 8);
-  RB_CHECK(rocsolver_dgelqf(c->blas, (rocblas_int)kd, (rocblas_int)mn, (double*)Nb.p, (rocblas_int)kd, (double*)tau.p));
-  RB_CHECK(rocsolver_dgelqf(c->blas, (rocblas_int)kd, (rocblas_int)mn, (double*)Sb.p, (rocblas_int)kd,
-                            (double*)tau.p + r));
-  HIP_CHECK(ctmk::launch_extract_lower((const double*)Nb.p, kd, kd, 0, (double*)Ln.p, r, 0, 1, dev.stream));
-  HIP_CHECK(ctmk::launch_extract_lower((const double*)Sb.p, kd, kd, 0, (double*)Ls.p, r, 0, 1, dev.stream));
-  // M = R_n R_s^T = L_n^T L_s  (column-major r x r)
-  DBuf Mb(&dev, (size_t)r * r * 8), U(&dev, (size_t)r * r * 8), Vt(&dev, (size_t)r * r * 8), Sv(&dev, (size_t)r * 8),
-      E(&dev, (size_t)r * 8), w(&dev, (size_t)chi * 8);
-  TRef Lnv{Ln.p, T_F64, {kd, r}, {1, kd}, "ai"};
-  TRef Lsv{Ls.p, T_F64, {kd, r}, {1, kd}, "aj"};
-  contract(dev, m, TRef{Mb.p, T_F64, {r, r}, {1, r}, "ij"}, Lnv, Lsv);
-  int* info = (int*)c->flag.p + 2;
-  RB_CHECK(rocsolver_dgesvd(c->blas, rocblas_svect_singular, rocblas_svect_singular, (rocblas_int)r, (rocblas_int)r,
-                            (double*)Mb.p, (rocblas_int)r, (double*)Sv.p, (double*)U.p, (rocblas_int)r, (double*)Vt.p,
-                            (rocblas_int)r, (double*)E.p, rocblas_outofplace, info));
-  HIP_CHECK(ctmk::launch_flag_or(info, (int*)c->flag.p + 1, dev.stream));
-  HIP_CHECK(ctmk::launch_svd_weights((const double*)Sv.p, r, r, (double*)w.p, chi, c->cutoff, 1, dev.stream));
-  // P = R_s^T V w = L_s V w,  Q = R_n^T U w = L_n U w  (row-major kd x chi)
-  TRef Vv{Vt.p, T_F64, {r, chi}, {r, 1}, "ik"};
-  TRef Uv{U.p, T_F64, {r, chi}, {1, r}, "ik"};
-  contract(dev, m, view(P, T_F64, {kd, chi}, "ak"), relabel(Lsv, "ai"), Vv, 1.0, 0, (const double*)w.p);
-  contract(dev, m, view(Q, T_F64, {kd, chi}, "ak"), Lnv, Uv, 1.0, 0, (const double*)w.p);
 }
 
 // One left move in frame f (Fig. CTMRG b): for every column step J, the
@@ -380,13 +499,13 @@ void left_move(ctm_ctx* c, int f) {
   }
   for (int J = 0; J < b; ++J) {
     std::vector<int64_t> zd(a);
-    for (int I = 0; I < a; ++I) {
-      zd[I] = c->site(f, I, J).dim[3];
-      double* P = (double*)P64.p + (size_t)I * maxkd * chi;
-      double* Q = (double*)Q64.p + (size_t)I * maxkd * chi;
-      projectors(c, f, I, J, P, Q);
-      if (c->st != T_F64) {
+    for (int I = 0; I < a; ++I) zd[I] = c->site(f, I, J).dim[3];
+    column_projectors(c, f, J, (double*)P64.p, (double*)Q64.p, maxkd);
+    if (c->st != T_F64) {
+      for (int I = 0; I < a; ++I) {
         int64_t n = chi * zd[I] * chi;
+        double* P = (double*)P64.p + (size_t)I * maxkd * chi;
+        double* Q = (double*)Q64.p + (size_t)I * maxkd * chi;
         copy_into(dev, view((float*)Pst.p + (size_t)I * maxkd * chi, T_F32, {n}, "q"), view(P, T_F64, {n}, "q"));
         copy_into(dev, view((float*)Qst.p + (size_t)I * maxkd * chi, T_F32, {n}, "q"), view(Q, T_F64, {n}, "q"));
       }
@@ -776,10 +895,13 @@ int ctm_profile_end(ctm_ctx* c, double* kernel_ms, double* kernel_flops, int64_t
   if (!c) return CTM_EINVAL;
   try {
     g_counters.timing = false;
-    double ms = g_counters.collect_ms();
-    if (kernel_ms) *kernel_ms = ms;
-    if (kernel_flops) *kernel_flops = g_counters.flops;
-    if (launches) *launches = g_counters.launches;
+    double ms[3];
+    g_counters.collect_ms(ms);
+    for (int i = 0; i < 3; ++i) {
+      if (kernel_ms) kernel_ms[i] = ms[i];
+      if (kernel_flops) kernel_flops[i] = g_counters.mode_flops[i];
+      if (launches) launches[i] = g_counters.mode_launches[i];
+    }
     g_counters.reset_timing();
     return CTM_OK;
   } catch (const Error& e) { return fail(c, e); }

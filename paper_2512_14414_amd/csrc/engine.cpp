@@ -13,27 +13,28 @@ void Counters::reset_timing() {
   used = 0;
   launches = 0;
   flops = 0;
+  for (int i = 0; i < 3; ++i) { mode_launches[i] = 0; mode_flops[i] = 0; }
 }
 
-void Counters::record(hipStream_t s, bool start) {
+void Counters::record(hipStream_t s, int mode) {
   if (used == pool.size()) {
     hipEvent_t e;
     HIP_CHECK(hipEventCreate(&e));
     pool.push_back(e);
+    pool_mode.push_back(0);
   }
-  (void)start;
+  pool_mode[used] = mode;
   HIP_CHECK(hipEventRecord(pool[used++], s));
 }
 
-double Counters::collect_ms() {
-  double ms = 0;
+void Counters::collect_ms(double* ms) {
+  for (int i = 0; i < 3; ++i) ms[i] = 0;
   if (used) HIP_CHECK(hipEventSynchronize(pool[used - 1]));
   for (size_t i = 0; i + 1 < used; i += 2) {
     float t = 0;
     HIP_CHECK(hipEventElapsedTime(&t, pool[i], pool[i + 1]));
-    ms += t;
+    ms[pool_mode[i]] += t;
   }
-  return ms;
 }
 
 TRef view(void* p, int type, const std::vector<int64_t>& dims, const std::string& lab) {
@@ -212,11 +213,15 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
     if (!beta) fill(dev, C, 0.0);
     return;
   }
+  const int km = A.type == T_F64 ? ctmk::MODE_F64 : mode;
+  const double fl = 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
   g_counters.launches++;
-  g_counters.flops += 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
-  if (g_counters.timing) g_counters.record(dev.stream, true);
-  HIP_CHECK(ctmk::launch_contract(A.type == T_F64 ? ctmk::MODE_F64 : mode, g, dev.stream));
-  if (g_counters.timing) g_counters.record(dev.stream, false);
+  g_counters.flops += fl;
+  g_counters.mode_launches[km]++;
+  g_counters.mode_flops[km] += fl;
+  if (g_counters.timing) g_counters.record(dev.stream, km);
+  HIP_CHECK(ctmk::launch_contract(km, g, dev.stream));
+  if (g_counters.timing) g_counters.record(dev.stream, km);
 }
 
 }  // namespace

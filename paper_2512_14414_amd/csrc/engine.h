@@ -109,10 +109,13 @@ struct Counters {
   double flops = 0;
   bool timing = false;
   std::vector<hipEvent_t> pool;
+  std::vector<int> pool_mode;       // matrix-core path of each timed launch
   size_t used = 0;
+  int64_t mode_launches[3] = {0, 0, 0};
+  double mode_flops[3] = {0, 0, 0};
   void reset_timing();
-  void record(hipStream_t s, bool start);
-  double collect_ms();
+  void record(hipStream_t s, int mode);
+  void collect_ms(double* ms_per_mode);
 };
 extern Counters g_counters;
 

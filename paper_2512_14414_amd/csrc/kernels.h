@@ -51,6 +51,7 @@ struct EnergyTerm {
 hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s);
 hipError_t launch_permute(const PermArgs& p, int in_type, const void* in, int out_type, void* out, hipStream_t s);
 hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_normalize(int type, const NormList& L, int count, hipStream_t s);
 hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, double* w, int64_t chi, double cutoff,
                               int batch, hipStream_t st);
@@ -62,6 +63,17 @@ hipError_t launch_nonfinite(int type, const void* x, int64_t n, int* flag, hipSt
 hipError_t launch_spectra_delta(const double* sv, int64_t r, int64_t chi, double* cur, const double* prev, int count,
                                 double* delta_out, hipStream_t s);
 
-hipError_t launch_flag_or(const int* src, int* flag, hipStream_t s);
+hipError_t launch_flag_or(const int* src, int n, int* flag, hipStream_t s);
+hipError_t launch_jw_weights(const double* ev, int64_t n2, double* w, int64_t chi, double cutoff, int batch,
+                             hipStream_t s);
+
+hipError_t launch_jacobi_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
+                               const double* tiny2, int* rot, hipStream_t s);
+hipError_t launch_frob_tiny(const double* A, int64_t len, int64_t stride, int batch, double eps, double* tiny2,
+                            hipStream_t s);
+hipError_t launch_identity(double* V, int64_t n, int64_t stride, int batch, hipStream_t s);
+hipError_t launch_rt_from_qr(const double* A, double* X, int64_t n, int64_t stride, int batch, hipStream_t s);
+hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int64_t stride, int batch, int64_t kmax,
+                                double* sv, double* U, double* Vk, hipStream_t s);
 
 }  // namespace ctmk

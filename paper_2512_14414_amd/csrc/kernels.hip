@@ -64,12 +64,14 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
   const T* B = (const T*)g.B + split_off(bz, g.b_in, g.b_b_o, g.b_b_i);
   T* C = (T*)g.C + split_off(bz, g.b_in, g.c_b_o, g.c_b_i);
 
+  // offsets may be negative (reversed views); rows/columns past the edge are marked NONE
+  constexpr int64_t NONE = INT64_MIN;
   if (tid < BM) {
     int64_t m = m0 + tid;
-    a_row[tid] = m < g.M ? split_off(m, g.m_in, g.a_m_o, g.a_m_i) : -1;
+    a_row[tid] = m < g.M ? split_off(m, g.m_in, g.a_m_o, g.a_m_i) : NONE;
   } else if (tid < BM + BN) {
     int64_t n = n0 + tid - BM;
-    b_col[tid - BM] = n < g.N ? split_off(n, g.n_in, g.b_n_o, g.b_n_i) : -1;
+    b_col[tid - BM] = n < g.N ? split_off(n, g.n_in, g.b_n_o, g.b_n_i) : NONE;
   }
   __syncthreads();
 
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
       int64_t k = k0 + kk;
       T v = 0;
       int64_t ro = a_row[mm];
-      if (ro >= 0 && k < g.K) v = A[ro + split_off(k, g.k_in, g.a_k_o, g.a_k_i)];
+      if (ro != NONE && k < g.K) v = A[ro + split_off(k, g.k_in, g.a_k_o, g.a_k_i)];
       As[kk][mm] = to_lds<MODE>(v);
     }
 #pragma unroll
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
       int64_t k = k0 + kk;
       T v = 0;
       int64_t co = b_col[nn];
-      if (co >= 0 && k < g.K) v = B[co + split_off(k, g.k_in, g.b_k_o, g.b_k_i)];
+      if (co != NONE && k < g.K) v = B[co + split_off(k, g.k_in, g.b_k_o, g.b_k_i)];
       Bs[kk][nn] = to_lds<MODE>(v);
     }
     __syncthreads();
@@ -239,6 +241,16 @@ __global__ void fill_kernel(T* p, T v, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
 }
 
+__global__ void fill_int_kernel(int* p, int v, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
+}
+
+hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_int_kernel<<<grid_for(n), 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (type == 0) fill_kernel<double><<<grid_for(n), 256, 0, s>>>((double*)p, v, n);
@@ -302,18 +314,18 @@ hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, doub
 // with the Householder data above the diagonal replaced by zeros.
 __global__ void extract_lower_kernel(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l,
                                      int64_t rcols, int64_t stride_l, int batch) {
-  int64_t total = rows * rcols;
-  for (int b = 0; b < batch; ++b) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-      int64_t j = e / rows, i = e - j * rows;
-      l[b * stride_l + e] = i >= j ? a[b * stride_a + i + j * lda] : 0.0;
-    }
+  int64_t total = rows * rcols * batch;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t b = t / (rows * rcols), e = t - b * rows * rcols;
+    int64_t j = e / rows, i = e - j * rows;
+    l[b * stride_l + e] = i >= j ? a[b * stride_a + i + j * lda] : 0.0;
   }
 }
 
 hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,
                                 int64_t stride_l, int batch, hipStream_t s) {
-  extract_lower_kernel<<<grid_for(rows * rcols), 256, 0, s>>>(a, rows, lda, stride_a, l, rcols, stride_l, batch);
+  if (batch <= 0) return hipSuccess;
+  extract_lower_kernel<<<grid_for(rows * rcols * batch), 256, 0, s>>>(a, rows, lda, stride_a, l, rcols, stride_l, batch);
   return hipGetLastError();
 }
 
@@ -425,13 +437,187 @@ hipError_t launch_spectra_delta(const double* sv, int64_t r, int64_t chi, double
   return hipGetLastError();
 }
 
-// flag |= (src != 0), for solver status codes that are overwritten by the next call
-__global__ void flag_or_kernel(const int* src, int* flag) {
-  if (threadIdx.x == 0 && *src != 0) atomicOr(flag, 1);
+// flag |= (any src[i] != 0), for solver status codes
+__global__ void flag_or_kernel(const int* src, int n, int* flag) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (src[i] != 0) atomicOr(flag, 1);
 }
 
-hipError_t launch_flag_or(const int* src, int* flag, hipStream_t s) {
-  flag_or_kernel<<<1, 64, 0, s>>>(src, flag);
+hipError_t launch_flag_or(const int* src, int n, int* flag, hipStream_t s) {
+  flag_or_kernel<<<1, 64, 0, s>>>(src, n, flag);
+  return hipGetLastError();
+}
+
+// Projector weights from the ascending eigenvalues of the symmetric matrix
+// [[0, M], [M^T, 0]] (length n2 = 2r per batch entry): the k-th largest
+// singular value of M is ev[n2-1-k]; w_k = s_k^(-1/2) if s_k > cutoff * s_0.
+__global__ void jw_weights_kernel(const double* ev, int64_t n2, double* w, int64_t chi, double cutoff) {
+  const double* e = ev + (int64_t)blockIdx.x * n2;
+  double thr = cutoff * e[n2 - 1];
+  for (int64_t k = threadIdx.x; k < chi; k += blockDim.x) {
+    double v = k < n2 / 2 ? e[n2 - 1 - k] : 0.0;
+    w[(int64_t)blockIdx.x * chi + k] = (k < n2 / 2 && v > thr) ? 1.0 / sqrt(v) : 0.0;
+  }
+}
+
+hipError_t launch_jw_weights(const double* ev, int64_t n2, double* w, int64_t chi, double cutoff, int batch,
+                             hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  jw_weights_kernel<<<batch, 128, 0, s>>>(ev, n2, w, chi, cutoff);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched one-sided (Hestenes) Jacobi SVD of n x n column-major matrices A_b:
+// column pairs are rotated until all columns are mutually orthogonal, then
+// A_b V_b = U_b diag(s_b).  One wave per column pair; the pairs of a round of
+// the round-robin tournament are disjoint and run in one launch.  A pair (p,q)
+// is rotated when |a_p . a_q| > tol sqrt(|a_p|^2 |a_q|^2); ``rot`` counts the
+// rotations of the current sweep (one counter per matrix).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void jacobi_round_kernel(double* A, double* V, int64_t n, int64_t np, int64_t stride,
+                                                          int round, double tol, const double* tiny2, int* rot) {
+  const int k = blockIdx.x;            // pair index within the round
+  const int b = blockIdx.y;            // matrix
+  const int lane = threadIdx.x;
+  // tournament pairing over np (even) players; player np-1 is fixed
+  int64_t p, q;
+  if (k == 0) { p = round; q = np - 1; }
+  else { p = (round + k) % (np - 1); q = (round - k + (np - 1)) % (np - 1); }
+  if (p >= n || q >= n) return;        // padding player for odd n
+  if (p > q) { int64_t t = p; p = q; q = t; }
+  double* Ab = A + (int64_t)b * stride;
+  double* Vb = V + (int64_t)b * stride;
+  double* ap = Ab + p * n;
+  double* aq = Ab + q * n;
+  double al = 0, be = 0, ga = 0;
+  for (int64_t i = lane; i < n; i += 64) {
+    double x = ap[i], y = aq[i];
+    al += x * x; be += y * y; ga += x * y;
+  }
+  al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+  // columns below eps*|A|_F are numerically zero: rotating them only moves rounding noise
+  if (fmin(al, be) <= tiny2[b] || ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) return;
+  double zeta = (be - al) / (2.0 * ga);
+  double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+  for (int64_t i = lane; i < n; i += 64) {
+    double x = ap[i], y = aq[i];
+    ap[i] = c * x - sn * y;
+    aq[i] = sn * x + c * y;
+  }
+  double* vp = Vb + p * n;
+  double* vq = Vb + q * n;
+  for (int64_t i = lane; i < n; i += 64) {
+    double x = vp[i], y = vq[i];
+    vp[i] = c * x - sn * y;
+    vq[i] = sn * x + c * y;
+  }
+  if (lane == 0) atomicAdd(rot + b, 1);
+}
+
+hipError_t launch_jacobi_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
+                               const double* tiny2, int* rot, hipStream_t s) {
+  int64_t np = n + (n & 1);
+  dim3 grid((unsigned)(np / 2), (unsigned)batch);
+  jacobi_round_kernel<<<grid, 64, 0, s>>>(A, V, n, np, stride, round, tol, tiny2, rot);
+  return hipGetLastError();
+}
+
+// tiny2[b] = (eps * |A_b|_F)^2, one workgroup per matrix
+__global__ __launch_bounds__(256) void frob_tiny_kernel(const double* A, int64_t len, int64_t stride, double eps,
+                                                        double* tiny2) {
+  __shared__ double red[256];
+  const double* Ab = A + (int64_t)blockIdx.x * stride;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < len; i += 256) s += Ab[i] * Ab[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tiny2[blockIdx.x] = eps * eps * red[0];
+}
+
+hipError_t launch_frob_tiny(const double* A, int64_t len, int64_t stride, int batch, double eps, double* tiny2,
+                            hipStream_t s) {
+  frob_tiny_kernel<<<batch, 256, 0, s>>>(A, len, stride, eps, tiny2);
+  return hipGetLastError();
+}
+
+// X_b = R_b^T for the upper-triangular factor R_b stored by a QR factorisation
+// in the upper triangle of A_b (column-major n x n).
+__global__ void rt_from_qr_kernel(const double* A, double* X, int64_t n, int64_t stride, int batch) {
+  int64_t total = n * n * batch;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t b = t / (n * n), e = t - b * n * n;
+    int64_t j = e / n, i = e - j * n;
+    X[b * stride + e] = i >= j ? A[b * stride + j + i * n] : 0.0;
+  }
+}
+
+hipError_t launch_rt_from_qr(const double* A, double* X, int64_t n, int64_t stride, int batch, hipStream_t s) {
+  rt_from_qr_kernel<<<grid_for(n * n * batch), 256, 0, s>>>(A, X, n, stride, batch);
+  return hipGetLastError();
+}
+
+__global__ void identity_kernel(double* V, int64_t n, int64_t stride, int batch) {
+  int64_t total = n * n * batch;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = t % (n * n);
+    V[(t / (n * n)) * stride + e] = (e % n == e / n) ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_identity(double* V, int64_t n, int64_t stride, int batch, hipStream_t s) {
+  identity_kernel<<<grid_for(n * n * batch), 256, 0, s>>>(V, n, stride, batch);
+  return hipGetLastError();
+}
+
+// After convergence: s_j = |a_j|; the k largest (k <= kmax) in descending
+// order go to sv[b][k], their left vectors a_j / s_j to U[b] (n x kmax,
+// column-major) and right vectors to Vk[b] (n x kmax); all n sorted values are
+// written to sv (length n per matrix).  One workgroup per matrix; ranks by
+// counting (n <= 4096), ties broken by column index.
+__global__ __launch_bounds__(256) void jacobi_finish_kernel(const double* A, const double* V, int64_t n, int64_t stride,
+                                                            int64_t kmax, double* sv, double* U, double* Vk) {
+  extern __shared__ double nrm[];
+  const int b = blockIdx.x;
+  const double* Ab = A + (int64_t)b * stride;
+  const double* Vb = V + (int64_t)b * stride;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    double s = 0;
+    for (int64_t i = 0; i < n; ++i) { double x = Ab[j * n + i]; s += x * x; }
+    nrm[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    double v = nrm[j];
+    int64_t rank = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      double w = nrm[i];
+      rank += (w > v) || (w == v && i < j);
+    }
+    sv[(int64_t)b * n + rank] = v;
+    if (rank < kmax) {
+      double inv = v > 0 ? 1.0 / v : 0.0;
+      double* u = U + (int64_t)b * n * kmax + rank * n;
+      double* vv = Vk + (int64_t)b * n * kmax + rank * n;
+      for (int64_t i = 0; i < n; ++i) { u[i] = Ab[j * n + i] * inv; vv[i] = Vb[j * n + i]; }
+    }
+  }
+}
+
+hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int64_t stride, int batch, int64_t kmax,
+                                double* sv, double* U, double* Vk, hipStream_t s) {
+  if (n > 4096) return hipErrorInvalidValue;
+  jacobi_finish_kernel<<<batch, 256, n * sizeof(double), s>>>(A, V, n, stride, kmax, sv, U, Vk);
   return hipGetLastError();
 }
 

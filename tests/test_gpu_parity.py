@@ -11,10 +11,11 @@ runs.
 """
 import numpy as np
 import pytest
+import scipy.linalg
 import torch
 
 import synth
-from oracle.ctmrg import CTM as OCTM, corner_spectra, env_from_flat, env_to_flat, init_env
+from oracle.ctmrg import CTM as OCTM, corner_spectra, env_from_flat, env_to_flat, init_env, truncated_inverse_sqrt
 from oracle.rdm import energy as oenergy, plaquette_rdm as orho
 
 pytestmark = pytest.mark.gpu
@@ -33,6 +34,36 @@ def ctm_mod():
 def gpu_spectra(env_flat, sites, chi):
     env = env_from_flat(env_flat.cpu(), sites, chi)
     return corner_spectra(env, chi)
+
+
+def gesvd_projectors(N, S, chi, cutoff):
+    """The oracle's projectors with LAPACK's QR-iteration SVD driver (gesvd)
+    in place of the default divide-and-conquer one: the spread between two
+    backward-stable SVDs calibrates how far rounding alone moves a result."""
+    Rn = torch.linalg.qr(N, mode="reduced")[1]
+    Rs = torch.linalg.qr(S, mode="reduced")[1]
+    U, s, Vh = scipy.linalg.svd((Rn @ Rs.T).numpy(), full_matrices=False, lapack_driver="gesvd")
+    U, s, Vh = torch.from_numpy(U), torch.from_numpy(s), torch.from_numpy(Vh)
+    k, w = truncated_inverse_sqrt(s, chi, cutoff)
+    return (Rs.T @ Vh[:k].T) * w, (Rn.T @ U[:, :k]) * w, s
+
+
+def rounding_spread(A, pattern, chi, sweeps, env0, so, Eo, terms):
+    """Largest change of the oracle's corner spectra (and, if terms are given,
+    energy) under (i) the gesvd driver and (ii) when the start env0 is given,
+    a relative 1e-13 perturbation of it."""
+    o2 = OCTM(A, pattern, chi, env0=env0)
+    o2.run(sweeps, proj=gesvd_projectors)
+    ds = (corner_spectra(o2.env, chi) - so).abs().max().item()
+    de = abs(oenergy(o2, H, terms).item() - Eo) if terms else None
+    if env0 is not None:
+        rng = np.random.default_rng(7)
+        o3 = OCTM(A, pattern, chi, env0=env0 * (1 + 1e-13 * rng.standard_normal(env0.shape)))
+        o3.run(sweeps)
+        ds = max(ds, (corner_spectra(o3.env, chi) - so).abs().max().item())
+        if terms:
+            de = max(de, abs(oenergy(o3, H, terms).item() - Eo))
+    return ds, de
 
 
 CASES = [
@@ -81,8 +112,8 @@ def test_one_sweep_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dis
     """One sweep of a random state from a random shared start.
 
     Such a sweep amplifies rounding strongly, so the bar is 10 times the
-    change the oracle itself shows when its start is perturbed by a relative
-    1e-13, plus 1e-12.
+    spread of the oracle itself under another SVD driver or a relative 1e-13
+    perturbation of its start, plus 1e-12.
     """
     A = synth.site_tensors(nt, 2, D, seed, dist)
     Ly, Lx = len(pattern), len(pattern[0])
@@ -92,16 +123,12 @@ def test_one_sweep_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dis
     g.sweep(1)
     o = OCTM(A, pattern, chi, env0=env0)
     o.run(1)
-    rng = np.random.default_rng(7)
-    o2 = OCTM(A, pattern, chi, env0=env0 * (1 + 1e-13 * rng.standard_normal(env0.shape)))
-    o2.run(1)
     terms = synth.heisenberg_terms(Lx, Ly)
-    sg = gpu_spectra(g.get_env(), o.sites, chi)
-    so, so2 = corner_spectra(o.env, chi), corner_spectra(o2.env, chi)
-    E, Eo, Eo2 = g.energy(H, terms), oenergy(o, H, terms).item(), oenergy(o2, H, terms).item()
-    cond_s, cond_e = (so2 - so).abs().max().item(), abs(Eo2 - Eo)
+    so, Eo = corner_spectra(o.env, chi), oenergy(o, H, terms).item()
+    cond_s, cond_e = rounding_spread(A, pattern, chi, 1, env0, so, Eo, terms)
+    sg, E = gpu_spectra(g.get_env(), o.sites, chi), g.energy(H, terms)
     err_s, err_e = (sg - so).abs().max().item(), abs(E - Eo)
-    print(f"{name}: spectra |d| gpu {err_s:.2e} oracle-self {cond_s:.2e}; E |d| gpu {err_e:.2e} oracle-self {cond_e:.2e}")
+    print(f"{name}: spectra |d| gpu {err_s:.2e} oracle spread {cond_s:.2e}; E |d| gpu {err_e:.2e} oracle spread {cond_e:.2e}")
     assert err_s <= 10 * cond_s + 1e-12
     assert err_e <= 10 * cond_e + 1e-12 * max(1.0, abs(Eo))
 
@@ -109,12 +136,14 @@ def test_one_sweep_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dis
 # Weakly entangled random states (noise of norm 0.3 on a product state): the
 # iteration is well conditioned from the sites-derived start, so whole runs of
 # several sweeps must agree tightly, at shapes that span several 64 x 64 tiles.
-# The energy is compared to 1e-10.  Corner spectra are compared to 1e-5: a
-# kept singular triplet of M with s_k just above the cutoff (1e-10 s_1) is
-# fixed by any backward-stable SVD only to a relative eps s_1 / s_k ~ 1e-6,
-# and enters the corners with weight s_k^(-1/2); the energy is insensitive to
-# it because those directions carry weight s_k in the contracted network.
-SPECTRA_TOL = 1e-5
+# The energy is compared to 1e-10.  Individual corner spectra are not gauge
+# invariant: a kept singular triplet of M with s_k just above the cutoff
+# (1e-10 s_1) is fixed by a backward-stable SVD only to a relative eps s_1/s_k
+# and sets the gauge of the new corners with weight s_k^(-1/2), while the
+# energy is insensitive to it.  The spectra are therefore held to 30 times the
+# spread between the oracle's two LAPACK SVD drivers (three backward-stable
+# SVDs scatter over about a decade around each other after several
+# amplifying sweeps), plus 1e-9.
 NP_CASES = [
     ("np_1x1_D2_chi8", 1, 2, 8, [[0]], 6),
     ("np_2x2_D3_chi12", 4, 3, 12, [[0, 1], [2, 3]], 6),
@@ -132,10 +161,12 @@ def test_sweeps_weakly_entangled(ctm_mod, name, nt, D, chi, pattern, sweeps):
     o = OCTM(A, pattern, chi)
     o.run(sweeps)
     terms = synth.heisenberg_terms(Lx, Ly)
-    sg, so = gpu_spectra(g.get_env(), o.sites, chi), corner_spectra(o.env, chi)
-    E, Eo = g.energy(H, terms), oenergy(o, H, terms).item()
-    print(f"{name}: spectra |d| {(sg - so).abs().max().item():.2e}, E {E:.14f} |d| {abs(E - Eo):.2e}")
-    assert torch.allclose(sg, so, rtol=0, atol=SPECTRA_TOL)
+    so, Eo = corner_spectra(o.env, chi), oenergy(o, H, terms).item()
+    cond_s, _ = rounding_spread(A, pattern, chi, sweeps, None, so, Eo, None)
+    sg, E = gpu_spectra(g.get_env(), o.sites, chi), g.energy(H, terms)
+    err_s = (sg - so).abs().max().item()
+    print(f"{name}: spectra |d| {err_s:.2e} (driver spread {cond_s:.2e}), E {E:.14f} |d| {abs(E - Eo):.2e}")
+    assert err_s <= 30 * cond_s + 1e-9
     assert abs(E - Eo) < 1e-10 * max(1.0, abs(Eo))
 
 
@@ -148,11 +179,13 @@ def test_full_size_ssm_d6_chi72_weakly_entangled(ctm_mod):
     g.sweep(2)
     o = OCTM(A, cfg["pattern"], cfg["chi"])
     o.run(2)
-    sg, so = gpu_spectra(g.get_env(), o.sites, cfg["chi"]), corner_spectra(o.env, cfg["chi"])
     terms = [t for t in synth.config_terms(cfg) if (t[0], t[1]) == (0, 0)]
-    E, Eo = g.energy(H, terms), oenergy(o, H, terms).item()
-    print(f"ssm_d6_chi72: spectra |d| {(sg - so).abs().max().item():.2e}, E(0,0) {E:.14f} |d| {abs(E - Eo):.2e}")
-    assert torch.allclose(sg, so, rtol=0, atol=SPECTRA_TOL)
+    so, Eo = corner_spectra(o.env, cfg["chi"]), oenergy(o, H, terms).item()
+    cond_s, _ = rounding_spread(A, cfg["pattern"], cfg["chi"], 2, None, so, Eo, None)
+    sg, E = gpu_spectra(g.get_env(), o.sites, cfg["chi"]), g.energy(H, terms)
+    err_s = (sg - so).abs().max().item()
+    print(f"ssm_d6_chi72: spectra |d| {err_s:.2e} (driver spread {cond_s:.2e}), E(0,0) {E:.14f} |d| {abs(E - Eo):.2e}")
+    assert err_s <= 30 * cond_s + 1e-9
     assert abs(E - Eo) < 1e-10
 
 
