@@ -64,8 +64,6 @@ hipError_t launch_spectra_delta(const double* sv, int64_t r, int64_t chi, double
                                 double* delta_out, hipStream_t s);
 
 hipError_t launch_flag_or(const int* src, int n, int* flag, hipStream_t s);
-hipError_t launch_jw_weights(const double* ev, int64_t n2, double* w, int64_t chi, double cutoff, int batch,
-                             hipStream_t s);
 
 hipError_t launch_jacobi_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
                                const double* tiny2, int* rot, hipStream_t s);

@@ -448,25 +448,6 @@ hipError_t launch_flag_or(const int* src, int n, int* flag, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Projector weights from the ascending eigenvalues of the symmetric matrix
-// [[0, M], [M^T, 0]] (length n2 = 2r per batch entry): the k-th largest
-// singular value of M is ev[n2-1-k]; w_k = s_k^(-1/2) if s_k > cutoff * s_0.
-__global__ void jw_weights_kernel(const double* ev, int64_t n2, double* w, int64_t chi, double cutoff) {
-  const double* e = ev + (int64_t)blockIdx.x * n2;
-  double thr = cutoff * e[n2 - 1];
-  for (int64_t k = threadIdx.x; k < chi; k += blockDim.x) {
-    double v = k < n2 / 2 ? e[n2 - 1 - k] : 0.0;
-    w[(int64_t)blockIdx.x * chi + k] = (k < n2 / 2 && v > thr) ? 1.0 / sqrt(v) : 0.0;
-  }
-}
-
-hipError_t launch_jw_weights(const double* ev, int64_t n2, double* w, int64_t chi, double cutoff, int batch,
-                             hipStream_t s) {
-  if (batch <= 0) return hipSuccess;
-  jw_weights_kernel<<<batch, 128, 0, s>>>(ev, n2, w, chi, cutoff);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // Batched one-sided (Hestenes) Jacobi SVD of n x n column-major matrices A_b:
 // column pairs are rotated until all columns are mutually orthogonal, then
