@@ -46,7 +46,10 @@ def svd_backward(U, s, V, Ub, sb, Vb, eta, inv_mask):
     s2 = s * s
     Dl = s2[None, :] - s2[:, None]                     # s_j^2 - s_i^2
     scale = torch.maximum(s2[None, :], s2[:, None])
-    F = Dl / (Dl * Dl + (eta * scale) ** 2)
+    den = Dl * Dl + (eta * scale) ** 2
+    # the broadened 1/D is D/(D^2 + width^2), which is 0 at D = 0 (also when
+    # both singular values vanish and the width with them)
+    F = torch.where(den > 0, Dl / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(den))
     F.fill_diagonal_(0.0)
     UtUb = U.T @ Ub
     VtVb = V.T @ Vb
