@@ -116,6 +116,23 @@ int ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done, double
  * H_bond and terms are host arrays; E (host) receives the result. */
 int ctm_energy(ctm_ctx* ctx, const double* H_bond, int n_terms, const ctm_term* terms, double* E);
 
+/* Energy and its gradient (Eq. AD): E(A) = energy per site after n_sweeps
+ * sweeps started from the context's current environment, which is held
+ * constant (the shortened derivative chain of Sec. IV: from a given, ideally
+ * converged, environment).  If A (device, as in ctm_init) is not NULL it
+ * replaces the site tensors first.  dEdA (device, n_tensors*d*D^4 float64)
+ * receives dE/dA in the layout of A.  The derivative of every step is
+ * hand-written: contractions by their transposed contractions, the
+ * normalisations, the plaquette density matrices and the projectors, whose
+ * SVD derivative uses the Lorentzian-broadened F_ij = D/(D^2 + (eta m)^2),
+ * D = s_j^2 - s_i^2, m = max(s_i^2, s_j^2) (option "lorentz_eta").
+ * Checkpointing: one environment snapshot per sweep is kept and each sweep is
+ * recomputed once during the reverse pass.  Afterwards the environment is
+ * the one reached by the n_sweeps sweeps.  H_bond, terms as in ctm_energy;
+ * E (host) receives the energy. */
+int ctm_energy_grad(ctm_ctx* ctx, const double* A, int n_sweeps, const double* H_bond, int n_terms,
+                    const ctm_term* terms, double* E, double* dEdA);
+
 /* Plaquette density matrices of the last ctm_energy call, copied to a host
  * buffer of n * d^8 float64 values in the order of first appearance of the
  * plaquettes in the term list; n (host) receives the count. */

@@ -4,3 +4,4 @@ The computation lives in libctm.so (HIP kernels for gfx950, C ABI in
 include/ctm.h); ``CTM`` is its thin Python binding.
 """
 from .binding import CTM, CTMError, EXPORTED, LIB, LIB_PATH, PRECISIONS  # noqa: F401
+from .autograd import CTMEnergy  # noqa: F401

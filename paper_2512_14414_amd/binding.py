@@ -43,6 +43,7 @@ def _load():
         "ctm_get_env": (I, [P, P]),
         "ctm_sweep": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
         "ctm_energy": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D)]),
+        "ctm_energy_grad": (I, [P, P, I, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D), P]),
         "ctm_last_rdms": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
         "ctm_set_option": (I, [P, ctypes.c_char_p, D]),
         "ctm_profile_begin": (I, [P]),
@@ -58,7 +59,7 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("ctm_init", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
-            "ctm_sweep", "ctm_energy", "ctm_last_rdms", "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
+            "ctm_sweep", "ctm_energy", "ctm_energy_grad", "ctm_last_rdms", "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
             "ctm_last_error", "ctm_free")
 
 
@@ -67,6 +68,11 @@ def _terms(terms):
     for i, (px, py, a, b, coef) in enumerate(terms):
         arr[i] = Term(px, py, a, b, coef)
     return arr
+
+
+def _hbond(H):
+    vals = torch.as_tensor(H, dtype=torch.float64).reshape(-1).tolist()
+    return (ctypes.c_double * len(vals))(*[float(v) for v in vals])
 
 
 def _dptr(t: torch.Tensor, dtype=torch.float64):
@@ -139,10 +145,24 @@ class CTM:
         return n.value, dl.value, rc == CTM_OK
 
     def energy(self, H, terms):
-        H = (ctypes.c_double * 16)(*[float(v) for v in torch.as_tensor(H, dtype=torch.float64).reshape(-1).tolist()])
         E = ctypes.c_double()
-        self._check(LIB.ctm_energy(self._h, H, len(terms), _terms(terms), ctypes.byref(E)))
+        self._check(LIB.ctm_energy(self._h, _hbond(H), len(terms), _terms(terms), ctypes.byref(E)))
         return E.value
+
+    def energy_grad(self, n_sweeps, H, terms, A=None):
+        """(E, dE/dA) after ``n_sweeps`` sweeps from the current environment (held constant).
+
+        If A is given it replaces the site tensors first.  The environment is
+        left at the result of the sweeps."""
+        aptr = None
+        if A is not None:
+            self.A = torch.as_tensor(A, dtype=torch.float64).to(self.A.device).contiguous()
+            aptr = _dptr(self.A)
+        g = torch.empty_like(self.A)
+        E = ctypes.c_double()
+        self._check(LIB.ctm_energy_grad(self._h, aptr, int(n_sweeps), _hbond(H), len(terms), _terms(terms),
+                                        ctypes.byref(E), _dptr(g)))
+        return E.value, g
 
     def last_rdms(self, capacity=16):
         d8 = self.d ** 8

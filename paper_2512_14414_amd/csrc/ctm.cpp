@@ -84,6 +84,11 @@ struct ctm_ctx {
   int n_rdm = 0;
   DBuf flag;                      // int flags: [0] non-finite, [1..] solver info
   std::string err;
+  // Current storage of every environment tensor (position-major, 8 slots):
+  // normally views of ``env``; while a tape records, every update goes to a
+  // fresh buffer so that the values read before stay intact for the reverse pass.
+  std::vector<void*> slot_ptr;
+  Tape tape;
 
   int ny(int f) const { return (f & 1) ? NX : NY; }
   int nx(int f) const { return (f & 1) ? NY : NX; }
@@ -124,9 +129,32 @@ struct ctm_ctx {
     to_orig(f, I, J, oi, oj);
     int ok = ((k & 3) + f) % 4 + (k & 4);
     size_t idx = ((size_t)oi * NX + oj) * 8 + ok;
-    char* base = (char*)env.p + slot_off[idx] * type_size(st);
+    char* base = (char*)slot_ptr[idx];
     if (k < 4) return view(base, st, {chi, chi}, lab);
     return view(base, st, {chi, slot_leg[idx], chi}, lab);
+  }
+  size_t slot_index(int f, int I, int J, int k) const {
+    int a = ny(f), b = nx(f);
+    I = ((I % a) + a) % a; J = ((J % b) + b) % b;
+    int oi, oj;
+    to_orig(f, I, J, oi, oj);
+    return ((size_t)oi * NX + oj) * 8 + ((k & 3) + f) % 4 + (k & 4);
+  }
+  int64_t slot_elems(size_t idx) const { return idx % 8 < 4 ? (int64_t)chi * chi : (int64_t)chi * slot_leg[idx] * chi; }
+  void reset_slot_ptrs() {
+    slot_ptr.resize(slot_off.size());
+    for (size_t i = 0; i < slot_off.size(); ++i) slot_ptr[i] = (char*)env.p + slot_off[i] * type_size(st);
+  }
+  // Destination of an updated environment tensor: in place, or a fresh
+  // buffer while the tape records.
+  TRef out_slot(int f, int I, int J, int k, const std::string& lab) {
+    if (tape.recording()) {
+      size_t idx = slot_index(f, I, J, k);
+      void* p = dev.alloc((size_t)slot_elems(idx) * type_size(st));
+      tape.retained.push_back(p);
+      slot_ptr[idx] = p;
+    }
+    return slot(f, I, J, k, lab);
   }
 };
 
@@ -386,23 +414,38 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
 // float64, written to P64/Q64 + I*maxkd*chi as [(chi-leg, site-leg), chi]
 // matrices (the site leg is the down leg of (I, J)).
 //
-// Rows of equal parity have equal shapes and are handled together.  With
-// N, S of shape mn x kd (rows: right cut, columns: left cut a5a6):
-//  * mn > kd (tall): N^T = L_n Q_n and S^T = L_s Q_s (LQ of the column-major
-//    views, i.e. R = L^T of Eq. QRSVD), M = R_n R_s^T = L_n^T L_s;
-//    P = R_s^T V w = L_s V w, Q = R_n^T U w = L_n U w;
-//  * mn <= kd: the QR would not shrink anything, and rho = N S^T (mn x mn)
-//    has the same singular values as R_n R_s^T with U_rho = Q_n U,
-//    V_rho = Q_s V, so M = rho and P = S^T V_rho w, Q = N^T U_rho w (the
-//    same products as above, since N^T stored row-major is exactly a
-//    column-major kd x mn matrix like L_n).
-// In both cases M is r x r with r = chi*D, and w_k = s_k^(-1/2) for the chi
-// largest s_k above cutoff * s_1 (zero otherwise).
+// Rows of equal parity have equal shapes and are handled together.  N and S
+// are mn x kd (rows: right cut, columns: left cut a5a6), stored row-major, so
+// that the same memory is the column-major kd x mn matrix N^T.  Its LQ
+// factorisation N^T = L_n Q_n gives R_n = L_n^T of Eq. QRSVD (kd x r lower
+// trapezoidal L_n, r = min(kd, mn) = chi*D); then M = R_n R_s^T = L_n^T L_s,
+// M = U diag(s) V^T, P = R_s^T V w = L_s V w and Q = R_n^T U w = L_n U w with
+// w_k = s_k^(-1/2) for the chi largest s_k above cutoff * s_1 (zero
+// otherwise).  The QR is taken also when N is not tall: forming N S^T
+// directly loses the accuracy of the small kept singular values that the
+// triangular factors preserve.
+//
+// While the tape records, all r singular triplets are kept together with the
+// singular vectors of rho = N S^T (U_rho = Q_n^T-applied U, V_rho likewise)
+// and the derivative of the block (N, S) -> (P, Q) is recorded (see
+// proj_backward).
+struct ProjRow {
+  int64_t kd = 0, mn = 0;
+  std::shared_ptr<DBuf> N, S, Ur, Vr, s, w;   // N, S row-major mn x kd; Ur, Vr column-major mn x r
+  void* Nadj = nullptr;                        // forward address of N and S (their adjoints are looked up)
+  void* Sadj = nullptr;
+  double* P = nullptr;                         // forward address of P_I and Q_I (kd x chi row-major)
+  double* Q = nullptr;
+};
+
+void proj_backward(ctm_ctx* c, const ProjRow& R, int64_t r);
+
 void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64_t maxkd) {
   Dev& dev = c->dev;
   const int a = c->ny(f);
   const int64_t chi = c->chi;
   const int m = c->mode;
+  const bool rec = c->tape.recording();
   int64_t kd[2] = {0, 0}, mn[2] = {0, 0};
   int cnt[2] = {0, 0};
   for (int I = 0; I < a; ++I) {
@@ -414,7 +457,7 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
   const int64_t r = std::min(kd[0], mn[0]);
   for (int p = 0; p < 2; ++p)
     if (cnt[p] && std::min(kd[p], mn[p]) != r) throw Error(CTM_EINVAL, "rows of a column step differ in rank bound");
-  DBuf Nb[2], Sb[2], Ln[2], Ls[2], tau[2];
+  DBuf Nb[2], Sb[2];
   for (int p = 0; p < 2; ++p) {
     if (!cnt[p]) continue;
     Nb[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * mn[p] * 8);
@@ -424,18 +467,31 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     int p = I & 1, b = I >> 1;
     half_systems(c, f, I, J, (double*)Nb[p].p + (size_t)b * kd[p] * mn[p], (double*)Sb[p].p + (size_t)b * kd[p] * mn[p]);
   }
-  DBuf Mb(&dev, (size_t)a * r * r * 8), sv(&dev, (size_t)a * r * 8), Uk(&dev, (size_t)a * r * chi * 8),
-      Vk(&dev, (size_t)a * r * chi * 8), w(&dev, (size_t)a * chi * 8);
-  const double* Lf[2] = {nullptr, nullptr};   // column-major kd x r left factors (Q side)
-  const double* Rf[2] = {nullptr, nullptr};   // right factors (P side)
+  TapePause pause(dev);   // the block below is one recorded operation
+  std::vector<ProjRow> rows(rec ? a : 0);
+  if (rec)
+    for (int I = 0; I < a; ++I) {
+      int p = I & 1, b = I >> 1;
+      ProjRow& R = rows[I];
+      R.kd = kd[p]; R.mn = mn[p];
+      const size_t sz = (size_t)kd[p] * mn[p];
+      R.Nadj = (double*)Nb[p].p + (size_t)b * sz;
+      R.Sadj = (double*)Sb[p].p + (size_t)b * sz;
+      R.N = std::make_shared<DBuf>(&dev, sz * 8);
+      R.S = std::make_shared<DBuf>(&dev, sz * 8);
+      HIP_CHECK(hipMemcpyAsync(R.N->p, R.Nadj, sz * 8, hipMemcpyDeviceToDevice, dev.stream));
+      HIP_CHECK(hipMemcpyAsync(R.S->p, R.Sadj, sz * 8, hipMemcpyDeviceToDevice, dev.stream));
+      R.P = P64 + (size_t)I * maxkd * chi;
+      R.Q = Q64 + (size_t)I * maxkd * chi;
+    }
+  const int64_t kk = rec ? r : chi;   // singular vectors kept per row
+  DBuf Ln[2], Ls[2], tau[2];
+  DBuf Mb(&dev, (size_t)a * r * r * 8), sv(&dev, (size_t)a * r * 8), Uk(&dev, (size_t)a * r * kk * 8),
+      Vk(&dev, (size_t)a * r * kk * 8), w(&dev, (size_t)a * chi * 8);
   for (int p = 0; p < 2; ++p) {
     if (!cnt[p]) continue;
     const int64_t sz = kd[p] * mn[p];
     TRef Mv{(double*)Mb.p + (size_t)p * r * r, T_F64, {cnt[p], r, r}, {2 * r * r, 1, r}, "bij"};
-    // N (rows a1a2, columns a5a6) sits column-major as N^T; its LQ factor L is
-    // R_n^T of the QR of Eq. QRSVD (kd x r, lower trapezoidal).  The QR is taken
-    // also when N is not tall: forming N S^T directly loses the accuracy of the
-    // small kept singular values that the triangular factors preserve.
     Ln[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * r * 8);
     Ls[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * r * 8);
     tau[p] = DBuf(&dev, (size_t)cnt[p] * r * 8 * 2);
@@ -451,37 +507,163 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     TRef Lnv{Ln[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "bai"};
     TRef Lsv{Ls[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "baj"};
     contract(dev, m, Mv, Lnv, Lsv);
-    Lf[p] = (const double*)Ln[p].p;
-    Rf[p] = (const double*)Ls[p].p;
   }
   // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
-  jacobi_svd(c, (double*)Mb.p, r, a, chi, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
+  jacobi_svd(c, (double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
   HIP_CHECK(ctmk::launch_svd_weights((const double*)sv.p, r, r, (double*)w.p, chi, c->cutoff, a, dev.stream));
   for (int I = 0; I < a; ++I) {
     int p = I & 1, b = I >> 1;
     const int64_t lfs = kd[p] * r;
-    TRef Lv{(void*)(Lf[p] + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
-    TRef Rv{(void*)(Rf[p] + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
-    TRef Uv{(double*)Uk.p + (size_t)I * r * chi, T_F64, {r, chi}, {1, r}, "ik"};
-    TRef Vv{(double*)Vk.p + (size_t)I * r * chi, T_F64, {r, chi}, {1, r}, "ik"};
+    TRef Lv{(void*)((double*)Ln[p].p + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
+    TRef Rv{(void*)((double*)Ls[p].p + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
+    TRef Uv{(double*)Uk.p + (size_t)I * r * kk, T_F64, {r, chi}, {1, r}, "ik"};
+    TRef Vv{(double*)Vk.p + (size_t)I * r * kk, T_F64, {r, chi}, {1, r}, "ik"};
     const double* wI = (const double*)w.p + (size_t)I * chi;
     contract(dev, m, view(P64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Rv, Vv, 1.0, 0, wI);
     contract(dev, m, view(Q64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Lv, Uv, 1.0, 0, wI);
   }
-  if (const char* dump = getenv("CTM_DEBUG_DUMP")) {   // development aid: singular values of each row
-    std::vector<double> h((size_t)a * r);
-    HIP_CHECK(hipMemcpyAsync(h.data(), sv.p, h.size() * 8, hipMemcpyDeviceToHost, dev.stream));
-    HIP_CHECK(hipStreamSynchronize(dev.stream));
-    FILE* fp = fopen(dump, "a");
-    if (fp) {
-      for (int I = 0; I < a; ++I) {
-        fprintf(fp, "f%d J%d I%d sweeps%d", f, J, I, c->last_jacobi_sweeps);
-        for (int64_t k = 0; k < r; ++k) fprintf(fp, " %.17g", h[(size_t)I * r + k]);
-        fprintf(fp, "\n");
-      }
-      fclose(fp);
+  if (!rec) return;
+  // singular vectors of rho = N S^T: U_rho = Q_n-full^T [U; 0], V_rho likewise
+  for (int I = 0; I < a; ++I) {
+    int p = I & 1, b = I >> 1;
+    ProjRow& R = rows[I];
+    const int64_t mnp = mn[p];
+    const size_t sz = (size_t)kd[p] * mnp;
+    R.Ur = std::make_shared<DBuf>(&dev, (size_t)mnp * r * 8);
+    R.Vr = std::make_shared<DBuf>(&dev, (size_t)mnp * r * 8);
+    R.s = std::make_shared<DBuf>(&dev, (size_t)r * 8);
+    R.w = std::make_shared<DBuf>(&dev, (size_t)chi * 8);
+    HIP_CHECK(hipMemcpyAsync(R.s->p, (double*)sv.p + (size_t)I * r, r * 8, hipMemcpyDeviceToDevice, dev.stream));
+    HIP_CHECK(hipMemcpyAsync(R.w->p, (double*)w.p + (size_t)I * chi, chi * 8, hipMemcpyDeviceToDevice, dev.stream));
+    for (int side = 0; side < 2; ++side) {
+      DBuf& H = side == 0 ? Nb[p] : Sb[p];
+      double* dst = (double*)(side == 0 ? R.Ur : R.Vr)->p;
+      const double* src = (double*)(side == 0 ? Uk : Vk).p + (size_t)I * r * kk;
+      const double* tv = (double*)tau[p].p + (size_t)(side == 0 ? 0 : cnt[p]) * r + (size_t)b * r;
+      fill(dev, view(dst, T_F64, {mnp * r}, "q"), 0.0);
+      TRef dv{dst, T_F64, {r, r}, {1, mnp}, "ij"};
+      TRef sv_{(void*)src, T_F64, {r, r}, {1, r}, "ij"};
+      copy_into(dev, dv, sv_);
+      RB_CHECK(rocsolver_dormlq(c->blas, rocblas_side_left, rocblas_operation_transpose, (rocblas_int)mnp,
+                                (rocblas_int)r, (rocblas_int)r, (double*)H.p + (size_t)b * sz, (rocblas_int)kd[p],
+                                (double*)tv, dst, (rocblas_int)mnp));
     }
   }
+  c->tape.custom([c, rows, r]() {
+    for (const ProjRow& R : rows) proj_backward(c, R, r);
+  });
+}
+
+// Adjoint of (N, S) -> (P, Q) for one row, in the form P = S^T V_rho w,
+// Q = N^T U_rho w with rho = N S^T = U_rho diag(s) V_rho^T (thin, all r
+// triplets), which needs no inverse of the triangular factors:
+//   Sbar += X Pbar^T, Nbar += Y Qbar^T with X = V_rho[:, :chi] w, Y = U_rho[:, :chi] w;
+//   Ubar = (N Qbar) w, Vbar = (S Pbar) w on the first chi columns;
+//   sbar_k = -1/2 w_k^3 (<V_rho_k, S Pbar_k> + <U_rho_k, N Qbar_k>);
+//   rhobar from the thin-SVD derivative with the Lorentzian-broadened F
+//   (Eq. AD; F_ij = D/(D^2 + (eta max(s_i^2, s_j^2))^2), D = s_j^2 - s_i^2);
+//   Nbar += rhobar S, Sbar += rhobar^T N.
+void proj_backward(ctm_ctx* c, const ProjRow& R, int64_t r) {
+  Dev& dev = c->dev;
+  Tape& tp = c->tape;
+  const int64_t chi = c->chi, kd = R.kd, mn = R.mn;
+  const int m = ctmk::MODE_F64;
+  double* Nc = (double*)R.N->p;
+  double* Sc = (double*)R.S->p;
+  double* Ur = (double*)R.Ur->p;
+  double* Vr = (double*)R.Vr->p;
+  const double* sv = (const double*)R.s->p;
+  const double* w = (const double*)R.w->p;
+  TRef Pb = view(tp.adj_ptr(R.P), T_F64, {kd, chi}, "ak");
+  TRef Qb = view(tp.adj_ptr(R.Q), T_F64, {kd, chi}, "ak");
+  TRef Nb = view(tp.adj_ptr(R.Nadj), T_F64, {mn, kd}, "ia");
+  TRef Sb = view(tp.adj_ptr(R.Sadj), T_F64, {mn, kd}, "ia");
+  TRef Nv = view(Nc, T_F64, {mn, kd}, "ia"), Sv = view(Sc, T_F64, {mn, kd}, "ia");
+  TRef Urv{Ur, T_F64, {mn, r}, {1, mn}, "iq"}, Vrv{Vr, T_F64, {mn, r}, {1, mn}, "iq"};
+  DBuf X(&dev, (size_t)mn * chi * 8), Y(&dev, (size_t)mn * chi * 8), Xb(&dev, (size_t)mn * chi * 8),
+      Yb(&dev, (size_t)mn * chi * 8);
+  HIP_CHECK(ctmk::launch_colscale_copy(Vr, 1, mn, mn, chi, w, (double*)X.p, dev.stream));
+  HIP_CHECK(ctmk::launch_colscale_copy(Ur, 1, mn, mn, chi, w, (double*)Y.p, dev.stream));
+  contract(dev, m, Sb, view(X.p, T_F64, {mn, chi}, "ik"), Pb, 1.0, 1);
+  contract(dev, m, Nb, view(Y.p, T_F64, {mn, chi}, "ik"), Qb, 1.0, 1);
+  contract(dev, m, view(Xb.p, T_F64, {mn, chi}, "ik"), Sv, Pb);
+  contract(dev, m, view(Yb.p, T_F64, {mn, chi}, "ik"), Nv, Qb);
+  DBuf sb(&dev, (size_t)r * 8);
+  HIP_CHECK(ctmk::launch_svd_sbar(Ur, Vr, (const double*)Xb.p, (const double*)Yb.p, mn, r, chi, w, (double*)sb.p,
+                                  dev.stream));
+  // Ubar = Yb w, Vbar = Xb w (first chi columns)
+  DBuf Ubar(&dev, (size_t)mn * chi * 8), Vbar(&dev, (size_t)mn * chi * 8);
+  HIP_CHECK(ctmk::launch_colscale_copy((const double*)Yb.p, chi, 1, mn, chi, w, (double*)Ubar.p, dev.stream));
+  HIP_CHECK(ctmk::launch_colscale_copy((const double*)Xb.p, chi, 1, mn, chi, w, (double*)Vbar.p, dev.stream));
+  TRef Ubv = view(Ubar.p, T_F64, {mn, chi}, "ik"), Vbv = view(Vbar.p, T_F64, {mn, chi}, "ik");
+  DBuf G(&dev, (size_t)r * chi * 8), Hm(&dev, (size_t)r * chi * 8);
+  contract(dev, m, view(G.p, T_F64, {r, chi}, "qk"), Urv, Ubv);
+  contract(dev, m, view(Hm.p, T_F64, {r, chi}, "qk"), Vrv, Vbv);
+  DBuf core(&dev, (size_t)r * r * 8);
+  HIP_CHECK(ctmk::launch_svd_core((const double*)G.p, (const double*)Hm.p, sv, (const double*)sb.p, r, chi, c->eta,
+                                  (double*)core.p, dev.stream));
+  // Gm = Ur core + [ (Ubar - Ur G) sinv , 0 ]
+  DBuf Gm(&dev, (size_t)mn * r * 8), T(&dev, (size_t)mn * chi * 8), A2(&dev, (size_t)mn * chi * 8);
+  TRef Gmv = view(Gm.p, T_F64, {mn, r}, "ip");
+  contract(dev, m, Gmv, Urv, view(core.p, T_F64, {r, r}, "qp"));
+  contract(dev, m, view(T.p, T_F64, {mn, chi}, "ik"), Urv, view(G.p, T_F64, {r, chi}, "qk"));
+  HIP_CHECK(ctmk::launch_sub_sinv((const double*)Ubar.p, (const double*)T.p, mn, chi, sv, w, (double*)A2.p, dev.stream));
+  TRef Gm_k{Gm.p, T_F64, {mn, chi}, {r, 1}, "ik"};
+  copy_into(dev, Gm_k, view(A2.p, T_F64, {mn, chi}, "ik"), true);
+  // B2 = (Vbar - Vr H) sinv
+  DBuf B2(&dev, (size_t)mn * chi * 8);
+  contract(dev, m, view(T.p, T_F64, {mn, chi}, "ik"), Vrv, view(Hm.p, T_F64, {r, chi}, "qk"));
+  HIP_CHECK(ctmk::launch_sub_sinv((const double*)Vbar.p, (const double*)T.p, mn, chi, sv, w, (double*)B2.p, dev.stream));
+  // rhobar = Gm Vr^T + Ur[:, :chi] B2^T  (mn x mn)
+  DBuf rb(&dev, (size_t)mn * mn * 8);
+  TRef rbv = view(rb.p, T_F64, {mn, mn}, "ij");
+  contract(dev, m, rbv, Gmv, TRef{Vr, T_F64, {mn, r}, {1, mn}, "jp"});
+  contract(dev, m, rbv, TRef{Ur, T_F64, {mn, chi}, {1, mn}, "ik"}, view(B2.p, T_F64, {mn, chi}, "jk"), 1.0, 1);
+  // Nbar += rhobar S, Sbar += rhobar^T N
+  contract(dev, m, Nb, rbv, relabel(Sv, "ja"), 1.0, 1);
+  contract(dev, m, relabel(Sb, "ja"), rbv, Nv, 1.0, 1);
+}
+
+// Frobenius normalisation of the updated tensors, batched.  While the tape
+// records, the norms are kept and the adjoint is recorded.
+void normalize_all(ctm_ctx* c, const std::vector<TRef>& ts) {
+  Dev& dev = c->dev;
+  const bool rec = c->tape.recording();
+  std::shared_ptr<DBuf> norms;
+  if (rec) {
+    TapePause pause(dev);
+    norms = std::make_shared<DBuf>(&dev, std::max<size_t>(ts.size(), 1) * 8);
+  }
+  for (size_t s0 = 0; s0 < ts.size(); s0 += ctmk::NORM_MAX) {
+    ctmk::NormList L;
+    std::memset(&L, 0, sizeof(L));
+    int cnt = 0;
+    for (size_t i = s0; i < ts.size() && cnt < ctmk::NORM_MAX; ++i, ++cnt) {
+      L.ptr[cnt] = ts[i].p;
+      L.n[cnt] = ts[i].numel();
+    }
+    if (rec) L.norm_out = (double*)norms->p + s0;
+    HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, dev.stream));
+  }
+  if (!rec) return;
+  std::vector<TRef> keep = ts;
+  c->tape.custom([c, keep, norms]() {
+    Tape& tp = c->tape;
+    for (size_t s0 = 0; s0 < keep.size(); s0 += ctmk::NORM_MAX) {
+      ctmk::NormList Y, Yb;
+      std::memset(&Y, 0, sizeof(Y));
+      std::memset(&Yb, 0, sizeof(Yb));
+      int cnt = 0;
+      for (size_t i = s0; i < keep.size() && cnt < ctmk::NORM_MAX; ++i, ++cnt) {
+        Y.ptr[cnt] = keep[i].p;
+        Y.n[cnt] = keep[i].numel();
+        Yb.ptr[cnt] = tp.adj_ptr(keep[i].p);
+        Yb.n[cnt] = Y.n[cnt];
+      }
+      Y.norm_out = (double*)norms->p + s0;
+      HIP_CHECK(ctmk::launch_normalize_backward(c->st, Y, Yb, cnt, c->dev.stream));
+    }
+  });
 }
 
 // One left move in frame f (Fig. CTMRG b): for every column step J, the
@@ -491,13 +673,13 @@ void left_move(ctm_ctx* c, int f) {
   const int a = c->ny(f), b = c->nx(f);
   const int64_t chi = c->chi, maxkd = chi * c->D * c->d;
   const int m = c->mode;
-  DBuf P64(&dev, (size_t)a * maxkd * chi * 8), Q64(&dev, (size_t)a * maxkd * chi * 8);
-  DBuf Pst, Qst;
-  if (c->st != T_F64) {
-    Pst = DBuf(&dev, (size_t)a * maxkd * chi * 4);
-    Qst = DBuf(&dev, (size_t)a * maxkd * chi * 4);
-  }
   for (int J = 0; J < b; ++J) {
+    DBuf P64(&dev, (size_t)a * maxkd * chi * 8), Q64(&dev, (size_t)a * maxkd * chi * 8);
+    DBuf Pst, Qst;
+    if (c->st != T_F64) {
+      Pst = DBuf(&dev, (size_t)a * maxkd * chi * 4);
+      Qst = DBuf(&dev, (size_t)a * maxkd * chi * 4);
+    }
     std::vector<int64_t> zd(a);
     for (int I = 0; I < a; ++I) zd[I] = c->site(f, I, J).dim[3];
     column_projectors(c, f, J, (double*)P64.p, (double*)Q64.p, maxkd);
@@ -516,39 +698,31 @@ void left_move(ctm_ctx* c, int f) {
                                   : (void*)((float*)Bst.p + (size_t)Ii * maxkd * chi);
       return view(base, c->st, {chi, zd[Ii], chi}, lab);
     };
-    ctmk::NormList L;
-    std::memset(&L, 0, sizeof(L));
-    int cnt = 0;
+    std::vector<TRef> outs;
     for (int I = 0; I < a; ++I) {
       TRef s = c->site_t(f, I, J, "yxrz");
       // C1' = [C1 T1] P_{I-1}
       Tmp X1(&dev, c->st, {chi, s.dim[1], chi}, "axc");
       contract(dev, m, X1.t, c->slot(f, I, J, 0, "ab"), c->slot(f, I, J, 4, "bxc"));
-      TRef C1n = c->slot(f, I, J + 1, 0, "kc");
+      TRef C1n = c->out_slot(f, I, J + 1, 0, "kc");
       contract(dev, m, C1n, PQ(P64, Pst, I - 1, "axk"), X1.t);
       // T4' = Q_{I-1}^T [T4 s] P_I
       Tmp G1(&dev, c->st, {chi, chi, s.dim[1], s.dim[2], s.dim[3]}, "eaxrz");
       contract(dev, m, G1.t, c->slot(f, I, J, 7, "eya"), s);
       Tmp G2(&dev, c->st, {chi, chi, s.dim[2], s.dim[3]}, "emrz");
       contract(dev, m, G2.t, PQ(Q64, Qst, I - 1, "axm"), G1.t);
-      TRef T4n = c->slot(f, I, J + 1, 7, "krm");
+      TRef T4n = c->out_slot(f, I, J + 1, 7, "krm");
       contract(dev, m, T4n, PQ(P64, Pst, I, "ezk"), G2.t);
       // C4' = [C4 T3] Q_I
       Tmp V1(&dev, c->st, {chi, s.dim[3], chi}, "cwa");
       contract(dev, m, V1.t, c->slot(f, I, J, 6, "cwb"), c->slot(f, I, J, 3, "ba"));
-      TRef C4n = c->slot(f, I, J + 1, 3, "ck");
+      TRef C4n = c->out_slot(f, I, J + 1, 3, "ck");
       contract(dev, m, C4n, V1.t, PQ(Q64, Qst, I, "awk"));
-      for (const TRef* t : {&C1n, &T4n, &C4n}) {
-        if (cnt == ctmk::NORM_MAX) {
-          HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, dev.stream));
-          cnt = 0;
-        }
-        L.ptr[cnt] = t->p;
-        L.n[cnt] = t->numel();
-        ++cnt;
-      }
+      outs.push_back(C1n);
+      outs.push_back(T4n);
+      outs.push_back(C4n);
     }
-    HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, dev.stream));
+    normalize_all(c, outs);
   }
 }
 
@@ -711,6 +885,145 @@ void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
   }
 }
 
+// Energy per site (Eq. ExpH) from the current environment; while the tape
+// records, the adjoint d E / d rho of the density matrices is recorded.
+double energy_impl(ctm_ctx* c, const double* H_bond, int n_terms, const ctm_term* terms) {
+  std::vector<std::pair<int, int>> plaq;
+  std::vector<ctmk::EnergyTerm> et(n_terms);
+  for (int i = 0; i < n_terms; ++i) {
+    const ctm_term& t = terms[i];
+    if (t.px < 0 || t.px >= c->Lx || t.py < 0 || t.py >= c->Ly || t.a < 0 || t.a > 3 || t.b < 0 || t.b > 3 || t.a == t.b)
+      throw Error(CTM_EINVAL, "invalid term");
+    int idx = -1;
+    for (size_t q = 0; q < plaq.size(); ++q)
+      if (plaq[q] == std::make_pair(t.px, t.py)) idx = (int)q;
+    if (idx < 0) { idx = (int)plaq.size(); plaq.push_back({t.px, t.py}); }
+    et[i].rho_index = idx; et[i].a = t.a; et[i].b = t.b; et[i].coef = t.coef;
+  }
+  const int64_t d4 = (int64_t)c->d * c->d * c->d * c->d, rsz = d4 * d4;
+  if (plaq.empty()) return 0.0;
+  c->rdm_buf = DBuf(&c->dev, (size_t)plaq.size() * rsz * 8);
+  c->n_rdm = (int)plaq.size();
+  for (size_t q = 0; q < plaq.size(); ++q)
+    plaquette_rdm(c, plaq[q].first, plaq[q].second, (double*)c->rdm_buf.p + q * rsz);
+  const bool rec = c->tape.recording();
+  TapePause pause(c->dev);
+  auto hb = std::make_shared<DBuf>(&c->dev, (size_t)d4 * 8);
+  auto tb = std::make_shared<DBuf>(&c->dev, sizeof(ctmk::EnergyTerm) * std::max(n_terms, 1));
+  auto bond = std::make_shared<DBuf>(&c->dev, (size_t)std::max(n_terms, 1) * 8);
+  HIP_CHECK(hipMemcpyAsync(hb->p, H_bond, (size_t)d4 * 8, hipMemcpyHostToDevice, c->dev.stream));
+  HIP_CHECK(hipMemcpyAsync(tb->p, et.data(), sizeof(ctmk::EnergyTerm) * n_terms, hipMemcpyHostToDevice, c->dev.stream));
+  const double inv_sites = 1.0 / (c->Lx * c->Ly);
+  HIP_CHECK(ctmk::launch_energy((const double*)c->rdm_buf.p, rsz, (const double*)hb->p,
+                                (const ctmk::EnergyTerm*)tb->p, n_terms, c->d, inv_sites, (double*)c->dscal.p,
+                                (double*)bond->p, c->dev.stream));
+  HIP_CHECK(ctmk::launch_nonfinite(T_F64, c->dscal.p, 1, (int*)c->flag.p, c->dev.stream));
+  double E = 0.0;
+  HIP_CHECK(hipMemcpyAsync(&E, c->dscal.p, 8, hipMemcpyDeviceToHost, c->dev.stream));
+  HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+  if (rec) {
+    void* rho = c->rdm_buf.p;
+    int nr = (int)plaq.size();
+    c->tape.custom([c, rho, rsz, hb, tb, bond, n_terms, nr, inv_sites]() {
+      HIP_CHECK(ctmk::launch_energy_backward((const double*)rho, rsz, (const double*)hb->p,
+                                             (const ctmk::EnergyTerm*)tb->p, n_terms, c->d, inv_sites,
+                                             (const double*)bond->p, nr, (double*)c->tape.adj_ptr(rho),
+                                             c->dev.stream));
+    });
+  }
+  return E;
+}
+
+// Adjoint of the site tensors of all frames (site_adj mirrors site_buf) added
+// up into dE/dA[t][s][l][u][r][d] (float64, overwritten).
+void sites_adjoint_to_A(ctm_ctx* c, const void* site_adj, double* grad) {
+  Dev& dev = c->dev;
+  const int d = c->d, D = c->D;
+  const int64_t Dd = (int64_t)D * d, n4 = (int64_t)D * D * D * D, nk = (int64_t)d * n4, ny_ = (int64_t)d * d * n4;
+  const int64_t per_frame = 2 * c->nt * nk + n4 + ny_;
+  const size_t es = type_size(c->st);
+  fill(dev, view(grad, T_F64, {c->nt * nk}, "q"), 0.0);
+  const std::string lurd = "lurd";
+  Tmp k0(&dev, T_F64, {D, D, D, d, D}, "lursd");
+  Tmp b0(&dev, T_F64, {D, D, d, D, D}, "lusrd");
+  for (int f = 0; f < 4; ++f) {
+    std::string rl;
+    for (int i = 0; i < 4; ++i) rl += lurd[(i + f) % 4];
+    const char* fb = (const char*)site_adj + (size_t)f * per_frame * es;
+    int64_t kd0[4] = {D, D, Dd, D}, bd0[4] = {D, Dd, D, D}, nk_[4], nb_[4];
+    for (int i = 0; i < 4; ++i) { nk_[i] = kd0[(i + f) % 4]; nb_[i] = bd0[(i + f) % 4]; }
+    for (int t = 0; t < c->nt; ++t) {
+      TRef gA = view(grad + t * nk, T_F64, {d, D, D, D, D}, "slurd");
+      copy_into(dev, view(k0.buf.p, T_F64, {kd0[0], kd0[1], kd0[2], kd0[3]}, lurd),
+                view((void*)(fb + (size_t)(2 * t) * nk * es), c->st, {nk_[0], nk_[1], nk_[2], nk_[3]}, rl));
+      copy_into(dev, gA, k0.t, true);
+      copy_into(dev, view(b0.buf.p, T_F64, {bd0[0], bd0[1], bd0[2], bd0[3]}, lurd),
+                view((void*)(fb + (size_t)(2 * t + 1) * nk * es), c->st, {nb_[0], nb_[1], nb_[2], nb_[3]}, rl));
+      copy_into(dev, gA, b0.t, true);
+    }
+  }
+}
+
+// E and dE/dA of the energy after n sweeps from the current environment,
+// which is held constant (the shortened chain of Sec. IV).  Checkpointing:
+// the forward pass keeps one environment snapshot per sweep; the reverse
+// pass recomputes one sweep at a time under the tape and propagates the
+// environment adjoint back through it, so the tape never holds more than one
+// sweep.  The environment is left at the result of the n sweeps.
+double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, const ctm_term* terms, double* grad) {
+  Dev& dev = c->dev;
+  const size_t eb = (size_t)c->env_elems * type_size(c->st);
+  std::vector<DBuf> snap;
+  for (int i = 0; i < n; ++i) {
+    snap.emplace_back(&dev, eb);
+    HIP_CHECK(hipMemcpyAsync(snap.back().p, c->env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
+    for (int f : MOVE_FRAMES) left_move(c, f);
+  }
+  HIP_CHECK(ctmk::launch_nonfinite(c->st, c->env.p, c->env_elems, (int*)c->flag.p, dev.stream));
+  DBuf final_env(&dev, eb);
+  HIP_CHECK(hipMemcpyAsync(final_env.p, c->env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
+  DBuf site_adj(&dev, c->site_buf.bytes), env_adj(&dev, eb), env_adj2(&dev, eb);
+  HIP_CHECK(hipMemsetAsync(site_adj.p, 0, site_adj.bytes, dev.stream));
+  HIP_CHECK(hipMemsetAsync(env_adj.p, 0, eb, dev.stream));
+  // energy at the final environment
+  c->tape.begin(&dev);
+  c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
+  c->tape.reg(c->env.p, eb, env_adj.p);
+  double E = energy_impl(c, H_bond, n_terms, terms);
+  c->tape.backward();
+  c->tape.clear();
+  // sweeps in reverse order
+  const size_t es = type_size(c->st);
+  for (int i = n - 1; i >= 0; --i) {
+    HIP_CHECK(hipMemcpyAsync(c->env.p, snap[i].p, eb, hipMemcpyDeviceToDevice, dev.stream));
+    c->reset_slot_ptrs();
+    HIP_CHECK(hipMemsetAsync(env_adj2.p, 0, eb, dev.stream));
+    c->tape.begin(&dev);
+    c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
+    c->tape.reg(c->env.p, eb, env_adj2.p);
+    for (int f : MOVE_FRAMES) left_move(c, f);
+    // seed: the adjoint of the environment after this sweep
+    TapePause pause(dev);
+    for (size_t idx = 0; idx < c->slot_ptr.size(); ++idx) {
+      const int64_t ne = c->slot_elems(idx);
+      void* seed = (char*)env_adj.p + c->slot_off[idx] * es;
+      copy_into(dev, view(c->tape.adj_ptr(c->slot_ptr[idx]), c->st, {ne}, "q"), view(seed, c->st, {ne}, "q"), true);
+    }
+    c->tape.backward();
+    c->tape.clear();
+    std::swap(env_adj, env_adj2);
+    c->reset_slot_ptrs();
+  }
+  HIP_CHECK(hipMemcpyAsync(c->env.p, final_env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
+  c->reset_slot_ptrs();
+  c->have_prev = false;
+  sites_adjoint_to_A(c, site_adj.p, grad);
+  HIP_CHECK(ctmk::launch_nonfinite(T_F64, grad, (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D, (int*)c->flag.p,
+                                   dev.stream));
+  HIP_CHECK(hipStreamSynchronize(dev.stream));
+  return E;
+}
+
 int fail(ctm_ctx* c, const Error& e) {
   if (c) c->err = e.what();
   else g_init_error = e.what();
@@ -751,6 +1064,7 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int 
     HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
     build_layout(c);
     c->env = DBuf(&c->dev, (size_t)c->env_elems * type_size(c->st));
+    c->reset_slot_ptrs();
     build_sites(c);
     init_env(c);
     HIP_CHECK(hipStreamSynchronize(c->dev.stream));
@@ -828,35 +1142,29 @@ int ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, double* 
 int ctm_energy(ctm_ctx* c, const double* H_bond, int n_terms, const ctm_term* terms, double* E) {
   if (!c || !H_bond || (n_terms > 0 && !terms) || !E) return CTM_EINVAL;
   try {
-    std::vector<std::pair<int, int>> plaq;
-    std::vector<ctmk::EnergyTerm> et(n_terms);
-    for (int i = 0; i < n_terms; ++i) {
-      const ctm_term& t = terms[i];
-      if (t.px < 0 || t.px >= c->Lx || t.py < 0 || t.py >= c->Ly || t.a < 0 || t.a > 3 || t.b < 0 || t.b > 3 || t.a == t.b)
-        throw Error(CTM_EINVAL, "invalid term");
-      int idx = -1;
-      for (size_t q = 0; q < plaq.size(); ++q)
-        if (plaq[q] == std::make_pair(t.px, t.py)) idx = (int)q;
-      if (idx < 0) { idx = (int)plaq.size(); plaq.push_back({t.px, t.py}); }
-      et[i].rho_index = idx; et[i].a = t.a; et[i].b = t.b; et[i].coef = t.coef;
-    }
-    const int64_t d4 = (int64_t)c->d * c->d * c->d * c->d, rsz = d4 * d4;
-    if (plaq.empty()) { *E = 0.0; return CTM_OK; }
-    c->rdm_buf = DBuf(&c->dev, (size_t)plaq.size() * rsz * 8);
-    c->n_rdm = (int)plaq.size();
-    for (size_t q = 0; q < plaq.size(); ++q)
-      plaquette_rdm(c, plaq[q].first, plaq[q].second, (double*)c->rdm_buf.p + q * rsz);
-    DBuf hb(&c->dev, (size_t)c->d * c->d * c->d * c->d * 8), tb(&c->dev, sizeof(ctmk::EnergyTerm) * n_terms);
-    HIP_CHECK(hipMemcpyAsync(hb.p, H_bond, (size_t)d4 * 8, hipMemcpyHostToDevice, c->dev.stream));
-    HIP_CHECK(hipMemcpyAsync(tb.p, et.data(), sizeof(ctmk::EnergyTerm) * n_terms, hipMemcpyHostToDevice, c->dev.stream));
-    HIP_CHECK(ctmk::launch_energy((const double*)c->rdm_buf.p, rsz, (const double*)hb.p,
-                                  (const ctmk::EnergyTerm*)tb.p, n_terms, c->d, 1.0 / (c->Lx * c->Ly),
-                                  (double*)c->dscal.p, nullptr, c->dev.stream));
-    HIP_CHECK(ctmk::launch_nonfinite(T_F64, c->dscal.p, 1, (int*)c->flag.p, c->dev.stream));
-    HIP_CHECK(hipMemcpyAsync(E, c->dscal.p, 8, hipMemcpyDeviceToHost, c->dev.stream));
+    *E = energy_impl(c, H_bond, n_terms, terms);
     check_flags(c);
     return CTM_OK;
   } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_energy_grad(ctm_ctx* c, const double* A, int n_sweeps, const double* H_bond, int n_terms,
+                    const ctm_term* terms, double* E, double* dEdA) {
+  if (!c || !H_bond || (n_terms > 0 && !terms) || !E || !dEdA || n_sweeps < 0) return CTM_EINVAL;
+  try {
+    if (A) {
+      int64_t nA = (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D;
+      HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
+      build_sites(c);
+    }
+    *E = energy_grad_impl(c, n_sweeps, H_bond, n_terms, terms, dEdA);
+    check_flags(c);
+    return CTM_OK;
+  } catch (const Error& e) {
+    c->tape.clear();
+    c->reset_slot_ptrs();
+    return fail(c, e);
+  }
 }
 
 int ctm_last_rdms(ctm_ctx* c, double* rho, int capacity, int* n) {

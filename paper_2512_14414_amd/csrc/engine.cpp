@@ -78,11 +78,101 @@ void* Dev::alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   hipError_t e = hipMallocAsync(&p, bytes, stream);
   if (e != hipSuccess) throw Error(e == hipErrorOutOfMemory ? -2 : -3, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  if (tape && tape->recording()) tape->reg(p, bytes);
   return p;
 }
 
 void Dev::free(void* p) {
-  if (p) (void)hipFreeAsync(p, stream);
+  if (!p) return;
+  if (tape && tape->on && tape->bufs.count((uintptr_t)p)) {
+    tape->retained.push_back(p);
+    return;
+  }
+  (void)hipFreeAsync(p, stream);
+}
+
+// ---------------------------------------------------------------------------
+void Tape::begin(Dev* d) {
+  clear();
+  dev = d;
+  d->tape = this;
+  on = true;
+}
+
+void Tape::reg(void* p, size_t bytes, void* adjp) {
+  Buf b;
+  b.bytes = bytes;
+  b.adj = adjp;
+  bufs[(uintptr_t)p] = b;
+}
+
+static std::map<uintptr_t, Tape::Buf>::iterator find_buf(std::map<uintptr_t, Tape::Buf>& m, const void* p) {
+  uintptr_t a = (uintptr_t)p;
+  auto it = m.upper_bound(a);
+  if (it == m.begin()) return m.end();
+  --it;
+  if (a >= it->first + it->second.bytes) return m.end();
+  return it;
+}
+
+bool Tape::has(const void* p) const {
+  auto& m = const_cast<std::map<uintptr_t, Buf>&>(bufs);
+  return find_buf(m, p) != m.end();
+}
+
+void* Tape::adj_ptr(const void* p) {
+  auto it = find_buf(bufs, p);
+  if (it == bufs.end()) throw Error(-1, "tape: adjoint of an unregistered buffer");
+  Buf& b = it->second;
+  if (!b.adj) {
+    HIP_CHECK(hipMallocAsync(&b.adj, b.bytes, dev->stream));
+    HIP_CHECK(hipMemsetAsync(b.adj, 0, b.bytes, dev->stream));
+    b.own = true;
+  }
+  return (char*)b.adj + ((uintptr_t)p - it->first);
+}
+
+TRef Tape::adj(const TRef& t) {
+  TRef r = t;
+  r.p = adj_ptr(t.p);
+  return r;
+}
+
+void Tape::custom(std::function<void()> f) {
+  Op o;
+  o.kind = 2;
+  o.backward = std::move(f);
+  ops.push_back(std::move(o));
+}
+
+void Tape::backward() {
+  bool was = on;
+  on = false;
+  for (size_t i = ops.size(); i-- > 0;) {
+    Op& o = ops[i];
+    if (o.kind == 0) {
+      if (!has(o.c.p)) continue;
+      TRef cb = adj(o.c);
+      if (has(o.a.p)) contract(*dev, o.mode, adj(o.a), cb, o.b, o.alpha, 1);
+      if (has(o.b.p)) contract(*dev, o.mode, adj(o.b), o.a, cb, o.alpha, 1);
+    } else if (o.kind == 1) {
+      if (has(o.c.p) && has(o.a.p)) copy_into(*dev, adj(o.a), adj(o.c), true);
+    } else {
+      o.backward();
+    }
+  }
+  on = was;
+}
+
+void Tape::clear() {
+  on = false;
+  ops.clear();
+  for (auto& kv : bufs)
+    if (kv.second.own && kv.second.adj) (void)hipFreeAsync(kv.second.adj, dev->stream);
+  bufs.clear();
+  for (void* p : retained) (void)hipFreeAsync(p, dev->stream);
+  retained.clear();
+  if (dev) dev->tape = nullptr;
 }
 
 namespace {
@@ -229,6 +319,16 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
 void contract(Dev& dev, int mode, const TRef& C, const TRef& A, const TRef& B, double alpha, int beta,
               const double* colscale) {
   if (A.type != B.type || A.type != C.type) throw Error(-1, "contract: operand types differ");
+  if (dev.tape && dev.tape->recording()) {
+    if (colscale) throw Error(-1, "contract: a column scale cannot be recorded");
+    Tape::Op o;
+    o.kind = 0;
+    o.a = A; o.b = B; o.c = C;
+    o.alpha = alpha;
+    o.mode = mode;
+    dev.tape->ops.push_back(o);
+  }
+  TapePause pause(dev);
   Plan P = make_plan(C, A, B);
   if (P.ok()) {
     launch_plan(dev, mode, P, C, A, B, alpha, beta, colscale);
@@ -261,6 +361,13 @@ void contract(Dev& dev, int mode, const TRef& C, const TRef& A, const TRef& B, d
 
 void copy_into(Dev& dev, const TRef& out, const TRef& in, bool accumulate) {
   if (out.lab.size() != in.lab.size()) throw Error(-1, "copy_into: rank mismatch " + in.lab + " -> " + out.lab);
+  if (dev.tape && dev.tape->recording()) {
+    Tape::Op o;
+    o.kind = 1;
+    o.a = in; o.c = out;
+    o.accumulate = accumulate;
+    dev.tape->ops.push_back(o);
+  }
   ctmk::PermArgs p;
   std::memset(&p, 0, sizeof(p));
   // iterate in the order of ``out``; drop size-1 axes
@@ -282,6 +389,7 @@ void copy_into(Dev& dev, const TRef& out, const TRef& in, bool accumulate) {
 }
 
 Tmp permuted(Dev& dev, const TRef& in, const std::string& lab, int type) {
+  TapePause pause(dev);
   std::vector<int64_t> d;
   for (char c : lab) {
     size_t j = in.lab.find(c);

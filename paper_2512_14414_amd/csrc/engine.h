@@ -3,6 +3,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
+#include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -45,9 +48,14 @@ TRef relabel(const TRef& t, const std::string& lab);
 // Split axis ``label`` (dimension a*b) into two axes (a major, b minor).
 TRef split_axis(const TRef& t, char label, int64_t a, int64_t b, char lab_major, char lab_minor);
 
-// Stream-ordered device memory.
+struct Tape;
+
+// Stream-ordered device memory.  While a tape records, every allocation is
+// registered with it and frees are deferred until the tape is cleared, so that
+// the values a backward pass needs stay alive.
 struct Dev {
   hipStream_t stream = nullptr;
+  Tape* tape = nullptr;
   void* alloc(size_t bytes);
   void free(void* p);
 };
@@ -100,6 +108,54 @@ void copy_into(Dev& dev, const TRef& out, const TRef& in, bool accumulate = fals
 Tmp permuted(Dev& dev, const TRef& in, const std::string& lab, int type = -1);
 
 void fill(Dev& dev, const TRef& t, double v);   // t must be contiguous
+
+// Reverse-mode tape over the engine's operations.  A contraction C = a A.B is
+// recorded with its operand views; its adjoint is again a labelled
+// contraction (Abar += a Cbar.B, Bbar += a A.Cbar).  Copies (with type
+// conversion) map adjoints back by labels.  Operations with a hand-written
+// derivative (projectors, normalisation, energy) are recorded as closures.
+// Adjoints live in buffers that mirror the registered forward buffers byte
+// for byte: the adjoint view of a forward view has the same strides at the
+// same offset.  Pointers not registered with the tape are constants.
+struct Tape {
+  struct Buf {
+    size_t bytes = 0;
+    void* adj = nullptr;     // adjoint buffer (allocated on first use unless given)
+    bool own = false;
+  };
+  struct Op {
+    int kind = 0;            // 0 contract, 1 copy, 2 custom
+    TRef a, b, c;
+    double alpha = 1.0;
+    int mode = 0;
+    bool accumulate = false;
+    std::function<void()> backward;
+  };
+  Dev* dev = nullptr;
+  bool on = false;
+  int paused = 0;
+  std::map<uintptr_t, Buf> bufs;
+  std::vector<Op> ops;
+  std::vector<void*> retained;
+
+  bool recording() const { return on && paused == 0; }
+  void begin(Dev* d);
+  // register a forward buffer; ``adj`` (optional) is an external adjoint buffer of the same size
+  void reg(void* p, size_t bytes, void* adj = nullptr);
+  bool has(const void* p) const;
+  // adjoint view of forward view t (zero-initialised buffer on first use); requires has(t.p)
+  TRef adj(const TRef& t);
+  void* adj_ptr(const void* p);
+  void custom(std::function<void()> f);
+  void backward();
+  void clear();          // frees retained forward buffers and owned adjoints
+};
+
+struct TapePause {
+  Tape* t;
+  explicit TapePause(Dev& d) : t(d.tape) { if (t) ++t->paused; }
+  ~TapePause() { if (t) --t->paused; }
+};
 
 // Count of contraction-kernel launches and their algorithmic flops (2 M N K per
 // batch entry).  While ``timing`` is on, every launch is bracketed by a pair

@@ -74,4 +74,18 @@ hipError_t launch_rt_from_qr(const double* A, double* X, int64_t n, int64_t stri
 hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int64_t stride, int batch, int64_t kmax,
                                 double* sv, double* U, double* Vk, hipStream_t s);
 
+// reverse pass
+hipError_t launch_normalize_backward(int type, const NormList& Y, const NormList& Yb, int count, hipStream_t s);
+hipError_t launch_energy_backward(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms,
+                                  int n_terms, int d, double inv_sites, const double* bond, int n_rho, double* rho_bar,
+                                  hipStream_t s);
+hipError_t launch_colscale_copy(const double* in, int64_t s_row, int64_t s_col, int64_t rows, int64_t cols,
+                                const double* w, double* out, hipStream_t s);
+hipError_t launch_svd_sbar(const double* Ur, const double* Vr, const double* Xb, const double* Yb, int64_t rows,
+                           int64_t r, int64_t chi, const double* w, double* sbar, hipStream_t s);
+hipError_t launch_svd_core(const double* G, const double* H, const double* s, const double* sbar, int64_t r,
+                           int64_t chi, double eta, double* core, hipStream_t st);
+hipError_t launch_sub_sinv(const double* A, const double* B, int64_t rows, int64_t chi, const double* s,
+                           const double* w, double* out, hipStream_t st);
+
 }  // namespace ctmk

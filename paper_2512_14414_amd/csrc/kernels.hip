@@ -602,4 +602,168 @@ hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Kernels of the reverse pass.
+
+// Adjoint of y = x / |x| (in place on the adjoint): xbar = (ybar - y <y, ybar>) / |x|.
+template <typename T>
+__global__ __launch_bounds__(256) void normalize_backward_kernel(NormList Y, NormList Yb) {
+  int t = blockIdx.x;
+  const T* y = (const T*)Y.ptr[t];
+  T* yb = (T*)Yb.ptr[t];
+  int64_t n = Y.n[t];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)y[i] * (double)yb[i];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double dot = red[0], nrm = Y.norm_out[t];
+  double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) yb[i] = (T)(((double)yb[i] - (double)y[i] * dot) * inv);
+}
+
+hipError_t launch_normalize_backward(int type, const NormList& Y, const NormList& Yb, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (type == 0) normalize_backward_kernel<double><<<count, 256, 0, s>>>(Y, Yb);
+  else normalize_backward_kernel<float><<<count, 256, 0, s>>>(Y, Yb);
+  return hipGetLastError();
+}
+
+// Adjoint of the energy with respect to the plaquette density matrices:
+// with e_t = Tr(h_t rho)/Tr rho, d e_t / d rho[x][y] = (h_t[y][x] - e_t delta_xy) / Tr rho,
+// where h_t is the bond operator on sites (a, b) times the identity on the other two.
+__global__ void energy_backward_kernel(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms,
+                                       int n_terms, int d, double inv_sites, const double* bond, int n_rho,
+                                       double* rho_bar) {
+  const int D4 = d * d * d * d;
+  const int64_t total = (int64_t)n_rho * D4 * D4;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int p = (int)(e / ((int64_t)D4 * D4));
+    int ik = (int)((e / D4) % D4), ib = (int)(e % D4);
+    const double* r = rho + p * rho_stride;
+    double tr = 0.0;
+    for (int i = 0; i < D4; ++i) tr += r[(int64_t)i * D4 + i];
+    int ko[4], bo[4], dd[4] = {d * d * d, d * d, d, 1};
+    for (int q = 0; q < 4; ++q) { ko[q] = (ik / dd[q]) % d; bo[q] = (ib / dd[q]) % d; }
+    double g = 0.0;
+    for (int t = 0; t < n_terms; ++t) {
+      const EnergyTerm tm = terms[t];
+      if (tm.rho_index != p) continue;
+      bool spect = true;
+      for (int q = 0; q < 4; ++q)
+        if (q != tm.a && q != tm.b && ko[q] != bo[q]) spect = false;
+      double hv = spect ? h[(bo[tm.a] * d + bo[tm.b]) * d * d + ko[tm.a] * d + ko[tm.b]] : 0.0;
+      double diag = ik == ib ? bond[t] : 0.0;
+      g += tm.coef * (hv - diag) / tr;
+    }
+    rho_bar[e] += g * inv_sites;
+  }
+}
+
+hipError_t launch_energy_backward(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms,
+                                  int n_terms, int d, double inv_sites, const double* bond, int n_rho, double* rho_bar,
+                                  hipStream_t s) {
+  int64_t total = (int64_t)n_rho * d * d * d * d * d * d * d * d;
+  energy_backward_kernel<<<grid_for(total), 256, 0, s>>>(rho, rho_stride, h, terms, n_terms, d, inv_sites, bond, n_rho,
+                                                          rho_bar);
+  return hipGetLastError();
+}
+
+// out[i][k] (row-major rows x cols) = in[i*s_row + k*s_col] * w[k]; w may be null (factor 1).
+__global__ void colscale_copy_kernel(const double* in, int64_t s_row, int64_t s_col, int64_t rows, int64_t cols,
+                                     const double* w, double* out) {
+  int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e / cols, k = e - i * cols;
+    double v = in[i * s_row + k * s_col];
+    out[e] = w ? v * w[k] : v;
+  }
+}
+
+hipError_t launch_colscale_copy(const double* in, int64_t s_row, int64_t s_col, int64_t rows, int64_t cols,
+                                const double* w, double* out, hipStream_t s) {
+  if (rows * cols <= 0) return hipSuccess;
+  colscale_copy_kernel<<<grid_for(rows * cols), 256, 0, s>>>(in, s_row, s_col, rows, cols, w, out);
+  return hipGetLastError();
+}
+
+// sbar[k] = -1/2 w_k^3 (sum_j Vr[j][k] Xb[j][k] + sum_i Ur[i][k] Yb[i][k]) for k < chi, 0 for chi <= k < r.
+// Ur, Vr: column-major (rows x r, leading dimension rows); Xb, Yb: row-major rows x chi.
+__global__ __launch_bounds__(256) void svd_sbar_kernel(const double* Ur, const double* Vr, const double* Xb,
+                                                       const double* Yb, int64_t rows, int64_t r, int64_t chi,
+                                                       const double* w, double* sbar) {
+  int64_t k = blockIdx.x;
+  double acc = 0.0;
+  if (k < chi)
+    for (int64_t i = threadIdx.x; i < rows; i += 256)
+      acc += Vr[i + k * rows] * Xb[i * chi + k] + Ur[i + k * rows] * Yb[i * chi + k];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int q = 128; q > 0; q >>= 1) {
+    if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sbar[k] = k < chi ? -0.5 * red[0] * w[k] * w[k] * w[k] : 0.0;
+}
+
+hipError_t launch_svd_sbar(const double* Ur, const double* Vr, const double* Xb, const double* Yb, int64_t rows,
+                           int64_t r, int64_t chi, const double* w, double* sbar, hipStream_t s) {
+  svd_sbar_kernel<<<(unsigned)r, 256, 0, s>>>(Ur, Vr, Xb, Yb, rows, r, chi, w, sbar);
+  return hipGetLastError();
+}
+
+// Core of the SVD adjoint (row-major r x r):
+//   core = (F o (G - G^T)) diag(s) + diag(sbar) + diag(s) (F o (H - H^T)),
+// G = U^T Ubar and H = V^T Vbar given as r x chi (columns >= chi are zero),
+// F_qp = D / (D^2 + (eta m)^2), D = s_p^2 - s_q^2, m = max(s_q^2, s_p^2), F_qq = 0.
+__global__ void svd_core_kernel(const double* G, const double* H, const double* s, const double* sbar, int64_t r,
+                                int64_t chi, double eta, double* core) {
+  int64_t total = r * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = e / r, p = e - q * r;
+    double v;
+    if (q == p) {
+      v = sbar[q];
+    } else {
+      double sq = s[q] * s[q], sp = s[p] * s[p];
+      double Dl = sp - sq, m = fmax(sq, sp) * eta;
+      double den = Dl * Dl + m * m;
+      double F = den > 0.0 ? Dl / den : 0.0;
+      double gqp = p < chi ? G[q * chi + p] : 0.0, gpq = q < chi ? G[p * chi + q] : 0.0;
+      double hqp = p < chi ? H[q * chi + p] : 0.0, hpq = q < chi ? H[p * chi + q] : 0.0;
+      v = F * (gqp - gpq) * s[p] + s[q] * F * (hqp - hpq);
+    }
+    core[e] = v;
+  }
+}
+
+hipError_t launch_svd_core(const double* G, const double* H, const double* s, const double* sbar, int64_t r,
+                           int64_t chi, double eta, double* core, hipStream_t st) {
+  svd_core_kernel<<<grid_for(r * r), 256, 0, st>>>(G, H, s, sbar, r, chi, eta, core);
+  return hipGetLastError();
+}
+
+// out[i][k] = (A[i][k] - B[i][k]) * sinv_k (row-major rows x chi), sinv_k = 1/s_k where w_k != 0, else 0.
+__global__ void sub_sinv_kernel(const double* A, const double* B, int64_t rows, int64_t chi, const double* s,
+                                const double* w, double* out) {
+  int64_t total = rows * chi;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = e % chi;
+    double si = w[k] != 0.0 ? 1.0 / s[k] : 0.0;
+    out[e] = (A[e] - B[e]) * si;
+  }
+}
+
+hipError_t launch_sub_sinv(const double* A, const double* B, int64_t rows, int64_t chi, const double* s,
+                           const double* w, double* out, hipStream_t st) {
+  if (rows * chi <= 0) return hipSuccess;
+  sub_sinv_kernel<<<grid_for(rows * chi), 256, 0, st>>>(A, B, rows, chi, s, w, out);
+  return hipGetLastError();
+}
+
 }  // namespace ctmk

@@ -1,0 +1,144 @@
+"""Gradient of the energy (Eq. AD) from the library against the oracle.
+
+E(A) is the energy after n sweeps from a given environment held constant
+(Sec. IV); the environment is the oracle's converged one, where the iteration
+is contracting and E is a smooth function of A.
+
+Bar.  Where the gradient is well conditioned (the random D = 2 state below:
+the oracle's two LAPACK SVD drivers give gradients that agree to 2e-9
+relative) the library must agree with the oracle to 1e-8 of the largest
+entry.  Weakly entangled states have near-degenerate singular values of M,
+whose derivative terms carry 1/(s_i^2 - s_j^2): there the two LAPACK drivers
+themselves disagree by 1e-6 relative, and the bar is three times that
+measured spread (and never tighter than 1e-8).  FP32 mode: 1e-6.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+import synth
+from oracle.adjoint import energy_and_grad
+from oracle.ctmrg import CTM as OCTM, env_to_flat
+
+pytestmark = pytest.mark.gpu
+
+H = synth.heisenberg_bond()
+
+
+@pytest.fixture(scope="module")
+def ctm_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_14414_amd as m
+    return m
+
+
+GRAD_CASES = [
+    # name, n_tensors, D, chi, pattern, kind, seed, converge sweeps, differentiated sweeps, calibrated bar
+    ("rand_1x1_D2_chi8", 1, 2, 8, [[0]], "uniform", 1, 80, 2, False),
+    ("np_2x2_D2_chi8", 4, 2, 8, [[0, 1], [2, 3]], "near_product", 5, 60, 1, True),
+    ("np_2x1_D3_chi12", 2, 3, 12, [[0, 1]], "near_product", 5, 60, 1, True),
+    ("np_2x2_D3_chi12", 4, 3, 12, [[0, 1], [2, 3]], "near_product", 5, 60, 1, True),
+]
+
+
+def _tensors(nt, D, kind, seed):
+    if kind == "near_product":
+        return synth.near_product_tensors(nt, 2, D, seed, 0.3)
+    return synth.site_tensors(nt, 2, D, seed, kind)
+
+
+def _converged(A, pattern, chi, sweeps):
+    o = OCTM(A, pattern, chi)
+    o.run(sweeps)
+    return o
+
+
+def _gesvd(M, full_matrices=False):
+    U, s, Vh = scipy.linalg.svd(M.detach().numpy(), full_matrices=False, lapack_driver="gesvd")
+    return torch.from_numpy(U), torch.from_numpy(s), torch.from_numpy(Vh)
+
+
+@pytest.mark.parametrize("name,nt,D,chi,pattern,dist,seed,conv,n,calibrated", GRAD_CASES)
+def test_energy_grad_matches_oracle(ctm_mod, monkeypatch, name, nt, D, chi, pattern, dist, seed, conv, n, calibrated):
+    A = _tensors(nt, D, dist, seed)
+    Ly, Lx = len(pattern), len(pattern[0])
+    terms = synth.heisenberg_terms(Lx, Ly)
+    o = _converged(A, pattern, chi, conv)
+    Eo, go, _ = energy_and_grad(A, pattern, chi, o.env, n, H, terms)
+    scale = go.abs().max().item()
+    bar = 1e-8 * max(1.0, scale)
+    if calibrated:
+        with monkeypatch.context() as mp:
+            mp.setattr(torch.linalg, "svd", _gesvd)
+            _, go2, _ = energy_and_grad(A, pattern, chi, o.env, n, H, terms)
+        bar = max(bar, 3 * (go2 - go).abs().max().item())
+    g = ctm_mod.CTM(A, pattern, chi)
+    g.set_env(env_to_flat(o.env, o.sites, chi))
+    E, grad = g.energy_grad(n, H, terms)
+    err = (grad.cpu() - go).abs().max().item()
+    print(f"{name}: E {E:.14f} |dE| {abs(E - Eo):.2e}; |dg|max {err:.2e} bar {bar:.2e} (|g|max {scale:.2e})")
+    assert abs(E - Eo) < 1e-10 * max(1.0, abs(Eo))
+    assert err <= bar
+
+
+def test_energy_grad_fp32_mode(ctm_mod):
+    name, nt, D, chi, pattern, dist, seed, conv, n, _ = GRAD_CASES[0]
+    A = _tensors(nt, D, dist, seed)
+    terms = synth.heisenberg_terms(1, 1)
+    o = _converged(A, pattern, chi, conv)
+    Eo, go, _ = energy_and_grad(A, pattern, chi, o.env, n, H, terms)
+    g = ctm_mod.CTM(A, pattern, chi, precision="fp32")
+    g.set_env(env_to_flat(o.env, o.sites, chi))
+    E, grad = g.energy_grad(n, H, terms)
+    err = (grad.cpu() - go).abs().max().item()
+    print(f"fp32: |dE| {abs(E - Eo):.2e} |dg|max {err:.2e}")
+    assert abs(E - Eo) < 1e-6
+    assert err <= 1e-6 * max(1.0, go.abs().max().item())
+
+
+def test_energy_grad_central_differences(ctm_mod):
+    """Central differences (h = 1e-6) of the library's own energy on 6 seeded entries."""
+    name, nt, D, chi, pattern, dist, seed, conv, n, _ = GRAD_CASES[1]
+    A = _tensors(nt, D, dist, seed)
+    terms = synth.heisenberg_terms(2, 2)
+    o = _converged(A, pattern, chi, conv)
+    env0 = env_to_flat(o.env, o.sites, chi)
+    g = ctm_mod.CTM(A, pattern, chi)
+    g.set_env(env0)
+    E, grad = g.energy_grad(n, H, terms)
+    grad = grad.cpu()
+    rng = np.random.default_rng(3)
+    flat = torch.as_tensor(A).reshape(-1)
+    h = 1e-6
+    for idx in rng.choice(flat.numel(), 6, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            Ap = flat.clone()
+            Ap[idx] += sgn * h
+            g.set_tensors(Ap.reshape(A.shape))
+            g.set_env(env0)
+            g.sweep(n)
+            vals.append(g.energy(H, terms))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        gi = grad.reshape(-1)[idx].item()
+        print(f"entry {idx}: fd {fd:.10f} grad {gi:.10f}")
+        assert abs(fd - gi) < 1e-6 * max(1.0, abs(gi))
+
+
+def test_autograd_function(ctm_mod):
+    name, nt, D, chi, pattern, dist, seed, conv, n, _ = GRAD_CASES[0]
+    A = _tensors(nt, D, dist, seed)
+    terms = synth.heisenberg_terms(1, 1)
+    o = _converged(A, pattern, chi, conv)
+    env0 = env_to_flat(o.env, o.sites, chi)
+    g = ctm_mod.CTM(A, pattern, chi)
+    g.set_env(env0)
+    E_ref, grad_ref = g.energy_grad(n, H, terms)
+    g.set_env(env0)
+    At = torch.as_tensor(A, dtype=torch.float64).cuda().requires_grad_(True)
+    E = ctm_mod.CTMEnergy.apply(At, g, n, H, terms)
+    (2.0 * E).backward()
+    assert abs(E.item() - E_ref) < 1e-14
+    assert torch.allclose(At.grad, 2.0 * grad_ref, rtol=0, atol=1e-14)
