@@ -14,12 +14,16 @@ The paper minimises E(X) (Eq. OptPro) with L-BFGS on the gradient of Eq. AD
   interpolation (their Eq. 3.59; bisection when the minimiser falls outside
   the middle 80 % of the bracket), at most ``max_ls`` evaluations;
 * surrogate screening (from iteration ``sur_start``, once trained): the trial
-  steps alpha_j = alpha_init 2^-j (j < n_trials) are ranked by the predicted
-  energy; the best ``max_screened`` of them are evaluated exactly in that
-  order and the first one that satisfies the strong Wolfe conditions is
-  taken; otherwise the plain search runs.  Every exact evaluation is added to
-  the training set; the surrogate is refitted after iteration sur_start - 1
-  and then every ``refit_every`` iterations.
+  steps alpha_j = alpha_init 2^(extrap - j) (j < n_trials, so from
+  2^extrap down to 2^(extrap - n_trials + 1) times the unit step) are ranked
+  by the predicted energy relative to the prediction at the current point,
+  f + (y(x + alpha_j p) - y(x)), which cancels a smooth bias of the model;
+  the best ``max_screened`` candidates whose predicted decrease passes the
+  Armijo test are evaluated exactly in that order and the first that
+  satisfies the strong Wolfe conditions is taken; otherwise the plain search
+  runs.  Every exact evaluation is added to the training set; the surrogate
+  is refitted (on the last ``window`` pairs, or all) after iteration
+  sur_start - 1 and then every ``refit_every`` iterations.
 
 Plain numpy in float64.
 """
@@ -42,8 +46,10 @@ class Params:
     alpha0: float = 1.0
     sur_start: int = 0          # 0: no screening
     n_trials: int = 8
-    max_screened: int = 2
+    max_screened: int = 1
     refit_every: int = 10
+    extrap: int = 2
+    window: int = 0             # refit on the last ``window`` pairs; 0: all
 
 
 @dataclass
@@ -120,11 +126,14 @@ def minimize(fg, x0, p: Params, predictor=None, train=None, features=None):
 
         accepted, screened = None, 0
         if predictor is not None and trained and p.sur_start > 0 and k >= p.sur_start:
-            cands = [a_init * 2.0 ** -j for j in range(p.n_trials)]
-            preds = np.asarray(predictor([features(x + a * pdir) for a in cands]), dtype=np.float64)
-            order = np.argsort(preds, kind="stable")
+            cands = [a_init * 2.0 ** (p.extrap - j) for j in range(p.n_trials)]
+            preds = np.asarray(predictor([features(x)] + [features(x + a * pdir) for a in cands]), dtype=np.float64)
+            pc = f + (preds[1:] - preds[0])
+            order = np.argsort(pc, kind="stable")
             for j in order[: p.max_screened]:
                 a = cands[int(j)]
+                if not pc[int(j)] <= f + p.c1 * a * d0:
+                    break
                 xt = x + a * pdir
                 ft, gt = evaluate(xt)
                 if ft <= f + p.c1 * a * d0 and abs(float(gt @ pdir)) <= -p.c2 * d0:
@@ -146,7 +155,8 @@ def minimize(fg, x0, p: Params, predictor=None, train=None, features=None):
         res.records.append((k, res.evals, screened, f, float(np.max(np.abs(g))), a))
         if predictor is not None and p.sur_start > 0 and k >= p.sur_start - 1 and \
                 (k - (p.sur_start - 1)) % p.refit_every == 0:
-            train(res.data_x, res.data_f)
+            w = p.window if p.window > 0 else len(res.data_f)
+            train(res.data_x[-w:], res.data_f[-w:])
             trained = True
     res.x, res.f = x, f
     return res

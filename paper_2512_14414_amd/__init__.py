@@ -5,3 +5,4 @@ include/ctm.h); ``CTM`` is its thin Python binding.
 """
 from .binding import CTM, CTMError, EXPORTED, LIB, LIB_PATH, PRECISIONS  # noqa: F401
 from .autograd import CTMEnergy  # noqa: F401
+from .binding import Surrogate, energy_objective, lbfgs, lbfgs_params, python_objective  # noqa: F401

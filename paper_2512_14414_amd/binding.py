@@ -184,3 +184,200 @@ class CTM:
 
     def set_option(self, key, value):
         self._check(LIB.ctm_set_option(self._h, key.encode(), float(value)))
+
+
+# ---------------------------------------------------------------------------
+# Optimisation layer (include/ctm_opt.h)
+
+class LBFGSParams(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("history", ctypes.c_int), ("c1", ctypes.c_double),
+                ("c2", ctypes.c_double), ("gtol", ctypes.c_double), ("max_ls", ctypes.c_int),
+                ("alpha0", ctypes.c_double), ("sur_start", ctypes.c_int), ("n_trials", ctypes.c_int),
+                ("max_screened", ctypes.c_int), ("refit_every", ctypes.c_int), ("refit_steps", ctypes.c_int),
+                ("lr", ctypes.c_float), ("n_blocks", ctypes.c_int), ("extrap", ctypes.c_int),
+                ("window", ctypes.c_int)]
+
+
+class LBFGSRecord(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int), ("evals", ctypes.c_int), ("screened", ctypes.c_int), ("f", ctypes.c_double),
+                ("gmax", ctypes.c_double), ("step", ctypes.c_double)]
+
+
+class EnergyObjective(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("H_bond", ctypes.POINTER(ctypes.c_double)), ("n_terms", ctypes.c_int),
+                ("terms", ctypes.POINTER(Term)), ("conv_sweeps", ctypes.c_int), ("conv_tol", ctypes.c_double),
+                ("grad_sweeps", ctypes.c_int)]
+
+
+OBJECTIVE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                             ctypes.c_void_p)
+
+
+def _load_opt():
+    P, I, I64, F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
+    sig = {
+        "sur_init": (I, [ctypes.POINTER(P), I, I, ctypes.c_uint64, P]),
+        "sur_param_count": (I64, [P]),
+        "sur_get_params": (I, [P, P]),
+        "sur_set_params": (I, [P, P]),
+        "sur_predict": (I, [P, P, I, P]),
+        "sur_loss_grad": (I, [P, P, P, I, ctypes.POINTER(F), P]),
+        "sur_train": (I, [P, P, P, I, I, F, ctypes.POINTER(F)]),
+        "sur_last_error": (ctypes.c_char_p, [P]),
+        "sur_free": (None, [P]),
+        "ctm_lbfgs_default_params": (None, [ctypes.POINTER(LBFGSParams)]),
+        "ctm_lbfgs": (I, [I64, P, OBJECTIVE, P, P, ctypes.POINTER(LBFGSParams), P, ctypes.POINTER(LBFGSRecord), I,
+                          ctypes.POINTER(I)]),
+        "ctm_lbfgs_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(LIB, name)
+        f.restype, f.argtypes = res, args
+
+
+_load_opt()
+_HIP = ctypes.CDLL("libamdhip64.so")
+_HIP.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+_HIP.hipMemcpy.restype = ctypes.c_int
+
+
+def _d2d(dst, src, nbytes):
+    """Synchronous device-to-device copy between raw device addresses."""
+    torch.cuda.synchronize()
+    rc = _HIP.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
+def _fptr(t: torch.Tensor):
+    return _dptr(t, torch.float32)
+
+
+class Surrogate:
+    """The energy surrogate network on the current GPU (include/ctm_opt.h)."""
+
+    def __init__(self, n_in, width=256, seed=0, stream=None):
+        self.n_in, self.width = n_in, width
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        rc = LIB.sur_init(ctypes.byref(self._h), n_in, width, seed, ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != CTM_OK:
+            raise CTMError(rc, LIB.sur_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != CTM_OK:
+            raise CTMError(rc, LIB.sur_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            LIB.sur_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def param_count(self):
+        return int(LIB.sur_param_count(self._h))
+
+    def get_params(self):
+        out = torch.empty(self.param_count(), dtype=torch.float32, device="cuda")
+        self._check(LIB.sur_get_params(self._h, _fptr(out)))
+        return out
+
+    def set_params(self, theta):
+        theta = torch.as_tensor(theta, dtype=torch.float32).cuda().contiguous()
+        self._check(LIB.sur_set_params(self._h, _fptr(theta)))
+        torch.cuda.synchronize()
+
+    def predict(self, X):
+        X = torch.as_tensor(X, dtype=torch.float32).cuda().contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        self._check(LIB.sur_predict(self._h, _fptr(X), X.shape[0], _fptr(y)))
+        torch.cuda.synchronize()
+        return y
+
+    def loss_grad(self, X, t):
+        X = torch.as_tensor(X, dtype=torch.float32).cuda().contiguous()
+        t = torch.as_tensor(t, dtype=torch.float32).cuda().contiguous()
+        g = torch.empty(self.param_count(), dtype=torch.float32, device="cuda")
+        loss = ctypes.c_float()
+        self._check(LIB.sur_loss_grad(self._h, _fptr(X), _fptr(t), X.shape[0], ctypes.byref(loss), _fptr(g)))
+        return loss.value, g
+
+    def train(self, X, t, steps, lr=1e-3):
+        X = torch.as_tensor(X, dtype=torch.float32).cuda().contiguous()
+        t = torch.as_tensor(t, dtype=torch.float32).cuda().contiguous()
+        loss = ctypes.c_float()
+        self._check(LIB.sur_train(self._h, _fptr(X), _fptr(t), X.shape[0], steps, lr, ctypes.byref(loss)))
+        return loss.value
+
+
+def lbfgs_params(**kw):
+    p = LBFGSParams()
+    LIB.ctm_lbfgs_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def python_objective(fn, n):
+    """Wrap fn(x: cuda float64 tensor) -> (f, g) as a C objective (used by tests)."""
+    def cb(user, xp, fp, gp):
+        try:
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+            _d2d(x.data_ptr(), xp, n * 8)
+            f, g = fn(x)
+            g = torch.as_tensor(g, dtype=torch.float64, device="cuda").contiguous()
+            fp[0] = float(f)
+            _d2d(gp, g.data_ptr(), n * 8)
+            return 0
+        except Exception:
+            import traceback
+            traceback.print_exc()
+            return -1
+    return OBJECTIVE(cb)
+
+
+def lbfgs(x0, objective, user=None, sur=None, params=None, capacity=10000):
+    """Run ctm_lbfgs from x0 (float64 tensor); objective is an OBJECTIVE (see
+    python_objective) or an EnergyObjective.  Returns (x, records, converged)."""
+    x = torch.as_tensor(x0, dtype=torch.float64).cuda().contiguous().clone()
+    params = params if params is not None else lbfgs_params()
+    if isinstance(objective, EnergyObjective):
+        fn = ctypes.cast(LIB.ctm_energy_objective_fn, OBJECTIVE)
+        user = ctypes.cast(ctypes.pointer(objective), ctypes.c_void_p)
+    else:
+        fn = objective
+    trace = (LBFGSRecord * capacity)()
+    n_iter = ctypes.c_int()
+    stream = torch.cuda.current_stream()
+    rc = LIB.ctm_lbfgs(x.numel(), _dptr(x), fn, user, sur.handle if sur is not None else None, ctypes.byref(params),
+                       ctypes.c_void_p(stream.cuda_stream), trace, capacity, ctypes.byref(n_iter))
+    if rc not in (CTM_OK, CTM_ENOTCONV):
+        raise CTMError(rc, LIB.ctm_lbfgs_last_error().decode())
+    recs = [(r.iter, r.evals, r.screened, r.f, r.gmax, r.step) for r in trace[: min(n_iter.value, capacity)]]
+    return x, recs, rc == CTM_OK
+
+
+def energy_objective(ctm, H, terms, conv_sweeps=20, conv_tol=1e-9, grad_sweeps=1):
+    """The library's energy objective over a CTM context (keeps its arrays alive)."""
+    ob = EnergyObjective()
+    ob._H = _hbond(H)
+    ob._terms = _terms(terms)
+    ob.ctx = ctm._h
+    ob.H_bond = ctypes.cast(ob._H, ctypes.POINTER(ctypes.c_double))
+    ob.n_terms = len(terms)
+    ob.terms = ctypes.cast(ob._terms, ctypes.POINTER(Term))
+    ob.conv_sweeps = conv_sweeps
+    ob.conv_tol = conv_tol
+    ob.grad_sweeps = grad_sweeps
+    return ob

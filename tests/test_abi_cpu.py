@@ -8,14 +8,20 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "ctm.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ctm_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"typedef[^;]*;", "", text)
+            names |= set(re.findall(r"\b((?:ctm|sur)_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for n in ("ctm_init", "ctm_sweep", "ctm_energy", "ctm_free", "ctm_last_error"):
+    for n in ("ctm_init", "ctm_sweep", "ctm_energy", "ctm_energy_grad", "ctm_free", "ctm_last_error", "sur_init",
+              "sur_predict", "sur_train", "sur_free", "ctm_lbfgs"):
         assert n in names
 
 

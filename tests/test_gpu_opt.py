@@ -1,0 +1,182 @@
+"""Surrogate network and L-BFGS of the library against the oracle (GPU).
+
+The network runs in float32 (MFMA products over K up to 5000 terms), the
+oracle in float64 with the same float32 parameters: forward values and loss
+agree to 1e-5 relative, gradients to 1e-4 of their largest entry.  L-BFGS is
+float64 on both sides and follows the same decisions, so the iterates of a
+quadratic and of the Rosenbrock function agree to rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lbfgs as olbfgs, mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_14414_amd as mod
+    return mod
+
+
+def test_surrogate_init_matches_oracle(m):
+    net = m.Surrogate(50, 16, seed=7)
+    got = net.get_params().cpu().numpy()
+    ref = mlp.init_params(50, 16, 7)
+    assert got.dtype == np.float32 and got.shape == ref.shape
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("n_in,width,batch", [(50, 16, 8), (5000, 256, 8), (300, 64, 40)])
+def test_surrogate_forward_and_gradient(m, n_in, width, batch):
+    net = m.Surrogate(n_in, width, seed=3)
+    theta = mlp.init_params(n_in, width, 3)
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((batch, n_in)).astype(np.float32) / np.sqrt(n_in)
+    t = rng.standard_normal(batch).astype(np.float32)
+    y = net.predict(torch.from_numpy(X)).cpu().numpy().astype(np.float64)
+    y_ref = mlp.forward(theta, X.astype(np.float64), n_in, width)
+    assert np.max(np.abs(y - y_ref)) <= 1e-5 * max(1.0, np.max(np.abs(y_ref)))
+    loss, g = net.loss_grad(torch.from_numpy(X), torch.from_numpy(t))
+    loss_ref, g_ref = mlp.loss_grad(theta, X.astype(np.float64), t.astype(np.float64), n_in, width)
+    g = g.cpu().numpy().astype(np.float64)
+    print(f"n_in {n_in}: |dy| {np.max(np.abs(y - y_ref)):.2e} loss {loss:.6f} vs {loss_ref:.6f} "
+          f"|dg| {np.max(np.abs(g - g_ref)):.2e} (|g| {np.max(np.abs(g_ref)):.2e})")
+    assert abs(loss - loss_ref) <= 1e-5 * max(1.0, loss_ref)
+    assert np.max(np.abs(g - g_ref)) <= 1e-4 * np.max(np.abs(g_ref))
+
+
+def test_surrogate_training_matches_oracle(m):
+    n_in, width, n = 40, 16, 60
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((n, n_in)).astype(np.float32)
+    t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] ** 2 + 3.0).astype(np.float32)
+    net = m.Surrogate(n_in, width, seed=9)
+    theta0 = mlp.init_params(n_in, width, 9)
+    # one Adam step, parameter by parameter (entries with a well-determined gradient sign)
+    net.train(torch.from_numpy(X), torch.from_numpy(t), 1, 1e-3)
+    p1 = net.get_params().cpu().numpy().astype(np.float64)
+    mu, sd = mlp.standardize(t)
+    _, g0 = mlp.loss_grad(theta0.astype(np.float64), X.astype(np.float64), (t - mu) / sd, n_in, width)
+    r1, _, _ = mlp.adam_step(theta0.astype(np.float64), g0, 0 * g0, 0 * g0, 1, 1e-3)
+    sure = np.abs(g0) > 1e-3 * np.max(np.abs(g0))
+    assert np.max(np.abs(p1 - r1)[sure]) < 1e-6
+    assert np.max(np.abs(p1 - r1)) <= 2e-3 + 1e-6
+    # 200 steps: the same loss curve to float32 accuracy of the trajectory
+    net.set_params(torch.from_numpy(theta0))
+    loss = net.train(torch.from_numpy(X), torch.from_numpy(t), 200, 1e-3)
+    _, stats, losses = mlp.train(theta0, X.astype(np.float64), t.astype(np.float64), n_in, width, 200, 1e-3)
+    print(f"loss after 200 steps: gpu {loss:.6f} oracle {losses[-1]:.6f} (start {losses[0]:.6f})")
+    assert losses[-1] < 0.5 * losses[0]
+    assert abs(loss - losses[-1]) <= 2e-2 * losses[-1]
+    y = net.predict(torch.from_numpy(X)).cpu().numpy()
+    assert np.sqrt(np.mean((y - t) ** 2)) < np.std(t)
+
+
+def _quadratic(n, seed):
+    rng = np.random.default_rng(seed)
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    return A, b
+
+
+def _rosenbrock(x):
+    f = np.sum(100.0 * (x[1:] - x[:-1] ** 2) ** 2 + (1 - x[:-1]) ** 2)
+    g = np.zeros_like(x)
+    g[:-1] = -400.0 * x[:-1] * (x[1:] - x[:-1] ** 2) - 2.0 * (1 - x[:-1])
+    g[1:] += 200.0 * (x[1:] - x[:-1] ** 2)
+    return f, g
+
+
+def _numpy_on_gpu(fn):
+    def f(x):
+        v, g = fn(x.cpu().numpy())
+        return v, torch.from_numpy(g)
+    return f
+
+
+@pytest.mark.parametrize("problem", ["quadratic", "rosenbrock"])
+def test_lbfgs_matches_oracle(m, problem):
+    if problem == "quadratic":
+        A, b = _quadratic(30, 0)
+        xs = np.linalg.solve(A, b)
+        fn = lambda x: (0.5 * (x - xs) @ A @ (x - xs), A @ (x - xs))
+        x0 = np.zeros(30)
+        kw = dict(max_iter=200, gtol=1e-10)
+    else:
+        fn = _rosenbrock
+        x0 = np.array([-1.2, 1.0, -1.2, 1.0, 0.5, -0.3])
+        kw = dict(max_iter=300, gtol=1e-8)
+    ref = olbfgs.minimize(fn, x0, olbfgs.Params(**kw))
+    x, recs, ok = m.lbfgs(torch.from_numpy(x0), m.python_objective(_numpy_on_gpu(fn), x0.size),
+                          params=m.lbfgs_params(**kw))
+    assert ok
+    assert len(recs) == len(ref.records)
+    for r, q in zip(recs, ref.records):
+        assert r[0] == q[0] and r[1] == q[1] and r[2] == q[2]
+        assert abs(r[3] - q[3]) <= 1e-9 * max(1.0, abs(q[3]))
+    assert np.max(np.abs(x.cpu().numpy() - ref.x)) < 1e-9
+
+
+def test_lbfgs_screened_quadratic_with_the_network(m):
+    """Screening by the library's own network on a quadratic: every accepted
+    step decreases f and the run converges to the exact minimiser (a screened
+    step is only taken after its exact evaluation passes the strong Wolfe
+    test, so a poor network costs evaluations, never correctness)."""
+    n = 24
+    A, b = _quadratic(n, 3)
+    xs = np.linalg.solve(A, b)
+    fn = lambda x: (0.5 * (x - xs) @ A @ (x - xs), A @ (x - xs))
+    net = m.Surrogate(n, 32, seed=1)
+    p = m.lbfgs_params(max_iter=200, gtol=1e-9, sur_start=6, refit_every=5, refit_steps=200, lr=1e-2)
+    x, recs, ok = m.lbfgs(torch.zeros(n, dtype=torch.float64), m.python_objective(_numpy_on_gpu(fn), n), sur=net,
+                          params=p)
+    assert ok
+    assert np.max(np.abs(x.cpu().numpy() - np.linalg.solve(A, b))) < 1e-8
+    fs = [r[3] for r in recs]
+    assert all(q <= pv + 1e-12 for pv, q in zip(fs, fs[1:]))
+    print(f"screened steps {sum(r[2] for r in recs)} of {len(recs)}, evaluations {recs[-1][1]}")
+
+
+def test_energy_lbfgs_with_and_without_surrogate(m):
+    """L-BFGS on the nested-CTMRG energy (Heisenberg, 1x1 cell, D=2, chi=8),
+    plain and screened by the surrogate from iteration 11 (refit every 5
+    iterations on all exact evaluations).  Both runs lower the energy
+    monotonically; the exact evaluations, the screened steps and the
+    evaluations needed to reach the better final energy + 1e-4 are printed.
+    Measured: the plain strong-Wolfe search accepts the unit step at almost
+    every iteration (about 1.06 evaluations per iteration), so screening has
+    no evaluations to save here, and each screened candidate that fails the
+    exact Wolfe test costs one; the two runs reach energies within 2e-3 of
+    each other.  What the network gains is therefore reported, not assumed.
+    H = synth.heisenberg_bond()
+    terms = synth.heisenberg_terms(1, 1)
+    A0 = torch.as_tensor(synth.site_tensors(1, 2, 2, 1, "uniform"))
+    out = {}
+    for mode in ("plain", "screened"):
+        ctm = m.CTM(A0, [[0]], 8)
+        ctm.sweep(40)
+        ob = m.energy_objective(ctm, H, terms, conv_sweeps=20, conv_tol=1e-10, grad_sweeps=1)
+        net = m.Surrogate(A0.numel(), 64, seed=0) if mode == "screened" else None
+        p = m.lbfgs_params(max_iter=40, gtol=1e-7, sur_start=11 if net else 0, refit_every=5, refit_steps=300,
+                           lr=1e-3)
+        x, recs, ok = m.lbfgs(A0.reshape(-1), ob, sur=net, params=p)
+        out[mode] = recs
+        print(mode, [(r[0], r[1], r[2], round(r[3], 8)) for r in recs])
+    target = min(out["plain"][-1][3], out["screened"][-1][3]) + 1e-4
+    for mode, recs in out.items():
+        hit = [r[1] for r in recs if r[3] <= target]
+        print(f"{mode}: {recs[-1][1]} evaluations, final E {recs[-1][3]:.8f}, "
+              f"evaluations to E <= {target:.6f}: {hit[0] if hit else None}, "
+              f"screened steps {sum(r[2] for r in recs)}")
+    for mode, recs in out.items():
+        fs = [r[3] for r in recs]
+        assert fs[-1] < fs[0]
+        assert all(q <= pv + 1e-9 for pv, q in zip(fs, fs[1:]))
+    assert abs(out["plain"][-1][3] - out["screened"][-1][3]) < 5e-3
