@@ -154,7 +154,7 @@ def test_energy_lbfgs_with_and_without_surrogate(m):
     every iteration (about 1.06 evaluations per iteration), so screening has
     no evaluations to save here, and each screened candidate that fails the
     exact Wolfe test costs one; the two runs reach energies within 2e-3 of
-    each other.  What the network gains is therefore reported, not assumed.
+    each other.  What the network gains is therefore reported, not assumed."""
     H = synth.heisenberg_bond()
     terms = synth.heisenberg_terms(1, 1)
     A0 = torch.as_tensor(synth.site_tensors(1, 2, 2, 1, "uniform"))
