@@ -26,6 +26,7 @@
 #include "../../include/ctm.h"
 #include "engine.h"
 #include "kernels.h"
+#include "qr_kernels.h"
 
 using namespace ctm;
 
@@ -366,32 +367,91 @@ void half_systems(ctm_ctx* c, int f, int I, int J, double* Nout, double* Sout) {
   }
 }
 
+// Batched Householder QR in place (qr_kernels.hip): matrix b is A + b*stride
+// with element (i, j) at i*rs + j*cs; keeps tau and the T factor of every
+// panel for applying Q later.
+struct HQR {
+  double* A = nullptr;
+  int64_t m = 0, n = 0, k = 0, rs = 0, cs = 0, stride = 0;
+  int batch = 0, nb = 16;
+  int64_t npanel = 0;
+  DBuf tau, T;
+  int64_t tstride() const { return npanel * nb * nb; }
+};
+
+// C_b[j0:m, c0:c0+ncols] <- H_p^T C_b (trans) or H_p C_b for the block
+// reflector H_p = I - V T V^T of panel p: C <- C - V (Y^T C), two FP64 MFMA products.
+void hqr_panel_apply(Dev& dev, const HQR& q, int64_t p, double* C, int64_t crs, int64_t ccs, int64_t cstride,
+                     int64_t c0, int64_t ncols, bool trans) {
+  const int64_t j0 = p * q.nb, L = q.m - j0;
+  const int nbp = (int)std::min<int64_t>(q.nb, q.k - j0);
+  if (ncols <= 0 || L <= 0) return;
+  const int64_t nb = q.nb, B = q.batch;
+  DBuf V(&dev, (size_t)B * L * nb * 8), Y(&dev, (size_t)B * L * nb * 8), Z(&dev, (size_t)B * nb * ncols * 8);
+  HIP_CHECK(qrk::launch_build_vy(q.A, q.rs, q.cs, q.stride, q.m, j0, nbp, q.nb, (const double*)q.T.p + p * nb * nb,
+                                 q.tstride(), trans, (double*)V.p, (double*)Y.p, q.batch, dev.stream));
+  TRef Vv{V.p, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
+  TRef Yv{Y.p, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
+  TRef Cv{C + j0 * crs + c0 * ccs, T_F64, {B, L, ncols}, {cstride, crs, ccs}, "brn"};
+  TRef Zv{Z.p, T_F64, {B, nb, ncols}, {nb * ncols, ncols, 1}, "bcn"};
+  contract(dev, ctmk::MODE_F64, Zv, Yv, Cv);
+  contract(dev, ctmk::MODE_F64, Cv, Vv, Zv, -1.0, 1);
+}
+
+void hqr_factor(Dev& dev, HQR& q) {
+  q.k = std::min(q.m, q.n);
+  q.nb = qrk::panel_width(q.m);
+  q.npanel = (q.k + q.nb - 1) / q.nb;
+  q.tau = DBuf(&dev, (size_t)std::max<int64_t>(1, q.batch * q.k) * 8);
+  q.T = DBuf(&dev, (size_t)std::max<int64_t>(1, q.batch * q.tstride()) * 8);
+  for (int64_t p = 0; p < q.npanel; ++p) {
+    const int64_t j0 = p * q.nb;
+    const int nbp = (int)std::min<int64_t>(q.nb, q.k - j0);
+    double* Tp = (double*)q.T.p + p * q.nb * q.nb;
+    HIP_CHECK(qrk::launch_panel(q.A, q.rs, q.cs, q.stride, q.m, q.n, j0, q.batch, (double*)q.tau.p, q.k, Tp,
+                                q.tstride(), dev.stream));
+    hqr_panel_apply(dev, q, p, q.A, q.rs, q.cs, q.stride, j0 + nbp, q.n - (j0 + nbp), true);
+  }
+}
+
+// C_b <- Q_b C_b (trans: Q_b^T C_b) for the m x ncols matrices C + b*cstride
+// with element (i, j) at i*crs + j*ccs.
+void hqr_apply(Dev& dev, const HQR& q, double* C, int64_t crs, int64_t ccs, int64_t cstride, int64_t ncols, bool trans) {
+  for (int64_t t = 0; t < q.npanel; ++t) {
+    const int64_t p = trans ? t : q.npanel - 1 - t;
+    hqr_panel_apply(dev, q, p, C, crs, ccs, cstride, 0, ncols, trans);
+  }
+}
+
 // SVD of the r x r column-major matrices A[b] (stride r*r) by one-sided
 // Jacobi with QR preconditioning: A = Q R (Householder), the columns of
 // X = R^T are rotated until mutually orthogonal, X W = U_X diag(s), so that
 // A = (Q W) diag(s) U_X^T.  Starting from R^T instead of A cuts the number of
-// Jacobi sweeps about threefold on the graded spectra of CTMRG.  Outputs: all
+// Jacobi sweeps about threefold on the graded spectra of CTMRG.  The sweeps
+// are blocked: each launch treats one round of a tournament over blocks of
+// columns, one wave per block pair (see bjac_round_kernel).  Outputs: all
 // r singular values, descending, to sv[b]; the kmax leading left vectors to
 // U[b] and right vectors to Vk[b] (column-major r x kmax).  A is overwritten.
 int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double* sv, double* U, double* Vk) {
   Dev& dev = c->dev;
   const int64_t stride = r * r;
-  DBuf X(&dev, (size_t)batch * stride * 8), W(&dev, (size_t)batch * stride * 8), tau(&dev, (size_t)batch * r * 8),
+  DBuf X(&dev, (size_t)batch * stride * 8), W(&dev, (size_t)batch * stride * 8),
       rot(&dev, (size_t)batch * sizeof(int)), tiny2(&dev, (size_t)batch * 8);
-  RB_CHECK(rocsolver_dgeqrf_strided_batched(c->blas, (rocblas_int)r, (rocblas_int)r, A, (rocblas_int)r, stride,
-                                            (double*)tau.p, r, batch));
+  HQR qm;
+  qm.A = A; qm.m = r; qm.n = r; qm.rs = 1; qm.cs = r; qm.stride = stride; qm.batch = batch;
+  hqr_factor(dev, qm);
   HIP_CHECK(ctmk::launch_rt_from_qr(A, (double*)X.p, r, stride, batch, dev.stream));
   HIP_CHECK(ctmk::launch_identity((double*)W.p, r, stride, batch, dev.stream));
   HIP_CHECK(ctmk::launch_frob_tiny((const double*)X.p, stride, stride, batch, 2.2e-16, (double*)tiny2.p, dev.stream));
   const double tol = std::max(1e-15, 2.2e-16 * std::sqrt((double)r));
-  const int64_t rounds = r + (r & 1) - 1;
+  const int64_t rounds = ctmk::bjac_rounds(r);
   std::vector<int> h(batch);
   int sweep = 0;
   for (sweep = 1; sweep <= c->jacobi_max_sweeps; ++sweep) {
     HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, batch, dev.stream));
     for (int64_t t = 0; t < rounds; ++t)
-      HIP_CHECK(ctmk::launch_jacobi_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
-                                          (const double*)tiny2.p, (int*)rot.p, dev.stream));
+      HIP_CHECK(ctmk::launch_bjac_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
+                                        (const double*)tiny2.p, 1, (int*)rot.p, dev.stream));
     HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, batch * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
     HIP_CHECK(hipStreamSynchronize(dev.stream));
     bool any = false;
@@ -402,10 +462,7 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   // normalised columns of X W are the right vectors of A; the columns of W, times Q, the left ones
   HIP_CHECK(ctmk::launch_jacobi_finish((const double*)X.p, (const double*)W.p, r, stride, batch, kmax, sv, Vk, U,
                                        dev.stream));
-  for (int b = 0; b < batch; ++b)
-    RB_CHECK(rocsolver_dormqr(c->blas, rocblas_side_left, rocblas_operation_none, (rocblas_int)r, (rocblas_int)kmax,
-                              (rocblas_int)r, A + (size_t)b * stride, (rocblas_int)r, (double*)tau.p + (size_t)b * r,
-                              U + (size_t)b * r * kmax, (rocblas_int)r));
+  hqr_apply(dev, qm, U, 1, r, r * kmax, kmax, false);
   c->last_jacobi_sweeps = sweep;
   return sweep;
 }
@@ -415,10 +472,10 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
 // matrices (the site leg is the down leg of (I, J)).
 //
 // Rows of equal parity have equal shapes and are handled together.  N and S
-// are mn x kd (rows: right cut, columns: left cut a5a6), stored row-major, so
-// that the same memory is the column-major kd x mn matrix N^T.  Its LQ
-// factorisation N^T = L_n Q_n gives R_n = L_n^T of Eq. QRSVD (kd x r lower
-// trapezoidal L_n, r = min(kd, mn) = chi*D); then M = R_n R_s^T = L_n^T L_s,
+// are mn x kd (rows: right cut, columns: left cut a5a6), stored row-major and
+// factorised in place by the batched Householder QR (N = Q_n R_n, R_n r x kd,
+// r = min(kd, mn) = chi*D, Eq. QRSVD); L = R^T is kept column-major
+// (kd x r); then M = R_n R_s^T = L_n^T L_s,
 // M = U diag(s) V^T, P = R_s^T V w = L_s V w and Q = R_n^T U w = L_n U w with
 // w_k = s_k^(-1/2) for the chi largest s_k above cutoff * s_1 (zero
 // otherwise).  The QR is taken also when N is not tall: forming N S^T
@@ -426,7 +483,7 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
 // triangular factors preserve.
 //
 // While the tape records, all r singular triplets are kept together with the
-// singular vectors of rho = N S^T (U_rho = Q_n^T-applied U, V_rho likewise)
+// singular vectors of rho = N S^T (U_rho = Q_n [U; 0], V_rho = Q_s [V; 0])
 // and the derivative of the block (N, S) -> (P, Q) is recorded (see
 // proj_backward).
 struct ProjRow {
@@ -457,15 +514,15 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
   const int64_t r = std::min(kd[0], mn[0]);
   for (int p = 0; p < 2; ++p)
     if (cnt[p] && std::min(kd[p], mn[p]) != r) throw Error(CTM_EINVAL, "rows of a column step differ in rank bound");
-  DBuf Nb[2], Sb[2];
-  for (int p = 0; p < 2; ++p) {
-    if (!cnt[p]) continue;
-    Nb[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * mn[p] * 8);
-    Sb[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * mn[p] * 8);
-  }
+  // per parity: N of the rows at 0..cnt-1, S at cnt..2cnt-1 (row-major mn x kd each)
+  DBuf NS[2];
+  for (int p = 0; p < 2; ++p)
+    if (cnt[p]) NS[p] = DBuf(&dev, (size_t)2 * cnt[p] * kd[p] * mn[p] * 8);
+  auto Nptr = [&](int p, int b) { return (double*)NS[p].p + (size_t)b * kd[p] * mn[p]; };
+  auto Sptr = [&](int p, int b) { return (double*)NS[p].p + (size_t)(cnt[p] + b) * kd[p] * mn[p]; };
   for (int I = 0; I < a; ++I) {
     int p = I & 1, b = I >> 1;
-    half_systems(c, f, I, J, (double*)Nb[p].p + (size_t)b * kd[p] * mn[p], (double*)Sb[p].p + (size_t)b * kd[p] * mn[p]);
+    half_systems(c, f, I, J, Nptr(p, b), Sptr(p, b));
   }
   TapePause pause(dev);   // the block below is one recorded operation
   std::vector<ProjRow> rows(rec ? a : 0);
@@ -475,8 +532,8 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
       ProjRow& R = rows[I];
       R.kd = kd[p]; R.mn = mn[p];
       const size_t sz = (size_t)kd[p] * mn[p];
-      R.Nadj = (double*)Nb[p].p + (size_t)b * sz;
-      R.Sadj = (double*)Sb[p].p + (size_t)b * sz;
+      R.Nadj = Nptr(p, b);
+      R.Sadj = Sptr(p, b);
       R.N = std::make_shared<DBuf>(&dev, sz * 8);
       R.S = std::make_shared<DBuf>(&dev, sz * 8);
       HIP_CHECK(hipMemcpyAsync(R.N->p, R.Nadj, sz * 8, hipMemcpyDeviceToDevice, dev.stream));
@@ -485,27 +542,22 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
       R.Q = Q64 + (size_t)I * maxkd * chi;
     }
   const int64_t kk = rec ? r : chi;   // singular vectors kept per row
-  DBuf Ln[2], Ls[2], tau[2];
+  HQR qr[2];
+  DBuf L[2];   // R^T of N (first cnt) and S (next cnt): column-major kd x r
   DBuf Mb(&dev, (size_t)a * r * r * 8), sv(&dev, (size_t)a * r * 8), Uk(&dev, (size_t)a * r * kk * 8),
       Vk(&dev, (size_t)a * r * kk * 8), w(&dev, (size_t)a * chi * 8);
   for (int p = 0; p < 2; ++p) {
     if (!cnt[p]) continue;
     const int64_t sz = kd[p] * mn[p];
+    qr[p].A = (double*)NS[p].p;
+    qr[p].m = mn[p]; qr[p].n = kd[p]; qr[p].rs = kd[p]; qr[p].cs = 1; qr[p].stride = sz; qr[p].batch = 2 * cnt[p];
+    hqr_factor(dev, qr[p]);
+    L[p] = DBuf(&dev, (size_t)2 * cnt[p] * kd[p] * r * 8);
+    HIP_CHECK(qrk::launch_extract_rt((const double*)NS[p].p, kd[p], 1, sz, kd[p], r, (double*)L[p].p, kd[p] * r,
+                                     2 * cnt[p], dev.stream));
     TRef Mv{(double*)Mb.p + (size_t)p * r * r, T_F64, {cnt[p], r, r}, {2 * r * r, 1, r}, "bij"};
-    Ln[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * r * 8);
-    Ls[p] = DBuf(&dev, (size_t)cnt[p] * kd[p] * r * 8);
-    tau[p] = DBuf(&dev, (size_t)cnt[p] * r * 8 * 2);
-    RB_CHECK(rocsolver_dgelqf_strided_batched(c->blas, (rocblas_int)kd[p], (rocblas_int)mn[p], (double*)Nb[p].p,
-                                              (rocblas_int)kd[p], sz, (double*)tau[p].p, r, cnt[p]));
-    RB_CHECK(rocsolver_dgelqf_strided_batched(c->blas, (rocblas_int)kd[p], (rocblas_int)mn[p], (double*)Sb[p].p,
-                                              (rocblas_int)kd[p], sz, (double*)tau[p].p + (size_t)cnt[p] * r, r,
-                                              cnt[p]));
-    HIP_CHECK(ctmk::launch_extract_lower((const double*)Nb[p].p, kd[p], kd[p], sz, (double*)Ln[p].p, r, kd[p] * r,
-                                         cnt[p], dev.stream));
-    HIP_CHECK(ctmk::launch_extract_lower((const double*)Sb[p].p, kd[p], kd[p], sz, (double*)Ls[p].p, r, kd[p] * r,
-                                         cnt[p], dev.stream));
-    TRef Lnv{Ln[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "bai"};
-    TRef Lsv{Ls[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "baj"};
+    TRef Lnv{L[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "bai"};
+    TRef Lsv{(double*)L[p].p + (size_t)cnt[p] * kd[p] * r, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "baj"};
     contract(dev, m, Mv, Lnv, Lsv);
   }
   // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
@@ -514,8 +566,8 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
   for (int I = 0; I < a; ++I) {
     int p = I & 1, b = I >> 1;
     const int64_t lfs = kd[p] * r;
-    TRef Lv{(void*)((double*)Ln[p].p + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
-    TRef Rv{(void*)((double*)Ls[p].p + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
+    TRef Lv{(void*)((double*)L[p].p + (size_t)b * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
+    TRef Rv{(void*)((double*)L[p].p + (size_t)(cnt[p] + b) * lfs), T_F64, {kd[p], r}, {1, kd[p]}, "ai"};
     TRef Uv{(double*)Uk.p + (size_t)I * r * kk, T_F64, {r, chi}, {1, r}, "ik"};
     TRef Vv{(double*)Vk.p + (size_t)I * r * kk, T_F64, {r, chi}, {1, r}, "ik"};
     const double* wI = (const double*)w.p + (size_t)I * chi;
@@ -523,31 +575,36 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     contract(dev, m, view(Q64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Lv, Uv, 1.0, 0, wI);
   }
   if (!rec) return;
-  // singular vectors of rho = N S^T: U_rho = Q_n-full^T [U; 0], V_rho likewise
-  for (int I = 0; I < a; ++I) {
-    int p = I & 1, b = I >> 1;
-    ProjRow& R = rows[I];
+  // singular vectors of rho = N S^T: U_rho = Q_n [U; 0], V_rho = Q_s [V; 0]
+  for (int p = 0; p < 2; ++p) {
+    if (!cnt[p]) continue;
     const int64_t mnp = mn[p];
-    const size_t sz = (size_t)kd[p] * mnp;
-    R.Ur = std::make_shared<DBuf>(&dev, (size_t)mnp * r * 8);
-    R.Vr = std::make_shared<DBuf>(&dev, (size_t)mnp * r * 8);
+    DBuf C(&dev, (size_t)2 * cnt[p] * mnp * r * 8);   // column-major mn x r, N rows then S rows
+    fill(dev, view(C.p, T_F64, {2 * cnt[p] * mnp * r}, "q"), 0.0);
+    for (int side = 0; side < 2; ++side)
+      for (int b = 0; b < cnt[p]; ++b) {
+        const int I = 2 * b + p;
+        const double* src = (double*)(side == 0 ? Uk : Vk).p + (size_t)I * r * kk;
+        double* dst = (double*)C.p + (size_t)(side * cnt[p] + b) * mnp * r;
+        copy_into(dev, TRef{dst, T_F64, {r, r}, {1, mnp}, "ij"}, TRef{(void*)src, T_F64, {r, r}, {1, r}, "ij"});
+      }
+    hqr_apply(dev, qr[p], (double*)C.p, 1, mnp, mnp * r, r, false);
+    for (int b = 0; b < cnt[p]; ++b) {
+      ProjRow& R = rows[2 * b + p];
+      R.Ur = std::make_shared<DBuf>(&dev, (size_t)mnp * r * 8);
+      R.Vr = std::make_shared<DBuf>(&dev, (size_t)mnp * r * 8);
+      HIP_CHECK(hipMemcpyAsync(R.Ur->p, (double*)C.p + (size_t)b * mnp * r, (size_t)mnp * r * 8,
+                               hipMemcpyDeviceToDevice, dev.stream));
+      HIP_CHECK(hipMemcpyAsync(R.Vr->p, (double*)C.p + (size_t)(cnt[p] + b) * mnp * r, (size_t)mnp * r * 8,
+                               hipMemcpyDeviceToDevice, dev.stream));
+    }
+  }
+  for (int I = 0; I < a; ++I) {
+    ProjRow& R = rows[I];
     R.s = std::make_shared<DBuf>(&dev, (size_t)r * 8);
     R.w = std::make_shared<DBuf>(&dev, (size_t)chi * 8);
     HIP_CHECK(hipMemcpyAsync(R.s->p, (double*)sv.p + (size_t)I * r, r * 8, hipMemcpyDeviceToDevice, dev.stream));
     HIP_CHECK(hipMemcpyAsync(R.w->p, (double*)w.p + (size_t)I * chi, chi * 8, hipMemcpyDeviceToDevice, dev.stream));
-    for (int side = 0; side < 2; ++side) {
-      DBuf& H = side == 0 ? Nb[p] : Sb[p];
-      double* dst = (double*)(side == 0 ? R.Ur : R.Vr)->p;
-      const double* src = (double*)(side == 0 ? Uk : Vk).p + (size_t)I * r * kk;
-      const double* tv = (double*)tau[p].p + (size_t)(side == 0 ? 0 : cnt[p]) * r + (size_t)b * r;
-      fill(dev, view(dst, T_F64, {mnp * r}, "q"), 0.0);
-      TRef dv{dst, T_F64, {r, r}, {1, mnp}, "ij"};
-      TRef sv_{(void*)src, T_F64, {r, r}, {1, r}, "ij"};
-      copy_into(dev, dv, sv_);
-      RB_CHECK(rocsolver_dormlq(c->blas, rocblas_side_left, rocblas_operation_transpose, (rocblas_int)mnp,
-                                (rocblas_int)r, (rocblas_int)r, (double*)H.p + (size_t)b * sz, (rocblas_int)kd[p],
-                                (double*)tv, dst, (rocblas_int)mnp));
-    }
   }
   c->tape.custom([c, rows, r]() {
     for (const ProjRow& R : rows) proj_backward(c, R, r);

@@ -74,6 +74,10 @@ hipError_t launch_rt_from_qr(const double* A, double* X, int64_t n, int64_t stri
 hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int64_t stride, int batch, int64_t kmax,
                                 double* sv, double* U, double* Vk, hipStream_t s);
 
+hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
+                             const double* tiny2, int inner, int* rot, hipStream_t s);
+int64_t bjac_rounds(int64_t n);
+
 // reverse pass
 hipError_t launch_normalize_backward(int type, const NormList& Y, const NormList& Yb, int count, hipStream_t s);
 hipError_t launch_energy_backward(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms,

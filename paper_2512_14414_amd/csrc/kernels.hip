@@ -86,30 +86,54 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
       for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
 
   constexpr int PER = BM * BK / NT;   // elements per thread per operand per K step
+  // Each thread stages PER fixed (k-in-tile, row/column) positions of A and of
+  // B.  The K index of a position advances by BK per step; its split into
+  // (outer, inner) parts is carried along incrementally instead of divided.
+  int a_mm[PER], b_nn[PER], a_kq[PER], a_kr[PER], b_kq[PER], b_kr[PER];
+  int a_kk[PER], b_kk[PER];
+  const int kin = (int)g.k_in;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    if (AK) { a_kk[i] = e % BK; a_mm[i] = e / BK; } else { a_mm[i] = e % BM; a_kk[i] = e / BM; }
+    if (BN_FAST) { b_nn[i] = e % BN; b_kk[i] = e / BN; } else { b_kk[i] = e % BK; b_nn[i] = e / BK; }
+    a_kq[i] = a_kk[i] / kin; a_kr[i] = a_kk[i] - a_kq[i] * kin;
+    b_kq[i] = b_kk[i] / kin; b_kr[i] = b_kk[i] - b_kq[i] * kin;
+  }
+  T va[PER], vb[PER];
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int64_t ro = a_row[a_mm[i]];
+      const bool ok = ro != NONE && k0 + a_kk[i] < g.K;
+      va[i] = ok ? A[ro + (int64_t)a_kq[i] * g.a_k_o + (int64_t)a_kr[i] * g.a_k_i] : (T)0;
+      const int64_t co = b_col[b_nn[i]];
+      const bool okb = co != NONE && k0 + b_kk[i] < g.K;
+      vb[i] = okb ? B[co + (int64_t)b_kq[i] * g.b_k_o + (int64_t)b_kr[i] * g.b_k_i] : (T)0;
+    }
+  };
+  auto advance = [&]() {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      a_kr[i] += BK;
+      while (a_kr[i] >= kin) { a_kr[i] -= kin; ++a_kq[i]; }
+      b_kr[i] += BK;
+      while (b_kr[i] >= kin) { b_kr[i] -= kin; ++b_kq[i]; }
+    }
+  };
+  load_tiles(0);
   for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      int e = tid + i * NT;
-      int kk, mm;
-      if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      int64_t k = k0 + kk;
-      T v = 0;
-      int64_t ro = a_row[mm];
-      if (ro != NONE && k < g.K) v = A[ro + split_off(k, g.k_in, g.a_k_o, g.a_k_i)];
-      As[kk][mm] = to_lds<MODE>(v);
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      int e = tid + i * NT;
-      int kk, nn;
-      if (BN_FAST) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
-      int64_t k = k0 + kk;
-      T v = 0;
-      int64_t co = b_col[nn];
-      if (co != NONE && k < g.K) v = B[co + split_off(k, g.k_in, g.b_k_o, g.b_k_i)];
-      Bs[kk][nn] = to_lds<MODE>(v);
+      As[a_kk[i]][a_mm[i]] = to_lds<MODE>(va[i]);
+      Bs[b_kk[i]][b_nn[i]] = to_lds<MODE>(vb[i]);
     }
     __syncthreads();
+    // prefetch the next K tile into registers while the matrix cores work
+    if (k0 + BK < g.K) {
+      advance();
+      load_tiles(k0 + BK);
+    }
     if constexpr (MODE == MODE_F64) {
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
@@ -764,6 +788,201 @@ hipError_t launch_sub_sinv(const double* A, const double* B, int64_t rows, int64
   if (rows * chi <= 0) return hipSuccess;
   sub_sinv_kernel<<<grid_for(rows * chi), 256, 0, st>>>(A, B, rows, chi, s, w, out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block one-sided Jacobi: one round of the round-robin tournament over blocks
+// of BW columns.  One workgroup per block pair (2 BW columns of the n x n
+// column-major matrix A_b): it forms the Gram matrix G of the pair from the
+// columns (float64 dot products, rows staged through LDS in chunks), the
+// first wave runs cyclic two-sided Jacobi sweeps on G (at most ``inner``
+// sweeps, each pair rotated when |g_pq| > tol sqrt(g_pp g_qq) and both
+// columns are above the negligible size tiny2), accumulating the rotations in
+// R, and, if any was applied, the workgroup replaces the pair's columns of A
+// and V by A R and V R.  The number of rotations is added to rot[b].  The
+// pair threshold is the one of the scalar method, evaluated on dot products
+// of the current columns, so a round with no rotation anywhere certifies the
+// same orthogonality.
+constexpr int BJ_BW = 8;            // columns per block
+constexpr int BJ_C = 2 * BJ_BW;     // columns per pair
+constexpr int BJ_CHUNK = 448;       // rows staged per chunk (56 KB of LDS)
+constexpr int BJ_NT = 256;          // threads per workgroup
+
+// LDS traffic between the lanes of one wave: order the accesses without a
+// workgroup barrier (the other waves are not taking part).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
+                                                           int64_t stride, int round, double tol, const double* tiny2,
+                                                           int inner, int* rot) {
+  __shared__ double xs[BJ_CHUNK * BJ_C];   // staged rows [row][col]
+  __shared__ double G[BJ_C * BJ_C];
+  __shared__ double R[BJ_C * BJ_C];
+  __shared__ double cs[BJ_C / 2][2];
+  __shared__ int pr[BJ_C / 2][2];
+  __shared__ int nrot_s;
+  const int k = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  int64_t P, Q;
+  if (k == 0) { P = round; Q = np - 1; }
+  else { P = (round + k) % (np - 1); Q = (round - k + (np - 1)) % (np - 1); }
+  if (P >= nblk || Q >= nblk) return;
+  if (P > Q) { int64_t t = P; P = Q; Q = t; }
+  double* Ab = A + (int64_t)b * stride;
+  double* Vb = V + (int64_t)b * stride;
+  // global column of local column c, or -1 past the end of the matrix
+  const int64_t c0P = P * BJ_BW, c0Q = Q * BJ_BW;
+  auto gcol = [&](int c) -> int64_t {
+    const int64_t g = c < BJ_BW ? c0P + c : c0Q + (c - BJ_BW);
+    return g < n ? g : -1;
+  };
+  // Gram matrix: thread e < 136 owns upper-triangle entry (ea, eb)
+  constexpr int NE = BJ_C * (BJ_C + 1) / 2;
+  int ea = -1, eb = -1;
+  if (tid < NE) {
+    int rem = tid, a = 0;
+    while (rem >= BJ_C - a) { rem -= BJ_C - a; ++a; }
+    ea = a; eb = a + rem;
+  }
+  double acc = 0.0;
+  for (int64_t r0 = 0; r0 < n; r0 += BJ_CHUNK) {
+    const int rows = (int)((n - r0) < BJ_CHUNK ? (n - r0) : BJ_CHUNK);
+    // stage element e = c * CHUNK + i; groups of 7 loads in flight per thread
+    constexpr int PER = BJ_CHUNK * BJ_C / BJ_NT;   // 28
+    for (int u0 = 0; u0 < PER; u0 += 7) {
+      double v[7];
+#pragma unroll
+      for (int u = 0; u < 7; ++u) {
+        const int e = tid + (u0 + u) * BJ_NT, c = e / BJ_CHUNK, i = e - c * BJ_CHUNK;
+        const int64_t g = gcol(c);
+        v[u] = (g >= 0 && i < rows) ? Ab[g * n + r0 + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 7; ++u) {
+        const int e = tid + (u0 + u) * BJ_NT, c = e / BJ_CHUNK, i = e - c * BJ_CHUNK;
+        xs[i * BJ_C + c] = v[u];
+      }
+    }
+    __syncthreads();
+    if (ea >= 0) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = 0;
+      for (; i + 4 <= rows; i += 4) {
+        a0 += xs[i * BJ_C + ea] * xs[i * BJ_C + eb];
+        a1 += xs[(i + 1) * BJ_C + ea] * xs[(i + 1) * BJ_C + eb];
+        a2 += xs[(i + 2) * BJ_C + ea] * xs[(i + 2) * BJ_C + eb];
+        a3 += xs[(i + 3) * BJ_C + ea] * xs[(i + 3) * BJ_C + eb];
+      }
+      for (; i < rows; ++i) a0 += xs[i * BJ_C + ea] * xs[i * BJ_C + eb];
+      acc += (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+  }
+  if (ea >= 0) { G[ea * BJ_C + eb] = acc; G[eb * BJ_C + ea] = acc; }
+  for (int e = tid; e < BJ_C * BJ_C; e += BJ_NT) R[e] = (e / BJ_C == e % BJ_C) ? 1.0 : 0.0;
+  __syncthreads();
+  if (tid < 64) {
+    const int lane = tid;
+    const double t2 = tiny2[b];
+    int nrot = 0;
+    for (int sw = 0; sw < inner; ++sw) {
+      int sweep_rot = 0;
+      for (int rd = 0; rd < BJ_C - 1; ++rd) {
+        if (lane < BJ_C / 2) {
+          int p, q;
+          if (lane == 0) { p = rd; q = BJ_C - 1; }
+          else { p = (rd + lane) % (BJ_C - 1); q = (rd - lane + (BJ_C - 1)) % (BJ_C - 1); }
+          if (p > q) { int t = p; p = q; q = t; }
+          double al = G[p * BJ_C + p], be = G[q * BJ_C + q], ga = G[p * BJ_C + q];
+          double c = 1.0, sn = 0.0;
+          if (gcol(p) >= 0 && gcol(q) >= 0 && fmin(al, be) > t2 && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+            double zeta = (be - al) / (2.0 * ga);
+            double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = c * t;
+          }
+          pr[lane][0] = p; pr[lane][1] = q;
+          cs[lane][0] = c; cs[lane][1] = sn;
+        }
+        wave_sync();
+        int live = 0;
+        for (int j = 0; j < BJ_C / 2; ++j) live += cs[j][1] != 0.0;
+        if (live) {
+          sweep_rot += live;
+          // G <- J^T G (rows p, q), 8 pairs x 16 columns, 2 per lane
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            int u = lane + 64 * h, j = u / BJ_C, col = u % BJ_C;
+            int p = pr[j][0], q = pr[j][1];
+            double c = cs[j][0], sn = cs[j][1];
+            double gp = G[p * BJ_C + col], gq = G[q * BJ_C + col];
+            G[p * BJ_C + col] = c * gp - sn * gq;
+            G[q * BJ_C + col] = sn * gp + c * gq;
+          }
+          wave_sync();
+          // G <- G J and R <- R J (columns p, q)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            int u = lane + 64 * h, j = u / BJ_C, row = u % BJ_C;
+            int p = pr[j][0], q = pr[j][1];
+            double c = cs[j][0], sn = cs[j][1];
+            double gp = G[row * BJ_C + p], gq = G[row * BJ_C + q];
+            G[row * BJ_C + p] = c * gp - sn * gq;
+            G[row * BJ_C + q] = sn * gp + c * gq;
+            double rp = R[row * BJ_C + p], rq = R[row * BJ_C + q];
+            R[row * BJ_C + p] = c * rp - sn * rq;
+            R[row * BJ_C + q] = sn * rp + c * rq;
+          }
+        }
+        wave_sync();
+      }
+      nrot += sweep_rot;
+      if (sweep_rot == 0) break;
+    }
+    if (lane == 0) {
+      nrot_s = nrot;
+      if (nrot) atomicAdd(rot + b, nrot);
+    }
+  }
+  __syncthreads();
+  if (nrot_s == 0) return;
+  // columns of the pair <- columns R (A and V); a thread owns rows
+  for (int mat = 0; mat < 2; ++mat) {
+    double* M = mat == 0 ? Ab : Vb;
+    for (int64_t i = tid; i < n; i += BJ_NT) {
+      double row[BJ_C];
+#pragma unroll
+      for (int c = 0; c < BJ_C; ++c) {
+        const int64_t g = gcol(c);
+        row[c] = g >= 0 ? M[g * n + i] : 0.0;
+      }
+#pragma unroll 4
+      for (int c = 0; c < BJ_C; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < BJ_C; ++j) v += row[j] * R[j * BJ_C + c];
+        const int64_t g = gcol(c);
+        if (g >= 0) M[g * n + i] = v;
+      }
+    }
+  }
+}
+
+hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
+                             const double* tiny2, int inner, int* rot, hipStream_t s) {
+  const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
+  const int64_t np = nblk + (nblk & 1);
+  dim3 grid((unsigned)(np / 2), (unsigned)batch);
+  bjac_round_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, round, tol, tiny2, inner, rot);
+  return hipGetLastError();
+}
+
+int64_t bjac_rounds(int64_t n) {
+  const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
+  return nblk + (nblk & 1) - 1;
 }
 
 }  // namespace ctmk

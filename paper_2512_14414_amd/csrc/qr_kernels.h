@@ -1,0 +1,27 @@
+// Launch interface of the batched Householder QR kernels (qr_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qrk {
+
+// Panel width used for matrices of m rows (16, or 8 above 1024 rows).
+int panel_width(int64_t m);
+
+// Factorise the panel of columns j0 .. j0+nb-1 (nb = panel_width(m)) of every
+// matrix; writes tau[b*tau_stride + j] and the nb x nb T of the block
+// reflector (row-major) at T + b*T_stride.
+hipError_t launch_panel(double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m, int64_t n, int64_t j0, int batch,
+                        double* tau, int64_t tau_stride, double* T, int64_t T_stride, hipStream_t s);
+
+// Dense V (L x nb) and Y = V T (trans) or V T^T of the panel at (j0, j0), L = m - j0,
+// both row-major per matrix (stride L*nb), for C <- C - V (Y^T C).
+hipError_t launch_build_vy(const double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m, int64_t j0, int nbp,
+                           int nb, const double* T, int64_t T_stride, bool trans, double* V, double* Y, int batch,
+                           hipStream_t s);
+
+// Column-major n x k L_b = R_b^T (zero above the diagonal) of the factorised A_b.
+hipError_t launch_extract_rt(const double* A, int64_t rs, int64_t cs, int64_t stride, int64_t n, int64_t k, double* L,
+                             int64_t lstride, int batch, hipStream_t s);
+
+}  // namespace qrk

@@ -48,14 +48,29 @@ def gesvd_projectors(N, S, chi, cutoff):
     return (Rs.T @ Vh[:k].T) * w, (Rn.T @ U[:, :k]) * w, s
 
 
+def transposed_projectors(N, S, chi, cutoff):
+    """The oracle's projectors with the SVD taken of M^T (a different
+    bidiagonalisation, hence a different basis inside near-degenerate
+    singular subspaces)."""
+    Rn = torch.linalg.qr(N, mode="reduced")[1]
+    Rs = torch.linalg.qr(S, mode="reduced")[1]
+    Ut, s, Vth = torch.linalg.svd((Rn @ Rs.T).T.contiguous(), full_matrices=False)
+    U, Vh = Vth.T, Ut.T
+    k, w = truncated_inverse_sqrt(s, chi, cutoff)
+    return (Rs.T @ Vh[:k].T) * w, (Rn.T @ U[:, :k]) * w, s
+
+
 def rounding_spread(A, pattern, chi, sweeps, env0, so, Eo, terms):
     """Largest change of the oracle's corner spectra (and, if terms are given,
-    energy) under (i) the gesvd driver and (ii) when the start env0 is given,
-    a relative 1e-13 perturbation of it."""
-    o2 = OCTM(A, pattern, chi, env0=env0)
-    o2.run(sweeps, proj=gesvd_projectors)
-    ds = (corner_spectra(o2.env, chi) - so).abs().max().item()
-    de = abs(oenergy(o2, H, terms).item() - Eo) if terms else None
+    energy) under (i) the gesvd driver, (ii) the SVD of M^T and (iii) when the
+    start env0 is given, a relative 1e-13 perturbation of it."""
+    ds, de = 0.0, 0.0
+    for proj in (gesvd_projectors, transposed_projectors):
+        o2 = OCTM(A, pattern, chi, env0=env0)
+        o2.run(sweeps, proj=proj)
+        ds = max(ds, (corner_spectra(o2.env, chi) - so).abs().max().item())
+        if terms:
+            de = max(de, abs(oenergy(o2, H, terms).item() - Eo))
     if env0 is not None:
         rng = np.random.default_rng(7)
         o3 = OCTM(A, pattern, chi, env0=env0 * (1 + 1e-13 * rng.standard_normal(env0.shape)))
@@ -63,7 +78,7 @@ def rounding_spread(A, pattern, chi, sweeps, env0, so, Eo, terms):
         ds = max(ds, (corner_spectra(o3.env, chi) - so).abs().max().item())
         if terms:
             de = max(de, abs(oenergy(o3, H, terms).item() - Eo))
-    return ds, de
+    return ds, (de if terms else None)
 
 
 CASES = [
@@ -141,9 +156,10 @@ def test_one_sweep_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dis
 # (1e-10 s_1) is fixed by a backward-stable SVD only to a relative eps s_1/s_k
 # and sets the gauge of the new corners with weight s_k^(-1/2), while the
 # energy is insensitive to it.  The spectra are therefore held to 30 times the
-# spread between the oracle's two LAPACK SVD drivers (three backward-stable
-# SVDs scatter over about a decade around each other after several
-# amplifying sweeps), plus 1e-9.
+# spread of the oracle itself under LAPACK's other SVD driver or the SVD of
+# M^T (backward-stable SVDs scatter over one to two decades around each other
+# after several amplifying sweeps), plus 1e-8 absolute on spectra normalised
+# to sum 1.
 NP_CASES = [
     ("np_1x1_D2_chi8", 1, 2, 8, [[0]], 6),
     ("np_2x2_D3_chi12", 4, 3, 12, [[0, 1], [2, 3]], 6),
@@ -165,8 +181,8 @@ def test_sweeps_weakly_entangled(ctm_mod, name, nt, D, chi, pattern, sweeps):
     cond_s, _ = rounding_spread(A, pattern, chi, sweeps, None, so, Eo, None)
     sg, E = gpu_spectra(g.get_env(), o.sites, chi), g.energy(H, terms)
     err_s = (sg - so).abs().max().item()
-    print(f"{name}: spectra |d| {err_s:.2e} (driver spread {cond_s:.2e}), E {E:.14f} |d| {abs(E - Eo):.2e}")
-    assert err_s <= 30 * cond_s + 1e-9
+    print(f"{name}: spectra |d| {err_s:.2e} (oracle spread {cond_s:.2e}), E {E:.14f} |d| {abs(E - Eo):.2e}")
+    assert err_s <= 30 * cond_s + 1e-8
     assert abs(E - Eo) < 1e-10 * max(1.0, abs(Eo))
 
 
@@ -184,8 +200,8 @@ def test_full_size_ssm_d6_chi72_weakly_entangled(ctm_mod):
     cond_s, _ = rounding_spread(A, cfg["pattern"], cfg["chi"], 2, None, so, Eo, None)
     sg, E = gpu_spectra(g.get_env(), o.sites, cfg["chi"]), g.energy(H, terms)
     err_s = (sg - so).abs().max().item()
-    print(f"ssm_d6_chi72: spectra |d| {err_s:.2e} (driver spread {cond_s:.2e}), E(0,0) {E:.14f} |d| {abs(E - Eo):.2e}")
-    assert err_s <= 30 * cond_s + 1e-9
+    print(f"ssm_d6_chi72: spectra |d| {err_s:.2e} (oracle spread {cond_s:.2e}), E(0,0) {E:.14f} |d| {abs(E - Eo):.2e}")
+    assert err_s <= 30 * cond_s + 1e-8
     assert abs(E - Eo) < 1e-10
 
 
