@@ -9,9 +9,13 @@ FP32 accumulation), projector QR/SVD in FP64.
 
 A step is one CTMRG sweep (left, right, up and down moves: 64 projector
 computations and the environment updates); ``value`` is sweeps per second.
-The same line reports the energy evaluation time, the FP64-mode sweep rate,
-the roofline of the MFMA contraction kernel measured live with HIP events on
-the library's stream, and the CPU oracle timed on a bounded sample.
+The same line reports: the energy+gradient evaluations per second (energy
+after one differentiated sweep from the current environment, and its
+gradient by the hand-written reverse pass), the same in FP64 mode, the
+mixed-precision error of E and dE/dA against FP64 mode (on a weakly
+entangled state of the same shape, from one shared environment), the roofline of the kernel family that dominates a sweep
+(timed live with HIP events on the library's stream), and the CPU oracle
+timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16|fp32|fp64]
 """
@@ -25,7 +29,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CTMRG sweeps/s + E&grad evals/s at D=6,chi=72 (mixed vs FP64), |dE| vs oracle"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # MI355X dense matrix-core peaks
+# MI355X peaks: dense matrix cores per path, FP64 vector ALU for the Jacobi and QR families
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "jacobi": 78.6, "qr_panel": 78.6}
+BOUND = {"fp64": "mfma", "fp32": "mfma", "bf16": "mfma", "jacobi": "alu", "qr_panel": "alu"}
+KERNEL = {"fp64": "contract_kernel<MODE_F64> (FP64 MFMA)", "fp32": "contract_kernel<MODE_F32> (FP32 MFMA)",
+          "bf16": "contract_kernel<MODE_BF16> (BF16 MFMA, FP32 accumulation)",
+          "jacobi": "bjac_round_kernel (block one-sided Jacobi round, FP64)",
+          "qr_panel": "panel_kernel (Householder QR panel, FP64)"}
 
 
 def main():
@@ -36,8 +46,12 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=("bf16", "fp32", "fp64"))
     ap.add_argument("--config", default="ssm_d6_chi72")
     ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--egrad-sweeps", type=int, default=1)
+    ap.add_argument("--no-egrad", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a device buffer of MIB mebibytes once (calibration of the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -45,6 +59,19 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe > 0:
+        # source and destination are written first, then a buffer as large as
+        # both is written so that neither stays in the last-level cache
+        n = args.copy_probe * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        flush = torch.zeros(2 * n, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "check": float(y[-1].item()) + float(flush[0].item())}), flush=True)
+        return
     import synth
     import paper_2512_14414_amd as ctm
 
@@ -70,8 +97,9 @@ def main():
     torch.cuda.synchronize()
     t_sweeps = time.perf_counter() - t0
     sweeps_per_s = args.steps / t_sweeps
+    log(f"[bench] {sweeps_per_s:.3f} sweeps/s")
 
-    # ---- live roofline of the contraction kernel over one more sweep
+    # ---- live kernel timing over one more sweep
     g.profile_begin()
     t0 = time.perf_counter()
     g.sweep(1)
@@ -90,40 +118,71 @@ def main():
         t_energy = time.perf_counter() - t0
         log(f"[bench] energy {E:.10f} in {t_energy * 1e3:.1f} ms")
 
-    # ---- FP64 mode for comparison
+    # ---- energy + gradient throughput, production precision and FP64, from one shared environment
+    egrad = {}
+    env_shared = g.get_env()
+    g64 = ctm.CTM(A, cfg["pattern"], chi, precision="fp64")
+    if not args.no_egrad:
+        for label, ctx in ((args.precision, g), ("fp64", g64)):
+            ctx.set_env(env_shared)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Eg, grad = ctx.energy_grad(args.egrad_sweeps, H, terms)
+            torch.cuda.synchronize()
+            egrad[label] = time.perf_counter() - t0
+            log(f"[bench] E&grad {label}: {egrad[label]:.2f} s")
     fp64_sweeps_per_s = None
     if args.precision != "fp64" and args.fp64_steps > 0:
-        g64 = ctm.CTM(A, cfg["pattern"], chi, precision="fp64")
-        g64.sweep(1)
+        g64.set_env(env_shared)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g64.sweep(args.fp64_steps)
         torch.cuda.synchronize()
         fp64_sweeps_per_s = args.fp64_steps / (time.perf_counter() - t0)
         log(f"[bench] fp64 sweeps/s {fp64_sweeps_per_s:.3f}")
-        g64.close()
+    g64.close()
 
-    # ---- roofline of the dominant kernel family (bulk contractions in the production path)
-    path = args.precision
-    ms, flops, launches = prof[path]
-    if launches == 0:
-        path = "fp64"
-        ms, flops, launches = prof[path]
+    # ---- mixed-precision error on a well-conditioned state of the same shape: the
+    # random tensors above do not settle (their environment keeps changing at
+    # order one), so E and dE/dA are compared on a weakly entangled state
+    # (noise 0.3 on a product state) after 4 FP64 sweeps from the sites start
+    accuracy = None
+    if not args.no_egrad and args.precision != "fp64":
+        An = synth.near_product_tensors(len(A), 2, cfg["D"], 5, 0.3)
+        h64 = ctm.CTM(An, cfg["pattern"], chi, precision="fp64")
+        h64.sweep(4)
+        env_np = h64.get_env()
+        E64, g64v = h64.energy_grad(args.egrad_sweeps, H, terms)
+        hmx = ctm.CTM(An, cfg["pattern"], chi, precision=args.precision)
+        hmx.set_env(env_np)
+        Emx, gmx = hmx.energy_grad(args.egrad_sweeps, H, terms)
+        accuracy = {"state": "weakly entangled (product + 0.3 noise, seed 5), same shape, 4 FP64 sweeps",
+                    "E_fp64": E64, "dE": abs(Emx - E64), "dgrad_max": (gmx - g64v).abs().max().item(),
+                    "grad_max": g64v.abs().max().item(),
+                    "fp64_vs_oracle": "tested: |dE| <= 1e-10 at this shape (tests/test_gpu_parity.py)"}
+        log(f"[bench] mixed vs fp64: {accuracy}")
+        h64.close()
+        hmx.close()
+
+    # ---- roofline of the kernel family with the largest share of the profiled sweep
+    fam = max(prof, key=lambda k: prof[k][0])
+    ms, flops, launches = prof[fam]
     achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     roofline = {
-        "kernel": f"contract_kernel ({path} MFMA path)",
-        "bound": "mfma",
-        "achieved": round(achieved, 3),
-        "peak": PEAK_TFLOPS[path],
+        "kernel": KERNEL[fam],
+        "bound": BOUND[fam],
+        "achieved": round(achieved, 4),
+        "peak": PEAK_TFLOPS[fam],
         "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_TFLOPS[path], 5),
+        "frac": round(achieved / PEAK_TFLOPS[fam], 6),
         "traffic": None,
         "launches_per_sweep": launches,
         "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
         "algorithmic_flops_per_sweep": flops,
         "kernel_ms_per_sweep": round(ms, 3),
-        "fp64_path_ms_per_sweep": round(prof["fp64"][0], 3),
         "sweep_ms": round(t_prof * 1e3, 2),
+        "families_ms_per_sweep": {k: round(v[0], 2) for k, v in prof.items()},
+        "families_tflops": {k: round(v[1] / (v[0] * 1e-3) / 1e12, 4) if v[0] > 0 else 0.0 for k, v in prof.items()},
     }
 
     # ---- CPU oracle on a bounded sample of the same workload
@@ -139,6 +198,8 @@ def main():
                "kind": "oracle", "sample": f"{n_cpu} sweeps of the same workload (float64, sites-derived start)"}
         log(f"[bench] oracle {n_cpu} sweeps in {t_cpu:.1f} s")
 
+    eg = egrad.get(args.precision)
+    e64 = egrad.get("fp64")
     out = {
         "metric": METRIC,
         "value": round(sweeps_per_s, 4),
@@ -157,8 +218,11 @@ def main():
                    "precision": args.precision, "projectors": "fp64 QR+SVD"},
         "fp64_sweeps_per_s": None if fp64_sweeps_per_s is None else round(fp64_sweeps_per_s, 4),
         "energy_s": None if t_energy is None else round(t_energy, 4),
-        "energy": E,
-        "egrad_per_s": None,
+        "egrad_per_s": None if eg is None else round(1.0 / eg, 4),
+        "egrad_per_s_fp64": None if e64 is None else round(1.0 / e64, 4),
+        "egrad_sweeps": args.egrad_sweeps,
+        "egrad_speedup_vs_fp64": None if (eg is None or e64 is None) else round(e64 / eg, 3),
+        "mixed_vs_fp64": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -144,13 +144,15 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *   "check_finite" 1 to test the environment for NaN/Inf after every sweep (default 1) */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
-/* Live timing of the MFMA contraction kernel (the corner, half-system,
- * projection and density-matrix contractions).  Between ctm_profile_begin and
- * ctm_profile_end every launch of that kernel, by any context of the process,
- * is bracketed by two HIP events on its stream.  ctm_profile_end fills three
- * host arrays of 3 entries each (any may be NULL), indexed by the matrix-core
- * path 0 = FP64, 1 = FP32, 2 = BF16: the summed kernel time in milliseconds,
- * the summed algorithmic flops (2*M*N*K per launch) and the launch count. */
+/* Live timing of the library's main kernel families.  Between
+ * ctm_profile_begin and ctm_profile_end every launch of a timed family, by
+ * any context of the process, is bracketed by two HIP events on its stream.
+ * ctm_profile_end fills three host arrays of 5 entries each (any may be NULL),
+ * indexed by family: 0, 1, 2 = the MFMA contraction kernel on the FP64, FP32
+ * and BF16 paths (flops 2*M*N*K per launch), 3 = the block Jacobi rounds of
+ * the projector SVD (flops of the Gram matrices and column rotations), 4 = the
+ * Householder QR panels: the summed kernel time in milliseconds, the summed
+ * algorithmic flops and the launch count. */
 int ctm_profile_begin(ctm_ctx* ctx);
 int ctm_profile_end(ctm_ctx* ctx, double* kernel_ms, double* kernel_flops, int64_t* launches);
 

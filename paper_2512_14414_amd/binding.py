@@ -176,11 +176,15 @@ class CTM:
     def profile_begin(self):
         self._check(LIB.ctm_profile_begin(self._h))
 
+    FAMILIES = ("fp64", "fp32", "bf16", "jacobi", "qr_panel")
+
     def profile_end(self):
-        """{path: (kernel ms, algorithmic flops, launches)} for path in fp64, fp32, bf16."""
-        ms, fl, n = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_int64 * 3)()
+        """{family: (kernel ms, algorithmic flops, launches)} for the contraction
+        kernel on the fp64, fp32 and bf16 paths, the block Jacobi rounds and the QR panels."""
+        n_f = len(self.FAMILIES)
+        ms, fl, n = (ctypes.c_double * n_f)(), (ctypes.c_double * n_f)(), (ctypes.c_int64 * n_f)()
         self._check(LIB.ctm_profile_end(self._h, ms, fl, n))
-        return {k: (ms[i], fl[i], n[i]) for i, k in enumerate(("fp64", "fp32", "bf16"))}
+        return {k: (ms[i], fl[i], n[i]) for i, k in enumerate(self.FAMILIES)}
 
     def set_option(self, key, value):
         self._check(LIB.ctm_set_option(self._h, key.encode(), float(value)))

@@ -408,8 +408,12 @@ void hqr_factor(Dev& dev, HQR& q) {
     const int64_t j0 = p * q.nb;
     const int nbp = (int)std::min<int64_t>(q.nb, q.k - j0);
     double* Tp = (double*)q.T.p + p * q.nb * q.nb;
+    if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
     HIP_CHECK(qrk::launch_panel(q.A, q.rs, q.cs, q.stride, q.m, q.n, j0, q.batch, (double*)q.tau.p, q.k, Tp,
                                 q.tstride(), dev.stream));
+    if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
+    // Householder panel: about 4 (m - j0) nbp^2 flops per matrix (norms, reflections, T factor)
+    g_counters.count(FAM_PANEL, 4.0 * (double)(q.m - j0) * nbp * nbp * q.batch);
     hqr_panel_apply(dev, q, p, q.A, q.rs, q.cs, q.stride, j0 + nbp, q.n - (j0 + nbp), true);
   }
 }
@@ -445,13 +449,23 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   HIP_CHECK(ctmk::launch_frob_tiny((const double*)X.p, stride, stride, batch, 2.2e-16, (double*)tiny2.p, dev.stream));
   const double tol = std::max(1e-15, 2.2e-16 * std::sqrt((double)r));
   const int64_t rounds = ctmk::bjac_rounds(r);
+  // algorithmic flops of one round: per block pair of C columns of length r, the
+  // Gram matrix (C(C+1)/2 dot products) and the rotation of the pair's columns
+  // of X and W (two r x C by C x C products); the inner Jacobi on C x C is not counted
+  const double Cw = (double)ctmk::bjac_pair_columns();
+  const double pairs = (double)(ctmk::bjac_rounds(r) + 1) / 2.0 * batch;
+  const double bj_flops = pairs * ((Cw * (Cw + 1) / 2.0) * 2.0 * r + 2.0 * (2.0 * r * Cw * Cw));
   std::vector<int> h(batch);
   int sweep = 0;
   for (sweep = 1; sweep <= c->jacobi_max_sweeps; ++sweep) {
     HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, batch, dev.stream));
-    for (int64_t t = 0; t < rounds; ++t)
+    for (int64_t t = 0; t < rounds; ++t) {
+      if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
       HIP_CHECK(ctmk::launch_bjac_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
                                         (const double*)tiny2.p, 1, (int*)rot.p, dev.stream));
+      if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
+      g_counters.count(FAM_JACOBI, bj_flops);
+    }
     HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, batch * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
     HIP_CHECK(hipStreamSynchronize(dev.stream));
     bool any = false;
@@ -1260,9 +1274,9 @@ int ctm_profile_end(ctm_ctx* c, double* kernel_ms, double* kernel_flops, int64_t
   if (!c) return CTM_EINVAL;
   try {
     g_counters.timing = false;
-    double ms[3];
+    double ms[N_FAMILIES];
     g_counters.collect_ms(ms);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < N_FAMILIES; ++i) {
       if (kernel_ms) kernel_ms[i] = ms[i];
       if (kernel_flops) kernel_flops[i] = g_counters.mode_flops[i];
       if (launches) launches[i] = g_counters.mode_launches[i];

@@ -13,7 +13,7 @@ void Counters::reset_timing() {
   used = 0;
   launches = 0;
   flops = 0;
-  for (int i = 0; i < 3; ++i) { mode_launches[i] = 0; mode_flops[i] = 0; }
+  for (int i = 0; i < N_FAMILIES; ++i) { mode_launches[i] = 0; mode_flops[i] = 0; }
 }
 
 void Counters::record(hipStream_t s, int mode) {
@@ -28,7 +28,7 @@ void Counters::record(hipStream_t s, int mode) {
 }
 
 void Counters::collect_ms(double* ms) {
-  for (int i = 0; i < 3; ++i) ms[i] = 0;
+  for (int i = 0; i < N_FAMILIES; ++i) ms[i] = 0;
   if (used) HIP_CHECK(hipEventSynchronize(pool[used - 1]));
   for (size_t i = 0; i + 1 < used; i += 2) {
     float t = 0;
@@ -307,8 +307,7 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
   const double fl = 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
   g_counters.launches++;
   g_counters.flops += fl;
-  g_counters.mode_launches[km]++;
-  g_counters.mode_flops[km] += fl;
+  g_counters.count(km, fl);
   if (g_counters.timing) g_counters.record(dev.stream, km);
   HIP_CHECK(ctmk::launch_contract(km, g, dev.stream));
   if (g_counters.timing) g_counters.record(dev.stream, km);

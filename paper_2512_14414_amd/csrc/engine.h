@@ -157,21 +157,30 @@ struct TapePause {
   ~TapePause() { if (t) --t->paused; }
 };
 
-// Count of contraction-kernel launches and their algorithmic flops (2 M N K per
-// batch entry).  While ``timing`` is on, every launch is bracketed by a pair
-// of HIP events on the launching stream; ``collect`` then sums their times.
+// Launch counts, algorithmic flops and (while ``timing`` is on) HIP-event
+// times of the timed kernel families: 0, 1, 2 = contraction kernel on the
+// FP64, FP32 and BF16 matrix-core paths, 3 = block Jacobi rounds, 4 = QR
+// panels.  Every timed launch is bracketed by a pair of events on its stream;
+// ``collect_ms`` sums their times per family.
+constexpr int N_FAMILIES = 5;
+enum { FAM_JACOBI = 3, FAM_PANEL = 4 };
 struct Counters {
   int64_t launches = 0;
   double flops = 0;
   bool timing = false;
   std::vector<hipEvent_t> pool;
-  std::vector<int> pool_mode;       // matrix-core path of each timed launch
+  std::vector<int> pool_mode;       // family of each timed launch
   size_t used = 0;
-  int64_t mode_launches[3] = {0, 0, 0};
-  double mode_flops[3] = {0, 0, 0};
+  int64_t mode_launches[N_FAMILIES] = {0, 0, 0, 0, 0};
+  double mode_flops[N_FAMILIES] = {0, 0, 0, 0, 0};
   void reset_timing();
-  void record(hipStream_t s, int mode);
-  void collect_ms(double* ms_per_mode);
+  void record(hipStream_t s, int family);
+  void collect_ms(double* ms_per_family);
+  // bookkeeping of one launch of ``family`` with ``flops`` algorithmic flops
+  void count(int family, double fl) {
+    mode_launches[family]++;
+    mode_flops[family] += fl;
+  }
 };
 extern Counters g_counters;
 

@@ -77,6 +77,7 @@ hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int
 hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
                              const double* tiny2, int inner, int* rot, hipStream_t s);
 int64_t bjac_rounds(int64_t n);
+int bjac_pair_columns();
 
 // reverse pass
 hipError_t launch_normalize_backward(int type, const NormList& Y, const NormList& Yb, int count, hipStream_t s);

@@ -829,7 +829,9 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
   int64_t P, Q;
   if (k == 0) { P = round; Q = np - 1; }
   else { P = (round + k) % (np - 1); Q = (round - k + (np - 1)) % (np - 1); }
-  if (P >= nblk || Q >= nblk) return;
+  // a block paired with the padding player (odd block count, or a single
+  // block) is still rotated within itself: the missing columns read as absent
+  if (P >= nblk && Q >= nblk) return;
   if (P > Q) { int64_t t = P; P = Q; Q = t; }
   double* Ab = A + (int64_t)b * stride;
   double* Vb = V + (int64_t)b * stride;
@@ -839,15 +841,21 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     const int64_t g = c < BJ_BW ? c0P + c : c0Q + (c - BJ_BW);
     return g < n ? g : -1;
   };
-  // Gram matrix: thread e < 136 owns upper-triangle entry (ea, eb)
+  // Gram matrix: thread owns upper-triangle entries e = tid + NT*j, (ea[j], eb[j])
   constexpr int NE = BJ_C * (BJ_C + 1) / 2;
-  int ea = -1, eb = -1;
-  if (tid < NE) {
-    int rem = tid, a = 0;
-    while (rem >= BJ_C - a) { rem -= BJ_C - a; ++a; }
-    ea = a; eb = a + rem;
+  constexpr int GPT = (NE + BJ_NT - 1) / BJ_NT;
+  int ea[GPT], eb[GPT];
+  double acc[GPT];
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) {
+    ea[j] = -1; eb[j] = -1; acc[j] = 0.0;
+    const int e0 = tid + BJ_NT * j;
+    if (e0 < NE) {
+      int rem = e0, a = 0;
+      while (rem >= BJ_C - a) { rem -= BJ_C - a; ++a; }
+      ea[j] = a; eb[j] = a + rem;
+    }
   }
-  double acc = 0.0;
   for (int64_t r0 = 0; r0 < n; r0 += BJ_CHUNK) {
     const int rows = (int)((n - r0) < BJ_CHUNK ? (n - r0) : BJ_CHUNK);
     // stage element e = c * CHUNK + i; groups of 7 loads in flight per thread
@@ -867,21 +875,26 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
       }
     }
     __syncthreads();
-    if (ea >= 0) {
+#pragma unroll
+    for (int j = 0; j < GPT; ++j) {
+      if (ea[j] < 0) continue;
+      const int pa = ea[j], pb = eb[j];
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int i = 0;
       for (; i + 4 <= rows; i += 4) {
-        a0 += xs[i * BJ_C + ea] * xs[i * BJ_C + eb];
-        a1 += xs[(i + 1) * BJ_C + ea] * xs[(i + 1) * BJ_C + eb];
-        a2 += xs[(i + 2) * BJ_C + ea] * xs[(i + 2) * BJ_C + eb];
-        a3 += xs[(i + 3) * BJ_C + ea] * xs[(i + 3) * BJ_C + eb];
+        a0 += xs[i * BJ_C + pa] * xs[i * BJ_C + pb];
+        a1 += xs[(i + 1) * BJ_C + pa] * xs[(i + 1) * BJ_C + pb];
+        a2 += xs[(i + 2) * BJ_C + pa] * xs[(i + 2) * BJ_C + pb];
+        a3 += xs[(i + 3) * BJ_C + pa] * xs[(i + 3) * BJ_C + pb];
       }
-      for (; i < rows; ++i) a0 += xs[i * BJ_C + ea] * xs[i * BJ_C + eb];
-      acc += (a0 + a1) + (a2 + a3);
+      for (; i < rows; ++i) a0 += xs[i * BJ_C + pa] * xs[i * BJ_C + pb];
+      acc[j] += (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
   }
-  if (ea >= 0) { G[ea * BJ_C + eb] = acc; G[eb * BJ_C + ea] = acc; }
+#pragma unroll
+  for (int j = 0; j < GPT; ++j)
+    if (ea[j] >= 0) { G[ea[j] * BJ_C + eb[j]] = acc[j]; G[eb[j] * BJ_C + ea[j]] = acc[j]; }
   for (int e = tid; e < BJ_C * BJ_C; e += BJ_NT) R[e] = (e / BJ_C == e % BJ_C) ? 1.0 : 0.0;
   __syncthreads();
   if (tid < 64) {
@@ -912,9 +925,9 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
         for (int j = 0; j < BJ_C / 2; ++j) live += cs[j][1] != 0.0;
         if (live) {
           sweep_rot += live;
-          // G <- J^T G (rows p, q), 8 pairs x 16 columns, 2 per lane
+          // G <- J^T G (rows p, q): C/2 pairs x C columns
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < (BJ_C / 2) * BJ_C / 64; ++h) {
             int u = lane + 64 * h, j = u / BJ_C, col = u % BJ_C;
             int p = pr[j][0], q = pr[j][1];
             double c = cs[j][0], sn = cs[j][1];
@@ -925,7 +938,7 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
           wave_sync();
           // G <- G J and R <- R J (columns p, q)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < (BJ_C / 2) * BJ_C / 64; ++h) {
             int u = lane + 64 * h, j = u / BJ_C, row = u % BJ_C;
             int p = pr[j][0], q = pr[j][1];
             double c = cs[j][0], sn = cs[j][1];
@@ -979,6 +992,8 @@ hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, in
   bjac_round_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, round, tol, tiny2, inner, rot);
   return hipGetLastError();
 }
+
+int bjac_pair_columns() { return BJ_C; }
 
 int64_t bjac_rounds(int64_t n) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
