@@ -2,6 +2,8 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -297,6 +299,9 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
   g.alpha = alpha;
   g.beta = beta;
   g.colscale = colscale;
+  g.ksplit = 1;
+  g.kchunk = g.K;
+  g.work = nullptr;
   if (g.batch > 65535) throw Error(-1, "contract: batch too large");
   if (((g.M + 63) / 64) * ((g.N + 63) / 64) > 2147483647LL) throw Error(-1, "contract: too many tiles");
   if (g.K == 0) {   // empty sum
@@ -305,6 +310,19 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
   }
   const int km = A.type == T_F64 ? ctmk::MODE_F64 : mode;
   const double fl = 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
+  // few output tiles and a long sum: split K over more workgroups (partials in a workspace)
+  DBuf work;
+  const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+  if (tiles < 128 && g.K >= 2048) {
+    int64_t want = std::min<int64_t>((512 + tiles - 1) / tiles, g.K / 512);
+    if (want > 1) {
+      g.kchunk = ((g.K + want - 1) / want + 31) / 32 * 32;
+      g.ksplit = (g.K + g.kchunk - 1) / g.kchunk;
+      if (g.ksplit > 65535) throw Error(-1, "contract: K too long to split");
+      work = DBuf(&dev, (size_t)g.ksplit * g.batch * g.M * g.N * type_size(C.type));
+      g.work = work.p;
+    }
+  }
   g_counters.launches++;
   g_counters.flops += fl;
   g_counters.count(km, fl);

@@ -24,6 +24,11 @@ struct GemmArgs {
   double alpha;
   int beta;                 // 0: overwrite C, 1: accumulate into C
   const double* colscale;   // optional factor per n (device, length N)
+  // split K: ksplit > 1 workgroups share one output tile, each summing a K
+  // range of kchunk (a multiple of 32); their partial tiles go to ``work``
+  // ([ksplit][batch][M][N], element type of C) and launch_contract adds them up.
+  int64_t ksplit, kchunk;
+  void* work;
 };
 
 constexpr int PERM_MAX_DIMS = 10;

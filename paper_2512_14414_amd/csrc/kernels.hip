@@ -32,7 +32,7 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
   return (unsigned short)(u >> 16);
 }
 
-constexpr int BM = 64, BN = 64, NT = 256;
+constexpr int BM = 64, NT = 256;
 
 template <int MODE> struct Cfg;
 template <> struct Cfg<MODE_F64> { typedef double T; typedef double L; static constexpr int BK = 16; };
@@ -44,13 +44,16 @@ template <> __device__ __forceinline__ double to_lds<MODE_F64>(double v) { retur
 template <> __device__ __forceinline__ float to_lds<MODE_F32>(float v) { return v; }
 template <> __device__ __forceinline__ unsigned short to_lds<MODE_BF16>(float v) { return f32_to_bf16_rne(v); }
 
-// One workgroup computes a 64 x 64 tile of C for one batch entry; the four
-// waves each own a 32 x 32 quarter made of 2 x 2 blocks of 16 x 16 MFMA tiles.
-template <int MODE, bool AK, bool BN_FAST>
+// One workgroup computes a 64 x BN tile of C (BN = 32 WN) for one batch
+// entry; the four waves each own a 32 x 16WN quarter made of 2 x WN blocks of
+// 16 x 16 MFMA tiles.  WN = 4 (BN = 128) halves the re-reads of the A operand
+// when N is wide (tall-skinny absorptions with N up to 128 read A once).
+template <int MODE, bool AK, bool BN_FAST, int WN>
 __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
   typedef typename Cfg<MODE>::T T;
   typedef typename Cfg<MODE>::L L;
   constexpr int BK = Cfg<MODE>::BK;
+  constexpr int BN = 32 * WN;
   __shared__ L As[BK][BM + 4];
   __shared__ L Bs[BK][BN + 4];
   __shared__ int64_t a_row[BM], b_col[BN];
@@ -60,6 +63,8 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
   const int64_t tile = blockIdx.x;
   const int64_t m0 = (tile / tiles_n) * BM, n0 = (tile % tiles_n) * BN;
   const int64_t bz = blockIdx.y;
+  const int64_t kbeg = g.ksplit > 1 ? (int64_t)blockIdx.z * g.kchunk : 0;
+  const int64_t kend = g.ksplit > 1 ? (kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K) : g.K;
   const T* A = (const T*)g.A + split_off(bz, g.b_in, g.a_b_o, g.a_b_i);
   const T* B = (const T*)g.B + split_off(bz, g.b_in, g.b_b_o, g.b_b_i);
   T* C = (T*)g.C + split_off(bz, g.b_in, g.c_b_o, g.c_b_i);
@@ -76,61 +81,73 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
   __syncthreads();
 
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 16 * WN;
   const int lr = lane & 15, lq = lane >> 4;
 
   typedef typename std::conditional<MODE == MODE_F64, d4_t, f4_t>::type acc_t;
-  acc_t acc[2][2];
+  acc_t acc[2][WN];
   for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WN; ++j)
       for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
 
-  constexpr int PER = BM * BK / NT;   // elements per thread per operand per K step
-  // Each thread stages PER fixed (k-in-tile, row/column) positions of A and of
-  // B.  The K index of a position advances by BK per step; its split into
+  constexpr int PA = BM * BK / NT;   // elements of A per thread per K step
+  constexpr int PB = BN * BK / NT;   // elements of B per thread per K step
+  // Each thread stages fixed (k-in-tile, row/column) positions of A and of B.
+  // The K index of a position advances by BK per step; its split into
   // (outer, inner) parts is carried along incrementally instead of divided.
-  int a_mm[PER], b_nn[PER], a_kq[PER], a_kr[PER], b_kq[PER], b_kr[PER];
-  int a_kk[PER], b_kk[PER];
+  int a_mm[PA], a_kq[PA], a_kr[PA], a_kk[PA];
+  int b_nn[PB], b_kq[PB], b_kr[PB], b_kk[PB];
   const int kin = (int)g.k_in;
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
+  for (int i = 0; i < PA; ++i) {
     const int e = tid + i * NT;
     if (AK) { a_kk[i] = e % BK; a_mm[i] = e / BK; } else { a_mm[i] = e % BM; a_kk[i] = e / BM; }
-    if (BN_FAST) { b_nn[i] = e % BN; b_kk[i] = e / BN; } else { b_kk[i] = e % BK; b_nn[i] = e / BK; }
-    a_kq[i] = a_kk[i] / kin; a_kr[i] = a_kk[i] - a_kq[i] * kin;
-    b_kq[i] = b_kk[i] / kin; b_kr[i] = b_kk[i] - b_kq[i] * kin;
+    const int k = (int)kbeg + a_kk[i];
+    a_kq[i] = k / kin; a_kr[i] = k - a_kq[i] * kin;
   }
-  T va[PER], vb[PER];
+#pragma unroll
+  for (int i = 0; i < PB; ++i) {
+    const int e = tid + i * NT;
+    if (BN_FAST) { b_nn[i] = e % BN; b_kk[i] = e / BN; } else { b_kk[i] = e % BK; b_nn[i] = e / BK; }
+    const int k = (int)kbeg + b_kk[i];
+    b_kq[i] = k / kin; b_kr[i] = k - b_kq[i] * kin;
+  }
+  T va[PA], vb[PB];
   auto load_tiles = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
+    for (int i = 0; i < PA; ++i) {
       const int64_t ro = a_row[a_mm[i]];
-      const bool ok = ro != NONE && k0 + a_kk[i] < g.K;
+      const bool ok = ro != NONE && k0 + a_kk[i] < kend;
       va[i] = ok ? A[ro + (int64_t)a_kq[i] * g.a_k_o + (int64_t)a_kr[i] * g.a_k_i] : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
       const int64_t co = b_col[b_nn[i]];
-      const bool okb = co != NONE && k0 + b_kk[i] < g.K;
+      const bool okb = co != NONE && k0 + b_kk[i] < kend;
       vb[i] = okb ? B[co + (int64_t)b_kq[i] * g.b_k_o + (int64_t)b_kr[i] * g.b_k_i] : (T)0;
     }
   };
   auto advance = [&]() {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
+    for (int i = 0; i < PA; ++i) {
       a_kr[i] += BK;
       while (a_kr[i] >= kin) { a_kr[i] -= kin; ++a_kq[i]; }
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
       b_kr[i] += BK;
       while (b_kr[i] >= kin) { b_kr[i] -= kin; ++b_kq[i]; }
     }
   };
-  load_tiles(0);
-  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+  load_tiles(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      As[a_kk[i]][a_mm[i]] = to_lds<MODE>(va[i]);
-      Bs[b_kk[i]][b_nn[i]] = to_lds<MODE>(vb[i]);
-    }
+    for (int i = 0; i < PA; ++i) As[a_kk[i]][a_mm[i]] = to_lds<MODE>(va[i]);
+#pragma unroll
+    for (int i = 0; i < PB; ++i) Bs[b_kk[i]][b_nn[i]] = to_lds<MODE>(vb[i]);
     __syncthreads();
     // prefetch the next K tile into registers while the matrix cores work
-    if (k0 + BK < g.K) {
+    if (k0 + BK < kend) {
       advance();
       load_tiles(k0 + BK);
     }
@@ -138,38 +155,42 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
         double a0 = As[ks + lq][wm + lr], a1 = As[ks + lq][wm + 16 + lr];
-        double b0 = Bs[ks + lq][wn + lr], b1 = Bs[ks + lq][wn + 16 + lr];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          double bj = Bs[ks + lq][wn + 16 * j + lr];
+          acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bj, acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bj, acc[1][j], 0, 0, 0);
+        }
       }
     } else if constexpr (MODE == MODE_F32) {
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
         float a0 = As[ks + lq][wm + lr], a1 = As[ks + lq][wm + 16 + lr];
-        float b0 = Bs[ks + lq][wn + lr], b1 = Bs[ks + lq][wn + 16 + lr];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          float bj = Bs[ks + lq][wn + 16 * j + lr];
+          acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bj, acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bj, acc[1][j], 0, 0, 0);
+        }
       }
     } else {
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 16) {
-        s4_t a0, a1, b0, b1;
+        s4_t a0, a1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           int kk = ks + lq * 4 + q;
           a0[q] = (short)As[kk][wm + lr];
           a1[q] = (short)As[kk][wm + 16 + lr];
-          b0[q] = (short)Bs[kk][wn + lr];
-          b1[q] = (short)Bs[kk][wn + 16 + lr];
         }
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          s4_t bj;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bj[q] = (short)Bs[ks + lq * 4 + q][wn + 16 * j + lr];
+          acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, bj, acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, bj, acc[1][j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -178,10 +199,27 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
   // D layout of the 16x16 MFMA tiles (measured on gfx950): register e of lane l
   // holds column l%16 and row 4*(l/16)+e for the f32 and bf16 instructions,
   // row (l/16)+4*e for v_mfma_f64_16x16x4f64.
+  if (g.ksplit > 1) {
+    T* W = (T*)g.work + ((int64_t)blockIdx.z * g.batch + bz) * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int64_t n = n0 + wn + j * 16 + lr;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = MODE == MODE_F64 ? lq + 4 * e : lq * 4 + e;
+          const int64_t m = m0 + wm + i * 16 + row;
+          if (m < g.M) W[m * g.N + n] = (T)acc[i][j][e];
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < WN; ++j) {
       int64_t n = n0 + wn + j * 16 + lr;
       if (n >= g.N) continue;
       int64_t cn = split_off(n, g.n_in, g.c_n_o, g.c_n_i);
@@ -199,17 +237,50 @@ __global__ __launch_bounds__(NT) void contract_kernel(GemmArgs g) {
     }
 }
 
-template <int MODE>
-static hipError_t launch_mode(const GemmArgs& g, hipStream_t s) {
-  // all (m, n) tiles of one batch entry along x, batch entries along y
-  dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), (unsigned)g.batch, 1);
+// C = alpha * colscale * (sum of the split-K partial tiles) (+ C)
+template <typename T>
+__global__ void split_reduce_kernel(GemmArgs g) {
+  const int64_t total = g.batch * g.M * g.N;
+  const T* W = (const T*)g.work;
+  T* C = (T*)g.C;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = e % g.N, bm = e / g.N, m = bm % g.M, b = bm / g.M;
+    double acc = 0.0;
+    for (int64_t s = 0; s < g.ksplit; ++s) acc += (double)W[s * total + e];
+    const int64_t off = split_off(b, g.b_in, g.c_b_o, g.c_b_i) + split_off(m, g.m_in, g.c_m_o, g.c_m_i) +
+                        split_off(n, g.n_in, g.c_n_o, g.c_n_i);
+    T v = (T)(g.alpha * (g.colscale ? g.colscale[n] : 1.0) * acc);
+    if (g.beta) v += C[off];
+    C[off] = v;
+  }
+}
+
+template <int MODE, int WN>
+static hipError_t launch_tiles(const GemmArgs& g, hipStream_t s) {
+  constexpr int BN = 32 * WN;
+  // all (m, n) tiles of one batch entry along x, batch entries along y, K ranges along z
+  dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), (unsigned)g.batch,
+            (unsigned)(g.ksplit > 1 ? g.ksplit : 1));
   // choose the fastest-varying index of each staged tile so that loads coalesce
   bool ak = g.a_k_i == 1 ? true : (g.a_m_i == 1 ? false : true);
   bool bn = g.b_n_i == 1 ? true : (g.b_k_i == 1 ? false : true);
-  if (ak && bn) contract_kernel<MODE, true, true><<<grid, NT, 0, s>>>(g);
-  else if (ak) contract_kernel<MODE, true, false><<<grid, NT, 0, s>>>(g);
-  else if (bn) contract_kernel<MODE, false, true><<<grid, NT, 0, s>>>(g);
-  else contract_kernel<MODE, false, false><<<grid, NT, 0, s>>>(g);
+  if (ak && bn) contract_kernel<MODE, true, true, WN><<<grid, NT, 0, s>>>(g);
+  else if (ak) contract_kernel<MODE, true, false, WN><<<grid, NT, 0, s>>>(g);
+  else if (bn) contract_kernel<MODE, false, true, WN><<<grid, NT, 0, s>>>(g);
+  else contract_kernel<MODE, false, false, WN><<<grid, NT, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_mode(const GemmArgs& g, hipStream_t s) {
+  // 128-wide tiles when N is wide and there are enough rows to fill the chip
+  const int64_t tiles_m = (g.M + BM - 1) / BM;
+  hipError_t e = (g.N > 64 && tiles_m * g.batch >= 512) ? launch_tiles<MODE, 4>(g, s) : launch_tiles<MODE, 2>(g, s);
+  if (e != hipSuccess || g.ksplit <= 1) return e;
+  const int64_t total = g.batch * g.M * g.N;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  split_reduce_kernel<typename Cfg<MODE>::T><<<(unsigned)blocks, 256, 0, s>>>(g);
   return hipGetLastError();
 }
 
