@@ -846,9 +846,17 @@ void check_flags(ctm_ctx* c) {
 // columns 2px..2px+3 with its border environment.  The four Y tensors are
 // cut: the ket end of the physical line stays with the fused leg coming from
 // K, the bra end is exposed on the B below.  X and cut Y tensors are pure
-// relabellings of legs.  The left half (boundary column and nested columns 0,
-// 1) and the right half (boundary column and columns 3, 2) are grown column
-// by column and joined.  Result: rho[(k_TL k_TR k_BL k_BR), (b_TL b_TR b_BL b_BR)].
+// relabellings of legs.
+//
+// Contraction order: each PEPS site of the plaquette with its corner and two
+// pairs of edge tensors forms a quadrant tensor with two cuts (a chi leg and
+// two D legs each) and its two open physical legs; the two upper quadrants
+// are joined over their common cut, likewise the two lower ones, and the two
+// halves are joined over both vertical cuts.  No intermediate carries more
+// than two quadrants' worth of open legs, so the largest tensor is a half of
+// (chi D^2)^2 d^4 entries (the column-by-column order carries a strip of
+// chi^2 D^4 d^4 entries and more).  Result:
+// rho[(k_TL k_TR k_BL k_BR), (b_TL b_TR b_BL b_BR)].
 void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
   Dev& dev = c->dev;
   const int m = c->mode;
@@ -865,13 +873,11 @@ void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
   const char* names[4] = {"TL", "TR", "BL", "BR"};
   auto kO = [&](int s) { return Lb(std::string("k") + names[s]); };
   auto bO = [&](int s) { return Lb(std::string("b") + names[s]); };
-  auto site_of = [&](int r, int cc) { return (r / 2) * 2 + (cc / 2); };   // 0 TL, 1 TR, 2 BL, 3 BR
   auto str = [](std::initializer_list<char> l) { return std::string(l); };
 
   auto env = [&](int r, int cc, int k, const std::string& lab) { return c->slot(0, r0 + r, c0 + cc, k, lab); };
   auto site = [&](int r, int cc, const std::string& lab) { return c->site_t(0, r0 + r, c0 + cc, lab); };
 
-  struct State { Tmp t; };
   auto absorb = [&](Tmp& S, const TRef& X) {
     std::string out;
     for (char ch : S.t.lab) if (X.lab.find(ch) == std::string::npos) out += ch;
@@ -888,70 +894,82 @@ void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
     if (i == std::string::npos) throw Error(CTM_EINVAL, "rdm: missing label");
     S.t.lab[i] = to;
   };
+  auto start = [&](const TRef& corner) {
+    Tmp S(&dev, c->st, corner.dim, corner.lab);
+    copy_into(dev, S.t, corner);
+    return S;
+  };
+  // bra site with its fused up leg split (virtual U, physical = open bra index)
+  auto bra = [&](int r, int cc, int s) {
+    TRef Bt = site(r, cc, "lurd");
+    Bt = split_axis(Bt, 'u', D, d, 'U', 'S');
+    return relabel(Bt, str({H(r, cc - 1), V(r - 1, cc), bO(s), H(r, cc), V(r, cc)}));
+  };
+  // ket site with its fused right leg split (virtual R = Hd, physical = open ket index)
+  auto ket_open = [&](int r, int cc, int s) {
+    TRef Kt = site(r, cc, "lurd");
+    Kt = split_axis(Kt, 'r', D, d, 'R', 'S');
+    return relabel(Kt, str({H(r, cc - 1), V(r - 1, cc), Hd(r, cc), kO(s), V(r, cc)}));
+  };
 
-  // ---- left half
-  Tmp Ls(&dev, c->st, {(int64_t)c->chi, (int64_t)c->chi}, str({chL(0), chT(0)}));
-  copy_into(dev, Ls.t, env(0, 0, 0, str({chL(0), chT(0)})));
-  for (int r = 0; r < 4; ++r) absorb(Ls, env(r, 0, 7, str({chL(r + 1), H(r, -1), chL(r)})));
-  absorb(Ls, env(3, 0, 3, str({chB(0), chL(4)})));
-  for (int cc = 0; cc < 2; ++cc) {
-    absorb(Ls, env(0, cc, 4, str({chT(cc), V(-1, cc), chT(cc + 1)})));
-    for (int r = 0; r < 4; ++r) {
-      int k = c->kind(r0 + r, c0 + cc);
-      if (k == 0) {                                       // K: dense
-        absorb(Ls, site(r, cc, str({H(r, cc - 1), V(r - 1, cc), H(r, cc), V(r, cc)})));
-      } else if (k == 2) {                                // X: relabel
-        rename(Ls, H(r, cc - 1), H(r, cc));
-        rename(Ls, V(r - 1, cc), V(r, cc));
-      } else if (k == 1) {                                // cut Y: split the fused leg from K
-        Ls.t = split_axis(Ls.t, H(r, cc - 1), D, d, H(r, cc), kO(site_of(r, cc)));
-        rename(Ls, V(r - 1, cc), V(r, cc));
-      } else {                                            // B: bra end of the line exposed
-        TRef Bt = site(r, cc, "lurd");
-        Bt = split_axis(Bt, 'u', D, d, 'U', 'S');
-        Bt = relabel(Bt, str({H(r, cc - 1), V(r - 1, cc), bO(site_of(r - 1, cc)), H(r, cc), V(r, cc)}));
-        absorb(Ls, Bt);
-      }
-    }
-    absorb(Ls, env(3, cc, 6, str({chB(cc + 1), V(3, cc), chB(cc)})));
-  }
-  // ---- right half
-  Tmp Rs(&dev, c->st, {(int64_t)c->chi, (int64_t)c->chi}, str({chT(4), chR(0)}));
-  copy_into(dev, Rs.t, env(0, 3, 1, str({chT(4), chR(0)})));
-  for (int r = 0; r < 4; ++r) absorb(Rs, env(r, 3, 5, str({chR(r), H(r, 3), chR(r + 1)})));
-  absorb(Rs, env(3, 3, 2, str({chR(4), chB(4)})));
-  for (int cc = 3; cc >= 2; --cc) {
-    absorb(Rs, env(0, cc, 4, str({chT(cc), V(-1, cc), chT(cc + 1)})));
-    for (int r = 0; r < 4; ++r) {
-      int k = c->kind(r0 + r, c0 + cc);
-      if (k == 0) {                                       // K: fused right leg split, physical index open
-        TRef Kt = site(r, cc, "lurd");
-        Kt = split_axis(Kt, 'r', D, d, 'R', 'S');
-        Kt = relabel(Kt, str({H(r, cc - 1), V(r - 1, cc), Hd(r, cc), kO(site_of(r, cc)), V(r, cc)}));
-        absorb(Rs, Kt);
-      } else if (k == 2) {                                // X
-        rename(Rs, H(r, cc), H(r, cc - 1));
-        rename(Rs, V(r - 1, cc), V(r, cc));
-      } else if (k == 1) {                                // cut Y: hand the ket line to the K on the left
-        rename(Rs, H(r, cc), Hd(r, cc - 1));
-        rename(Rs, V(r - 1, cc), V(r, cc));
-      } else {                                            // B
-        TRef Bt = site(r, cc, "lurd");
-        Bt = split_axis(Bt, 'u', D, d, 'U', 'S');
-        Bt = relabel(Bt, str({H(r, cc - 1), V(r - 1, cc), bO(site_of(r - 1, cc)), H(r, cc), V(r, cc)}));
-        absorb(Rs, Bt);
-      }
-    }
-    absorb(Rs, env(3, cc, 6, str({chB(cc + 1), V(3, cc), chB(cc)})));
-  }
-  // ---- join
+  // ---- TL quadrant: C1, T1(0,0), T4(0,0), K(0,0), T1(0,1), Y(0,1), T4(1,0), X(1,0), B(1,1)
+  Tmp TL = start(env(0, 0, 0, str({chL(0), chT(0)})));
+  absorb(TL, env(0, 0, 4, str({chT(0), V(-1, 0), chT(1)})));
+  absorb(TL, env(0, 0, 7, str({chL(1), H(0, -1), chL(0)})));
+  absorb(TL, site(0, 0, str({H(0, -1), V(-1, 0), H(0, 0), V(0, 0)})));
+  absorb(TL, env(0, 1, 4, str({chT(1), V(-1, 1), chT(2)})));
+  TL.t = split_axis(TL.t, H(0, 0), D, d, H(0, 1), kO(0));              // Y(0,1): ket index opened
+  rename(TL, V(-1, 1), V(0, 1));
+  absorb(TL, env(1, 0, 7, str({chL(2), H(1, -1), chL(1)})));
+  rename(TL, H(1, -1), H(1, 0));                                       // X(1,0)
+  rename(TL, V(0, 0), V(1, 0));
+  absorb(TL, bra(1, 1, 0));                                            // B(1,1): bra index opened
+  // ---- TR quadrant: C2, T1(0,3), T2(0,3), Y(0,3), T1(0,2), K(0,2), T2(1,3), B(1,3), X(1,2)
+  Tmp TR = start(env(0, 3, 1, str({chT(4), chR(0)})));
+  absorb(TR, env(0, 3, 4, str({chT(3), V(-1, 3), chT(4)})));
+  absorb(TR, env(0, 3, 5, str({chR(0), H(0, 3), chR(1)})));
+  rename(TR, H(0, 3), Hd(0, 2));                                       // Y(0,3): virtual part of K's leg
+  rename(TR, V(-1, 3), V(0, 3));
+  absorb(TR, env(0, 2, 4, str({chT(2), V(-1, 2), chT(3)})));
+  absorb(TR, ket_open(0, 2, 1));                                       // K(0,2): ket index opened
+  absorb(TR, env(1, 3, 5, str({chR(1), H(1, 3), chR(2)})));
+  absorb(TR, bra(1, 3, 1));                                            // B(1,3)
+  rename(TR, H(1, 2), H(1, 1));                                        // X(1,2)
+  rename(TR, V(0, 2), V(1, 2));
+  // ---- BL quadrant: C4, T4(3,0), T3(3,0), X(3,0), T4(2,0), K(2,0), T3(3,1), B(3,1), Y(2,1)
+  Tmp BL = start(env(3, 0, 3, str({chB(0), chL(4)})));
+  absorb(BL, env(3, 0, 7, str({chL(4), H(3, -1), chL(3)})));
+  absorb(BL, env(3, 0, 6, str({chB(1), V(3, 0), chB(0)})));
+  rename(BL, H(3, -1), H(3, 0));                                       // X(3,0)
+  rename(BL, V(3, 0), V(2, 0));
+  absorb(BL, env(2, 0, 7, str({chL(3), H(2, -1), chL(2)})));
+  absorb(BL, site(2, 0, str({H(2, -1), V(1, 0), H(2, 0), V(2, 0)})));
+  absorb(BL, env(3, 1, 6, str({chB(2), V(3, 1), chB(1)})));
+  absorb(BL, bra(3, 1, 2));                                            // B(3,1)
+  BL.t = split_axis(BL.t, H(2, 0), D, d, H(2, 1), kO(2));              // Y(2,1)
+  rename(BL, V(2, 1), V(1, 1));
+  // ---- BR quadrant: C3, T2(3,3), T3(3,3), B(3,3), T2(2,3), Y(2,3), T3(3,2), X(3,2), K(2,2)
+  Tmp BR = start(env(3, 3, 2, str({chR(4), chB(4)})));
+  absorb(BR, env(3, 3, 5, str({chR(3), H(3, 3), chR(4)})));
+  absorb(BR, env(3, 3, 6, str({chB(4), V(3, 3), chB(3)})));
+  absorb(BR, bra(3, 3, 3));                                            // B(3,3)
+  absorb(BR, env(2, 3, 5, str({chR(2), H(2, 3), chR(3)})));
+  rename(BR, H(2, 3), Hd(2, 2));                                       // Y(2,3)
+  rename(BR, V(2, 3), V(1, 3));
+  absorb(BR, env(3, 2, 6, str({chB(3), V(3, 2), chB(2)})));
+  rename(BR, H(3, 2), H(3, 1));                                        // X(3,2)
+  rename(BR, V(3, 2), V(2, 2));
+  absorb(BR, ket_open(2, 2, 3));                                       // K(2,2)
+  // ---- halves and the join
+  absorb(TL, TR.t);   // over cT2, H(0,1), H(1,1)
+  absorb(BL, BR.t);   // over cB2, H(2,1), H(3,1)
   std::string ol = str({kO(0), kO(1), kO(2), kO(3), bO(0), bO(1), bO(2), bO(3)});
   std::vector<int64_t> od(8, d);
   if (c->st == T_F64) {
-    contract(dev, m, view(rho_out, T_F64, od, ol), Ls.t, Rs.t);
+    contract(dev, m, view(rho_out, T_F64, od, ol), TL.t, BL.t);
   } else {
     Tmp r32(&dev, c->st, od, ol);
-    contract(dev, m, r32.t, Ls.t, Rs.t);
+    contract(dev, m, r32.t, TL.t, BL.t);
     copy_into(dev, view(rho_out, T_F64, od, ol), r32.t);
   }
 }
