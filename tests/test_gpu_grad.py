@@ -142,3 +142,52 @@ def test_autograd_function(ctm_mod):
     (2.0 * E).backward()
     assert abs(E.item() - E_ref) < 1e-14
     assert torch.allclose(At.grad, 2.0 * grad_ref, rtol=0, atol=1e-14)
+
+
+def test_cfg2_heisenberg_d4_chi32(ctm_mod, monkeypatch):
+    """The D=4, chi=32 Heisenberg configuration (one tensor, N(0,1) seed 0):
+    40 oracle sweeps, then E and dE/dA after one differentiated sweep in FP64
+    and FP32 mode against the oracle, and central differences (h = 1e-6) of
+    the library's own FP64 energy on 20 seeded entries."""
+    cfg = synth.CONFIGS["heis_d4_chi32"]
+    A = synth.config_tensors(cfg, 0)
+    terms = synth.config_terms(cfg)
+    o = _converged(A, cfg["pattern"], cfg["chi"], 40)
+    Eo, go, _ = energy_and_grad(A, cfg["pattern"], cfg["chi"], o.env, 1, H, terms)
+    with monkeypatch.context() as mp:
+        mp.setattr(torch.linalg, "svd", _gesvd)
+        _, go2, _ = energy_and_grad(A, cfg["pattern"], cfg["chi"], o.env, 1, H, terms)
+    scale = go.abs().max().item()
+    spread = (go2 - go).abs().max().item()
+    env0 = env_to_flat(o.env, o.sites, cfg["chi"])
+    for precision, floor in (("fp64", 1e-8), ("fp32", 1e-5)):
+        g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"], precision=precision)
+        g.set_env(env0)
+        E, grad = g.energy_grad(1, H, terms)
+        err = (grad.cpu() - go).abs().max().item()
+        bar = max(floor * max(1.0, scale), 3 * spread)
+        print(f"cfg2 {precision}: |dE| {abs(E - Eo):.2e}; |dg|max {err:.2e} bar {bar:.2e} (|g|max {scale:.2e}, "
+              f"driver spread {spread:.2e})")
+        assert abs(E - Eo) < (1e-10 if precision == "fp64" else 1e-6) * max(1.0, abs(Eo))
+        assert err <= bar
+    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+    g.set_env(env0)
+    _, grad = g.energy_grad(1, H, terms)
+    grad = grad.cpu().reshape(-1)
+    flat = torch.as_tensor(A).reshape(-1)
+    rng = np.random.default_rng(11)
+    h = 1e-6
+    worst = 0.0
+    for idx in rng.choice(flat.numel(), 20, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            Ap = flat.clone()
+            Ap[idx] += sgn * h
+            g.set_tensors(Ap.reshape(A.shape))
+            g.set_env(env0)
+            g.sweep(1)
+            vals.append(g.energy(H, terms))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        worst = max(worst, abs(fd - grad[idx].item()))
+    print(f"cfg2 central differences: max |fd - grad| {worst:.2e} (|g|max {scale:.2e})")
+    assert worst < 1e-6 * max(1.0, scale)

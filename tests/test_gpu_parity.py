@@ -205,6 +205,25 @@ def test_full_size_ssm_d6_chi72_weakly_entangled(ctm_mod):
     assert abs(E - Eo) < 1e-10
 
 
+def test_full_size_heis_d9_chi100_weakly_entangled(ctm_mod):
+    """The D=9, chi=100, 2x1 Heisenberg shape (half systems of 1800 x 900, the
+    eight-column QR panels and Jacobi on 900 x 900): one sweep, corner spectra
+    of all 32 corners against the oracle (its energy at this size does not fit
+    a CPU's memory; the energy is compared at D=6 and below)."""
+    cfg = synth.CONFIGS["heis_d9_chi100"]
+    A = synth.near_product_tensors(cfg["n_tensors"], 2, cfg["D"], 5, 0.3)
+    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+    g.sweep(1)
+    o = OCTM(A, cfg["pattern"], cfg["chi"])
+    o.run(1)
+    so = corner_spectra(o.env, cfg["chi"])
+    cond_s, _ = rounding_spread(A, cfg["pattern"], cfg["chi"], 1, None, so, None, None)
+    sg = gpu_spectra(g.get_env(), o.sites, cfg["chi"])
+    err_s = (sg - so).abs().max().item()
+    print(f"heis_d9_chi100: spectra |d| {err_s:.2e} (oracle spread {cond_s:.2e})")
+    assert err_s <= 30 * cond_s + 1e-8
+
+
 def test_two_sweeps_from_sites_start(ctm_mod):
     cfg = synth.CONFIGS["heis_d2_chi8"]
     A = synth.config_tensors(cfg, 0)
