@@ -863,21 +863,30 @@ hipError_t launch_sub_sinv(const double* A, const double* B, int64_t rows, int64
 
 // ---------------------------------------------------------------------------
 // Block one-sided Jacobi: one round of the round-robin tournament over blocks
-// of BW columns.  One workgroup per block pair (2 BW columns of the n x n
-// column-major matrix A_b): it forms the Gram matrix G of the pair from the
-// columns (float64 dot products, rows staged through LDS in chunks), the
-// first wave runs cyclic two-sided Jacobi sweeps on G (at most ``inner``
-// sweeps, each pair rotated when |g_pq| > tol sqrt(g_pp g_qq) and both
-// columns are above the negligible size tiny2), accumulating the rotations in
-// R, and, if any was applied, the workgroup replaces the pair's columns of A
-// and V by A R and V R.  The number of rotations is added to rot[b].  The
-// pair threshold is the one of the scalar method, evaluated on dot products
-// of the current columns, so a round with no rotation anywhere certifies the
-// same orthogonality.
+// of BW columns.  One workgroup per block pair (C = 2 BW columns of the n x n
+// column-major matrix A_b):
+//  * the Gram matrix G = X^T X of the pair's columns X (n x C) on the FP64
+//    matrix cores: X^T X is a product whose two operands are the same
+//    registers (a lane holds X[k][m] for the A operand and X[k][n] for the B
+//    operand, with k the row of X), each wave summing a range of rows, the
+//    wave partials reduced through LDS in wave order;
+//  * the first wave runs cyclic two-sided Jacobi sweeps on G (at most
+//    ``inner`` sweeps, each pair rotated when |g_pq| > tol sqrt(g_pp g_qq) and
+//    both columns are above the negligible size tiny2), accumulating the
+//    rotations in R; meanwhile the other waves have their 16-row tiles of the
+//    pair's columns of A and V in flight;
+//  * if any rotation was applied, X <- X R and V_pair <- V_pair R, a 16 x C
+//    tile times the C x C matrix R per MFMA chain.
+// The number of rotations is added to rot[b].  The pair threshold is the one
+// of the scalar method, evaluated on dot products of the current columns, so
+// a round with no rotation anywhere certifies the same orthogonality.
 constexpr int BJ_BW = 8;            // columns per block
-constexpr int BJ_C = 2 * BJ_BW;     // columns per pair
-constexpr int BJ_CHUNK = 448;       // rows staged per chunk (56 KB of LDS)
-constexpr int BJ_NT = 256;          // threads per workgroup
+constexpr int BJ_C = 2 * BJ_BW;     // columns per pair (the MFMA tile width)
+constexpr int BJ_NT = 1024;         // threads per workgroup (one workgroup per CU: latency, not occupancy)
+constexpr int BJ_NW = BJ_NT / 64;   // waves
+constexpr int BJ_GK = 8;            // Gram k-steps (4 rows each) in flight per wave
+constexpr int BJ_TPW = 4;           // tiles per wave held in registers across the inner Jacobi
+static_assert(BJ_C == 16, "the pair is one 16-wide MFMA tile");
 
 // LDS traffic between the lanes of one wave: order the accesses without a
 // workgroup barrier (the other waves are not taking part).
@@ -890,11 +899,10 @@ __device__ __forceinline__ void wave_sync() {
 __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
                                                            int64_t stride, int round, double tol, const double* tiny2,
                                                            int inner, int* rot) {
-  __shared__ double xs[BJ_CHUNK * BJ_C];   // staged rows [row][col]
-  __shared__ double G[BJ_C * BJ_C];
-  __shared__ double R[BJ_C * BJ_C];
-  __shared__ double cs[BJ_C / 2][2];
-  __shared__ int pr[BJ_C / 2][2];
+  constexpr int GS = BJ_C + 1;                  // padded row stride of G and R (column accesses spread over banks)
+  __shared__ double part[BJ_NW][BJ_C * BJ_C];   // per-wave Gram partials
+  __shared__ double G[BJ_C * GS];
+  __shared__ double R[BJ_C * GS];
   __shared__ int nrot_s;
   const int k = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   int64_t P, Q;
@@ -912,114 +920,108 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     const int64_t g = c < BJ_BW ? c0P + c : c0Q + (c - BJ_BW);
     return g < n ? g : -1;
   };
-  // Gram matrix: thread owns upper-triangle entries e = tid + NT*j, (ea[j], eb[j])
-  constexpr int NE = BJ_C * (BJ_C + 1) / 2;
-  constexpr int GPT = (NE + BJ_NT - 1) / BJ_NT;
-  int ea[GPT], eb[GPT];
-  double acc[GPT];
+  const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+
+  // ---- Gram matrix: wave w takes the k-steps [w GK, (w + 1) GK) + j NW GK;
+  // lane (lr, lq) holds X[4 k + lq][lr]
+  {
+    d4_t gacc = {0.0, 0.0, 0.0, 0.0};
+    const int64_t nks = (n + 3) / 4;
+    const int64_t gl = gcol(lr);
+    for (int64_t kb = (int64_t)wave * BJ_GK; kb < nks; kb += (int64_t)BJ_GK * BJ_NW) {
+      double x[BJ_GK];
 #pragma unroll
-  for (int j = 0; j < GPT; ++j) {
-    ea[j] = -1; eb[j] = -1; acc[j] = 0.0;
-    const int e0 = tid + BJ_NT * j;
-    if (e0 < NE) {
-      int rem = e0, a = 0;
-      while (rem >= BJ_C - a) { rem -= BJ_C - a; ++a; }
-      ea[j] = a; eb[j] = a + rem;
+      for (int u = 0; u < BJ_GK; ++u) {
+        const int64_t row = (kb + u) * 4 + lq;
+        x[u] = (gl >= 0 && row < n) ? Ab[gl * n + row] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BJ_GK; ++u) gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], gacc, 0, 0, 0);
     }
+    // D layout of v_mfma_f64_16x16x4f64: register e of lane l holds row l/16 + 4 e, column l % 16
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[wave][(lq + 4 * e) * BJ_C + lr] = gacc[e];
   }
-  for (int64_t r0 = 0; r0 < n; r0 += BJ_CHUNK) {
-    const int rows = (int)((n - r0) < BJ_CHUNK ? (n - r0) : BJ_CHUNK);
-    // stage element e = c * CHUNK + i; groups of 7 loads in flight per thread
-    constexpr int PER = BJ_CHUNK * BJ_C / BJ_NT;   // 28
-    for (int u0 = 0; u0 < PER; u0 += 7) {
-      double v[7];
+
+  // ---- tiles of the rotation, loaded now: task t < 2 * tiles is the 16-row
+  // tile t mod tiles of A (t < tiles) or of V; lane (lr, lq) holds rows
+  // i0 + lr of the columns 4 ks + lq (the A operand of the product)
+  const int64_t tiles = (n + 15) / 16, ntask = 2 * tiles;
+  int64_t gA[4];
 #pragma unroll
-      for (int u = 0; u < 7; ++u) {
-        const int e = tid + (u0 + u) * BJ_NT, c = e / BJ_CHUNK, i = e - c * BJ_CHUNK;
-        const int64_t g = gcol(c);
-        v[u] = (g >= 0 && i < rows) ? Ab[g * n + r0 + i] : 0.0;
-      }
+  for (int ks = 0; ks < 4; ++ks) gA[ks] = gcol(4 * ks + lq);
+  auto load_tile = [&](int64_t t, double* x) {
+    const bool isA = t < tiles;
+    const double* M = isA ? Ab : Vb;
+    const int64_t row = (isA ? t : t - tiles) * 16 + lr;
 #pragma unroll
-      for (int u = 0; u < 7; ++u) {
-        const int e = tid + (u0 + u) * BJ_NT, c = e / BJ_CHUNK, i = e - c * BJ_CHUNK;
-        xs[i * BJ_C + c] = v[u];
-      }
-    }
-    __syncthreads();
+    for (int ks = 0; ks < 4; ++ks) x[ks] = (t < ntask && gA[ks] >= 0 && row < n) ? M[gA[ks] * n + row] : 0.0;
+  };
+  double pf[BJ_TPW][4];
 #pragma unroll
-    for (int j = 0; j < GPT; ++j) {
-      if (ea[j] < 0) continue;
-      const int pa = ea[j], pb = eb[j];
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int i = 0;
-      for (; i + 4 <= rows; i += 4) {
-        a0 += xs[i * BJ_C + pa] * xs[i * BJ_C + pb];
-        a1 += xs[(i + 1) * BJ_C + pa] * xs[(i + 1) * BJ_C + pb];
-        a2 += xs[(i + 2) * BJ_C + pa] * xs[(i + 2) * BJ_C + pb];
-        a3 += xs[(i + 3) * BJ_C + pa] * xs[(i + 3) * BJ_C + pb];
-      }
-      for (; i < rows; ++i) a0 += xs[i * BJ_C + pa] * xs[i * BJ_C + pb];
-      acc[j] += (a0 + a1) + (a2 + a3);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < GPT; ++j)
-    if (ea[j] >= 0) { G[ea[j] * BJ_C + eb[j]] = acc[j]; G[eb[j] * BJ_C + ea[j]] = acc[j]; }
-  for (int e = tid; e < BJ_C * BJ_C; e += BJ_NT) R[e] = (e / BJ_C == e % BJ_C) ? 1.0 : 0.0;
+  for (int u = 0; u < BJ_TPW; ++u) load_tile(wave + (int64_t)BJ_NW * u, pf[u]);
+
+  for (int el = tid; el < BJ_C * BJ_C; el += BJ_NT) R[(el / BJ_C) * GS + el % BJ_C] = (el / BJ_C == el % BJ_C) ? 1.0 : 0.0;
   __syncthreads();
+  if (tid < BJ_C * BJ_C) {
+    // the upper triangle's sums serve both halves, so G is exactly symmetric
+    const int m = tid / BJ_C, c = tid % BJ_C;
+    if (m <= c) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < BJ_NW; ++w) s += part[w][m * BJ_C + c];
+      G[m * GS + c] = s;
+      G[c * GS + m] = s;
+    }
+  }
+  __syncthreads();
+  // inner Jacobi on G (first wave): a round of the C-player tournament rotates
+  // C/2 disjoint pairs; lane (j, k) = (lane / 8, lane % 8) owns the 2 x 2
+  // blocks of G and R in the rows of pair j and the columns of pair k, so the
+  // round's update G <- J^T G J, R <- R J is local to the lane once it has the
+  // rotations of pairs j and k, which lane (j, j) computes from its block
   if (tid < 64) {
-    const int lane = tid;
     const double t2 = tiny2[b];
+    const int pj = lane >> 3, pk = lane & 7;
     int nrot = 0;
     for (int sw = 0; sw < inner; ++sw) {
       int sweep_rot = 0;
+#pragma unroll 1
       for (int rd = 0; rd < BJ_C - 1; ++rd) {
-        if (lane < BJ_C / 2) {
-          int p, q;
-          if (lane == 0) { p = rd; q = BJ_C - 1; }
-          else { p = (rd + lane) % (BJ_C - 1); q = (rd - lane + (BJ_C - 1)) % (BJ_C - 1); }
+        auto players = [&](int x, int& p, int& q) {
+          if (x == 0) { p = rd; q = BJ_C - 1; }
+          else { p = (rd + x) % (BJ_C - 1); q = (rd - x + (BJ_C - 1)) % (BJ_C - 1); }
           if (p > q) { int t = p; p = q; q = t; }
-          double al = G[p * BJ_C + p], be = G[q * BJ_C + q], ga = G[p * BJ_C + q];
-          double c = 1.0, sn = 0.0;
-          if (gcol(p) >= 0 && gcol(q) >= 0 && fmin(al, be) > t2 && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-            double zeta = (be - al) / (2.0 * ga);
-            double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = c * t;
-          }
-          pr[lane][0] = p; pr[lane][1] = q;
-          cs[lane][0] = c; cs[lane][1] = sn;
+        };
+        int p, q, p2, q2;
+        players(pj, p, q);
+        players(pk, p2, q2);
+        const double g00 = G[p * GS + p2], g01 = G[p * GS + q2], g10 = G[q * GS + p2], g11 = G[q * GS + q2];
+        double c = 1.0, sn = 0.0;
+        if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 &&
+            fabs(g01) > tol * sqrt(g00 * g11)) {
+          const double zeta = (g11 - g00) / (2.0 * g01);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = c * t;
         }
-        wave_sync();
-        int live = 0;
-        for (int j = 0; j < BJ_C / 2; ++j) live += cs[j][1] != 0.0;
+        const unsigned long long live = __ballot(sn != 0.0);
         if (live) {
-          sweep_rot += live;
-          // G <- J^T G (rows p, q): C/2 pairs x C columns
-#pragma unroll
-          for (int h = 0; h < (BJ_C / 2) * BJ_C / 64; ++h) {
-            int u = lane + 64 * h, j = u / BJ_C, col = u % BJ_C;
-            int p = pr[j][0], q = pr[j][1];
-            double c = cs[j][0], sn = cs[j][1];
-            double gp = G[p * BJ_C + col], gq = G[q * BJ_C + col];
-            G[p * BJ_C + col] = c * gp - sn * gq;
-            G[q * BJ_C + col] = sn * gp + c * gq;
-          }
-          wave_sync();
-          // G <- G J and R <- R J (columns p, q)
-#pragma unroll
-          for (int h = 0; h < (BJ_C / 2) * BJ_C / 64; ++h) {
-            int u = lane + 64 * h, j = u / BJ_C, row = u % BJ_C;
-            int p = pr[j][0], q = pr[j][1];
-            double c = cs[j][0], sn = cs[j][1];
-            double gp = G[row * BJ_C + p], gq = G[row * BJ_C + q];
-            G[row * BJ_C + p] = c * gp - sn * gq;
-            G[row * BJ_C + q] = sn * gp + c * gq;
-            double rp = R[row * BJ_C + p], rq = R[row * BJ_C + q];
-            R[row * BJ_C + p] = c * rp - sn * rq;
-            R[row * BJ_C + q] = sn * rp + c * rq;
-          }
+          sweep_rot += __popcll(live);
+          const double cj = __shfl(c, pj * 9), sj = __shfl(sn, pj * 9);
+          const double ck = __shfl(c, pk * 9), sk = __shfl(sn, pk * 9);
+          const double r00 = R[p * GS + p2], r01 = R[p * GS + q2], r10 = R[q * GS + p2], r11 = R[q * GS + q2];
+          // rows p, q by pair j, then columns p2, q2 by pair k
+          const double a00 = cj * g00 - sj * g10, a01 = cj * g01 - sj * g11;
+          const double a10 = sj * g00 + cj * g10, a11 = sj * g01 + cj * g11;
+          G[p * GS + p2] = ck * a00 - sk * a01;
+          G[p * GS + q2] = sk * a00 + ck * a01;
+          G[q * GS + p2] = ck * a10 - sk * a11;
+          G[q * GS + q2] = sk * a10 + ck * a11;
+          R[p * GS + p2] = ck * r00 - sk * r01;
+          R[p * GS + q2] = sk * r00 + ck * r01;
+          R[q * GS + p2] = ck * r10 - sk * r11;
+          R[q * GS + q2] = sk * r10 + ck * r11;
         }
         wave_sync();
       }
@@ -1033,25 +1035,33 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
   }
   __syncthreads();
   if (nrot_s == 0) return;
-  // columns of the pair <- columns R (A and V); a thread owns rows
-  for (int mat = 0; mat < 2; ++mat) {
-    double* M = mat == 0 ? Ab : Vb;
-    for (int64_t i = tid; i < n; i += BJ_NT) {
-      double row[BJ_C];
+
+  // ---- X <- X R, V_pair <- V_pair R: B operand R[4 ks + lq][lr]; the
+  // result's lane (lr, lq) register e is row i0 + lq + 4 e of column lr
+  double rb[4];
 #pragma unroll
-      for (int c = 0; c < BJ_C; ++c) {
-        const int64_t g = gcol(c);
-        row[c] = g >= 0 ? M[g * n + i] : 0.0;
-      }
-#pragma unroll 4
-      for (int c = 0; c < BJ_C; ++c) {
-        double v = 0.0;
+  for (int ks = 0; ks < 4; ++ks) rb[ks] = R[(4 * ks + lq) * GS + lr];
+  const int64_t gD = gcol(lr);
+  auto store_tile = [&](int64_t t, const double* x) {
+    if (t >= ntask) return;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < BJ_C; ++j) v += row[j] * R[j * BJ_C + c];
-        const int64_t g = gcol(c);
-        if (g >= 0) M[g * n + i] = v;
-      }
+    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks], rb[ks], acc, 0, 0, 0);
+    const bool isA = t < tiles;
+    double* M = isA ? Ab : Vb;
+    const int64_t i0 = (isA ? t : t - tiles) * 16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = i0 + lq + 4 * e;
+      if (gD >= 0 && row < n) M[gD * n + row] = acc[e];
     }
+  };
+#pragma unroll
+  for (int u = 0; u < BJ_TPW; ++u) store_tile(wave + (int64_t)BJ_NW * u, pf[u]);
+  for (int64_t t = wave + (int64_t)BJ_NW * BJ_TPW; t < ntask; t += BJ_NW) {
+    double x[4];
+    load_tile(t, x);
+    store_tile(t, x);
   }
 }
 
