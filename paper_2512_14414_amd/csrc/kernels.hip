@@ -943,9 +943,11 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     for (int e = 0; e < 4; ++e) part[wave][(lq + 4 * e) * BJ_C + lr] = gacc[e];
   }
 
-  // ---- tiles of the rotation, loaded now: task t < 2 * tiles is the 16-row
-  // tile t mod tiles of A (t < tiles) or of V; lane (lr, lq) holds rows
-  // i0 + lr of the columns 4 ks + lq (the A operand of the product)
+  // ---- tiles of the rotation: task t < 2 * tiles is the 16-row tile
+  // t mod tiles of A (t < tiles) or of V; lane (lr, lq) holds rows i0 + lr of
+  // the columns 4 ks + lq.  The waves after the first take tasks
+  // wave - 1 + (NW - 1) u and load the first TPW of them while the first wave
+  // runs the inner Jacobi.
   const int64_t tiles = (n + 15) / 16, ntask = 2 * tiles;
   int64_t gA[4];
 #pragma unroll
@@ -957,9 +959,8 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) x[ks] = (t < ntask && gA[ks] >= 0 && row < n) ? M[gA[ks] * n + row] : 0.0;
   };
+  constexpr int AW = BJ_NW - 1;   // waves applying the rotation
   double pf[BJ_TPW][4];
-#pragma unroll
-  for (int u = 0; u < BJ_TPW; ++u) load_tile(wave + (int64_t)BJ_NW * u, pf[u]);
 
   for (int el = tid; el < BJ_C * BJ_C; el += BJ_NT) R[(el / BJ_C) * GS + el % BJ_C] = (el / BJ_C == el % BJ_C) ? 1.0 : 0.0;
   __syncthreads();
@@ -975,6 +976,10 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     }
   }
   __syncthreads();
+  if (wave > 0) {
+#pragma unroll
+    for (int u = 0; u < BJ_TPW; ++u) load_tile(wave - 1 + (int64_t)AW * u, pf[u]);
+  }
   // inner Jacobi on G (first wave): a round of the C-player tournament rotates
   // C/2 disjoint pairs; lane (j, k) = (lane / 8, lane % 8) owns the 2 x 2
   // blocks of G and R in the rows of pair j and the columns of pair k, so the
@@ -997,6 +1002,7 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
         players(pj, p, q);
         players(pk, p2, q2);
         const double g00 = G[p * GS + p2], g01 = G[p * GS + q2], g10 = G[q * GS + p2], g11 = G[q * GS + q2];
+        const double r00 = R[p * GS + p2], r01 = R[p * GS + q2], r10 = R[q * GS + p2], r11 = R[q * GS + q2];
         double c = 1.0, sn = 0.0;
         if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 &&
             fabs(g01) > tol * sqrt(g00 * g11)) {
@@ -1010,7 +1016,6 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
           sweep_rot += __popcll(live);
           const double cj = __shfl(c, pj * 9), sj = __shfl(sn, pj * 9);
           const double ck = __shfl(c, pk * 9), sk = __shfl(sn, pk * 9);
-          const double r00 = R[p * GS + p2], r01 = R[p * GS + q2], r10 = R[q * GS + p2], r11 = R[q * GS + q2];
           // rows p, q by pair j, then columns p2, q2 by pair k
           const double a00 = cj * g00 - sj * g10, a01 = cj * g01 - sj * g11;
           const double a10 = sj * g00 + cj * g10, a11 = sj * g01 + cj * g11;
@@ -1034,31 +1039,34 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     }
   }
   __syncthreads();
-  if (nrot_s == 0) return;
+  if (nrot_s == 0 || wave == 0) return;
 
-  // ---- X <- X R, V_pair <- V_pair R: B operand R[4 ks + lq][lr]; the
-  // result's lane (lr, lq) register e is row i0 + lq + 4 e of column lr
+  // ---- X <- X R, V_pair <- V_pair R, formed transposed, (X R)^T = R^T X^T,
+  // so that a store instruction writes whole 16-row column segments: the A
+  // operand is R^T (lane (lr, lq) holds R[4 ks + lq][lr]), the B operand X^T
+  // is the tile as loaded, and register e of lane (lr, lq) is row i0 + lr of
+  // column lq + 4 e
   double rb[4];
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) rb[ks] = R[(4 * ks + lq) * GS + lr];
-  const int64_t gD = gcol(lr);
+  int64_t gD[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) gD[e] = gcol(lq + 4 * e);
   auto store_tile = [&](int64_t t, const double* x) {
     if (t >= ntask) return;
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks], rb[ks], acc, 0, 0, 0);
+    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rb[ks], x[ks], acc, 0, 0, 0);
     const bool isA = t < tiles;
     double* M = isA ? Ab : Vb;
-    const int64_t i0 = (isA ? t : t - tiles) * 16;
+    const int64_t row = (isA ? t : t - tiles) * 16 + lr;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t row = i0 + lq + 4 * e;
-      if (gD >= 0 && row < n) M[gD * n + row] = acc[e];
-    }
+    for (int e = 0; e < 4; ++e)
+      if (gD[e] >= 0 && row < n) M[gD[e] * n + row] = acc[e];
   };
 #pragma unroll
-  for (int u = 0; u < BJ_TPW; ++u) store_tile(wave + (int64_t)BJ_NW * u, pf[u]);
-  for (int64_t t = wave + (int64_t)BJ_NW * BJ_TPW; t < ntask; t += BJ_NW) {
+  for (int u = 0; u < BJ_TPW; ++u) store_tile(wave - 1 + (int64_t)AW * u, pf[u]);
+  for (int64_t t = wave - 1 + (int64_t)AW * BJ_TPW; t < ntask; t += AW) {
     double x[4];
     load_tile(t, x);
     store_tile(t, x);
