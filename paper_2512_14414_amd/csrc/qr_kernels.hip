@@ -19,7 +19,6 @@
 
 namespace qrk {
 
-constexpr int NT = 256;   // threads of the panel and update kernels
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -27,7 +26,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sums v over the workgroup; every thread receives the total.  ``red`` holds NT/64 doubles.
+// Sums v over a workgroup of NTT threads; every thread receives the total.  ``red`` holds NTT/64 doubles.
+template <int NTT>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
@@ -36,20 +36,58 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  for (int i = 0; i < NTT / 64; ++i) s += red[i];
   return s;
 }
 
-template <int RPT, int NB>
-__global__ __launch_bounds__(NT) void panel_kernel(double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m,
-                                                   int64_t n, int64_t j0, double* tau, int64_t tau_stride, double* T,
-                                                   int64_t T_stride) {
-  __shared__ double red[NT / 64];
-  __shared__ double redv[NT / 64][NB];
+// Sums NV values (NV a power of two, at most 64) over the 64 lanes of a wave by
+// recursive halving: at each level a lane keeps half of its values, sends the
+// other half to the partner lane and adds what it receives, so lane l ends
+// with the wave total of value l / (64 / NV).  x is overwritten.  The levels
+// are template recursion so that every index is a compile-time constant.
+template <int H, int MASK>
+__device__ __forceinline__ void halving(double* x, int lane) {
+  if constexpr (H >= 1) {
+    const bool hi = lane & MASK;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double send = hi ? x[i] : x[i + H];
+      const double keep = hi ? x[i + H] : x[i];
+      x[i] = keep + __shfl_xor(send, MASK, 64);
+    }
+    halving<H / 2, MASK / 2>(x, lane);
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ double wave_reduce(double* x) {
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "power of two");
+  const int lane = threadIdx.x & 63;
+  halving<NV / 2, 32>(x, lane);
+  double v = x[0];
+#pragma unroll
+  for (int o = 32 / NV; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// The column loop is a real loop: unrolled, each column would run its own
+// straight-line code once, and the kernel would wait on instruction fetch.
+// Column c of the register panel is read and replaced by select chains over
+// the (unrolled) column index, which keeps the panel in registers.
+template <int RPT, int NB, int NTT>
+__global__ __launch_bounds__(NTT) void panel_kernel(double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m,
+                                                    int64_t n, int64_t j0, double* tau, int64_t tau_stride, double* T,
+                                                    int64_t T_stride) {
+  constexpr int NW = NTT / 64;
+  static_assert(NB * NB <= NTT && 64 % NB == 0, "panel shape");
+  __shared__ double red[NW];
+  __shared__ double redv[NW][NB];
+  __shared__ double wfin[2][NB];
   __shared__ double bc[2];
   __shared__ double Gs[NB][NB];
+  __shared__ double Tr[NB][NB];
   __shared__ double taus_s[NB];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = blockIdx.x;
   double* Ab = A + (int64_t)b * stride;
   const int64_t k = m < n ? m : n;
@@ -57,24 +95,31 @@ __global__ __launch_bounds__(NT) void panel_kernel(double* A, int64_t rs, int64_
   double a[RPT][NB];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t i = j0 + tid + (int64_t)NT * q;
+    const int64_t i = j0 + tid + (int64_t)NTT * q;
 #pragma unroll
     for (int c = 0; c < NB; ++c) a[q][c] = (i < m && c < nbp) ? Ab[i * rs + (j0 + c) * cs] : 0.0;
   }
   if (tid < NB) taus_s[tid] = 0.0;
+  if (tid < NB * NB) Gs[tid / NB][tid % NB] = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < nbp; ++c) {
+    double ac[RPT];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c >= nbp) continue;
+    for (int q = 0; q < RPT; ++q) {
+      ac[q] = a[q][0];
+#pragma unroll
+      for (int i = 1; i < NB; ++i) ac[q] = c == i ? a[q][i] : ac[q];
+    }
     // sigma = |x below the diagonal|^2, alpha = diagonal element (local row c, thread c, q = 0)
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = tid + NT * q;
-      if (r > c && j0 + r < m) part += a[q][c] * a[q][c];
+      const int r = tid + NTT * q;
+      if (r > c && j0 + r < m) part += ac[q] * ac[q];
     }
     // alternate slots: the next write to this slot comes after two more block sums
-    if (tid == c) bc[c & 1] = a[0][c];
-    const double sigma = block_sum(part, red);   // its barriers publish bc
+    if (tid == c) bc[c & 1] = ac[0];
+    const double sigma = block_sum<NTT>(part, red);   // its barriers publish bc
     const double alpha = bc[c & 1];
     double t = 0.0, beta = alpha, scale = 0.0;
     if (sigma > 0.0) {
@@ -86,110 +131,79 @@ __global__ __launch_bounds__(NT) void panel_kernel(double* A, int64_t rs, int64_
     // v below the diagonal; beta on the diagonal
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = tid + NT * q;
-      if (r > c && j0 + r < m) a[q][c] *= scale;
+      const int r = tid + NTT * q;
+      if (r > c && j0 + r < m) ac[q] *= scale;
     }
-    if (tid == c) a[0][c] = beta;
+    if (tid == c) ac[0] = beta;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int i = 0; i < NB; ++i) a[q][i] = c == i ? ac[q] : a[q][i];
     if (t == 0.0) continue;
-    // w_c' = v . A[:, c'] for c' > c, then A[:, c'] -= t v w_c'
-    double wpart[NB];
+    // one reduction gives w_cc = v . A[:, cc] for the trailing columns cc > c
+    // and v_l . v for the earlier vectors l < c (column c of V^T V, for T):
+    // below row c both read the stored column, and v vanishes above row c
+    double x[NB];
 #pragma unroll
-    for (int cc = 0; cc < NB; ++cc) wpart[cc] = 0.0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = tid + NT * q;
-      if (r < c || j0 + r >= m) continue;
-      const double v = r == c ? 1.0 : a[q][c];
-#pragma unroll
-      for (int cc = c + 1; cc < NB; ++cc) wpart[cc] += v * a[q][cc];
-    }
-#pragma unroll
-    for (int cc = c + 1; cc < NB; ++cc) wpart[cc] = wave_sum(wpart[cc]);
-    __syncthreads();
-    if ((tid & 63) == 0)
-#pragma unroll
-      for (int cc = c + 1; cc < NB; ++cc) redv[tid >> 6][cc] = wpart[cc];
-    __syncthreads();
-#pragma unroll
-    for (int cc = c + 1; cc < NB; ++cc) {
-      double w = 0.0;
-#pragma unroll
-      for (int i = 0; i < NT / 64; ++i) w += redv[i][cc];
-      wpart[cc] = w * t;
-    }
+    for (int cc = 0; cc < NB; ++cc) x[cc] = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = tid + NT * q;
+      const int r = tid + NTT * q;
       if (r < c || j0 + r >= m) continue;
-      const double v = r == c ? 1.0 : a[q][c];
+      const double v = r == c ? 1.0 : ac[q];
 #pragma unroll
-      for (int cc = c + 1; cc < NB; ++cc) a[q][cc] -= v * wpart[cc];
+      for (int cc = 0; cc < NB; ++cc) x[cc] += cc != c ? v * a[q][cc] : 0.0;
+    }
+    const double tot = wave_reduce<NB>(x);
+    if (lane % (64 / NB) == 0) redv[wave][lane / (64 / NB)] = tot;
+    __syncthreads();
+    if (tid < NB) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sum += redv[w][tid];
+      wfin[c & 1][tid] = sum;
+      if (tid < c) Gs[tid][c] = sum;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + NTT * q;
+      if (r < c || j0 + r >= m) continue;
+      const double vt = (r == c ? 1.0 : ac[q]) * t;
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc)
+        if (cc > c) a[q][cc] -= vt * wfin[c & 1][cc];
     }
   }
   // store the panel
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t i = j0 + tid + (int64_t)NT * q;
+    const int64_t i = j0 + tid + (int64_t)NTT * q;
     if (i >= m) continue;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c < nbp) Ab[i * rs + (j0 + c) * cs] = a[q][c];
   }
-  // T of the block reflector (LAPACK's larft, forward, columnwise):
-  // G = V^T V, T_cc = tau_c, T[i][c] = -tau_c sum_{l=i}^{c-1} T[i][l] G[l][c].
-  // Row c of G (entries cc > c) is summed over the workgroup in one reduction.
-  if (tid < NB * NB) Gs[tid / NB][tid % NB] = 0.0;
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c + 1 >= nbp) break;
-    double gp[NB];
-#pragma unroll
-    for (int cc = 0; cc < NB; ++cc) gp[cc] = 0.0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = tid + NT * q;
-      if (r <= c || j0 + r >= m) continue;   // v_cc vanishes above row cc > c, so r > c
-#pragma unroll
-      for (int cc = c + 1; cc < NB; ++cc) {
-        if (r < cc) continue;
-        gp[cc] += a[q][c] * (r == cc ? 1.0 : a[q][cc]);
-      }
-    }
-#pragma unroll
-    for (int cc = c + 1; cc < NB; ++cc) gp[cc] = wave_sum(gp[cc]);
-    __syncthreads();
-    if ((tid & 63) == 0)
-#pragma unroll
-      for (int cc = c + 1; cc < NB; ++cc) redv[tid >> 6][cc] = gp[cc];
-    __syncthreads();
-    if (tid < NB && tid > c) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < NT / 64; ++i) s += redv[i][tid];
-      Gs[c][tid] = s;
-    }
-  }
+  // T of the block reflector (LAPACK's larft, forward, columnwise) from
+  // G = V^T V (upper triangle, gathered above): T_cc = tau_c,
+  // T[i][c] = -tau_c sum_{l=i}^{c-1} T[i][l] G[l][c]; thread i < NB computes
+  // row i (it depends on that row only)
   __syncthreads();
-  // thread i < NB computes row i of T (it depends on that row only)
   if (tid < NB) {
     const int i = tid;
     double* Tb = T + (int64_t)b * T_stride;
-    double Trow[NB];
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < NB; ++c) {
       double v = 0.0;
       if (c < nbp && c == i) v = taus_s[c];
       else if (c < nbp && c > i) {
         double s = 0.0;
-#pragma unroll
-        for (int l = 0; l < NB; ++l)
-          if (l >= i && l < c) s += Trow[l] * Gs[l][c];
+        for (int l = i; l < c; ++l) s += Tr[i][l] * Gs[l][c];
         v = -taus_s[c] * s;
       }
-      Trow[c] = v;
+      Tr[i][c] = v;
+      Tb[i * NB + c] = v;
     }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) Tb[i * NB + c] = Trow[c];
     if (i < nbp) tau[(int64_t)b * tau_stride + j0 + i] = taus_s[i];
   }
 }
@@ -220,42 +234,48 @@ __global__ __launch_bounds__(256) void build_vy_kernel(const double* A, int64_t 
     double* Vr = V + ((int64_t)b * L + r) * NB;
     double* Yr = Y + ((int64_t)b * L + r) * NB;
 #pragma unroll
+    for (int c = 0; c < NB; ++c) Vr[c] = v[c];
+    // one output column at a time: hoisting all NB*NB entries of T would not fit the registers
+#pragma unroll 1
     for (int c = 0; c < NB; ++c) {
       double y = 0.0;
 #pragma unroll
       for (int l = 0; l < NB; ++l) y += v[l] * Ts[c * NB + l];
-      Vr[c] = v[c];
       Yr[c] = y;
     }
   }
 }
 
-static int pick_rpt(int64_t rows) {
-  if (rows <= NT) return 1;
-  if (rows <= 2 * NT) return 2;
-  if (rows <= 4 * NT) return 4;
-  if (rows <= 8 * NT) return 8;
+// Panel shapes: RPT rows per thread in a workgroup of NTT threads, one
+// register row per thread up to 1024 rows (more threads rather than more
+// rows per thread: the per-thread panel must stay in registers).
+static int panel_threads(int64_t rows) {
+  if (rows <= 256) return 256;
+  if (rows <= 512) return 512;
+  if (rows <= 1024) return 1024;
+  if (rows <= 2048) return 256 * 8;   // eight-column panels, 8 rows per thread, 256 threads
   return 0;
 }
 
-int panel_width(int64_t m) { return pick_rpt(m) == 8 ? 8 : 16; }
+int panel_width(int64_t m) { return m <= 1024 ? 16 : 8; }
 
 hipError_t launch_panel(double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m, int64_t n, int64_t j0, int batch,
                         double* tau, int64_t tau_stride, double* T, int64_t T_stride, hipStream_t s) {
-  const int rpt = pick_rpt(m - j0 > 0 ? m - j0 : 1);
-  const int nb = panel_width(m);
   if (batch <= 0) return hipSuccess;
-  // rows of the panel: local row r = tid + NT*q covers m - j0 rows
+  const int64_t rows = m - j0 > 0 ? m - j0 : 1;
+  const int nb = panel_width(m);
+  const int nt = panel_threads(rows);
+  if (nt == 0) return hipErrorInvalidValue;
+  // rows of the panel: local row r = tid + NTT*q covers m - j0 rows
   if (nb == 16) {
-    switch (rpt) {
-      case 1: panel_kernel<1, 16><<<batch, NT, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
-      case 2: panel_kernel<2, 16><<<batch, NT, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
-      case 4: panel_kernel<4, 16><<<batch, NT, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
+    switch (nt) {
+      case 256: panel_kernel<1, 16, 256><<<batch, 256, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
+      case 512: panel_kernel<1, 16, 512><<<batch, 512, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
+      case 1024: panel_kernel<2, 16, 512><<<batch, 512, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
       default: return hipErrorInvalidValue;
     }
   } else {
-    if (rpt == 0) return hipErrorInvalidValue;
-    panel_kernel<8, 8><<<batch, NT, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride);
+    panel_kernel<8, 8, 256><<<batch, 256, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride);
   }
   return hipGetLastError();
 }
