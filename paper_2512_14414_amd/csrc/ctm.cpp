@@ -1314,6 +1314,8 @@ void ctm_free(ctm_ctx* c) {
     t->A64.reset(); t->site_buf.reset(); t->env.reset(); t->spec_prev.reset(); t->spec_cur.reset();
     t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset();
   }
+  c->tape.clear();
+  c->dev.release();
   (void)hipStreamSynchronize(c->dev.stream);
   if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;

@@ -1,6 +1,9 @@
 // Contraction planner: labelled tensors -> batched MFMA contraction kernel.
 #include "engine.h"
 
+#include <mutex>
+#include <set>
+
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -75,11 +78,78 @@ TRef split_axis(const TRef& t, char label, int64_t a, int64_t b, char lab_major,
   return r;
 }
 
-void* Dev::alloc(size_t bytes) {
+// Freed blocks stay in the device's default memory pool across
+// synchronisations (its release threshold raised to the maximum): a sweep
+// allocates and frees its workspaces thousands of times, and with the
+// default threshold of zero every synchronisation would hand them back to the
+// driver.  Done once per device.
+static void retain_pool_memory() {
+  static std::mutex mu;
+  static std::set<int> done;
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!done.insert(d).second) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, d) != hipSuccess) return;
+  uint64_t threshold = UINT64_MAX;
+  (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+}
+
+// Size classes: multiples of 256 bytes up to 4 KiB, then 2^k and 3 * 2^(k-1)
+// (at most a third of a block unused).
+static size_t size_class(size_t b) {
+  if (b <= 4096) return (b + 255) & ~(size_t)255;
+  const size_t p = (size_t)1 << (63 - __builtin_clzll(b));
+  if (b == p) return b;
+  const size_t mid = p + (p >> 1);
+  return b <= mid ? mid : 2 * p;
+}
+
+void* Dev::take(size_t bytes) {
+  if (!pool_ready) {
+    retain_pool_memory();
+    pool_ready = true;
+  }
+  const size_t sz = size_class(bytes == 0 ? 8 : bytes);
+  auto it = cached.find(sz);
+  if (it != cached.end() && !it->second.empty()) {
+    void* p = it->second.back();
+    it->second.pop_back();
+    live[p] = sz;
+    return p;
+  }
   void* p = nullptr;
-  if (bytes == 0) bytes = 8;
-  hipError_t e = hipMallocAsync(&p, bytes, stream);
+  hipError_t e = hipMallocAsync(&p, sz, stream);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    release();
+    (void)hipStreamSynchronize(stream);
+    e = hipMallocAsync(&p, sz, stream);
+  }
   if (e != hipSuccess) throw Error(e == hipErrorOutOfMemory ? -2 : -3, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  live[p] = sz;
+  return p;
+}
+
+void Dev::give(void* p) {
+  auto it = live.find(p);
+  if (it == live.end()) {   // not from take(): straight back to the pool
+    (void)hipFreeAsync(p, stream);
+    return;
+  }
+  cached[it->second].push_back(p);
+  live.erase(it);
+}
+
+void Dev::release() {
+  for (auto& kv : cached)
+    for (void* p : kv.second) (void)hipFreeAsync(p, stream);
+  cached.clear();
+}
+
+void* Dev::alloc(size_t bytes) {
+  void* p = take(bytes);
   if (tape && tape->recording()) tape->reg(p, bytes);
   return p;
 }
@@ -90,7 +160,7 @@ void Dev::free(void* p) {
     tape->retained.push_back(p);
     return;
   }
-  (void)hipFreeAsync(p, stream);
+  give(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -127,7 +197,7 @@ void* Tape::adj_ptr(const void* p) {
   if (it == bufs.end()) throw Error(-1, "tape: adjoint of an unregistered buffer");
   Buf& b = it->second;
   if (!b.adj) {
-    HIP_CHECK(hipMallocAsync(&b.adj, b.bytes, dev->stream));
+    b.adj = dev->take(b.bytes);
     HIP_CHECK(hipMemsetAsync(b.adj, 0, b.bytes, dev->stream));
     b.own = true;
   }
@@ -170,9 +240,9 @@ void Tape::clear() {
   on = false;
   ops.clear();
   for (auto& kv : bufs)
-    if (kv.second.own && kv.second.adj) (void)hipFreeAsync(kv.second.adj, dev->stream);
+    if (kv.second.own && kv.second.adj) dev->give(kv.second.adj);
   bufs.clear();
-  for (void* p : retained) (void)hipFreeAsync(p, dev->stream);
+  for (void* p : retained) dev->give(p);
   retained.clear();
   if (dev) dev->tape = nullptr;
 }
@@ -313,8 +383,8 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
   // few output tiles and a long sum: split K over more workgroups (partials in a workspace)
   DBuf work;
   const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
-  if (tiles < 128 && g.K >= 2048) {
-    int64_t want = std::min<int64_t>((512 + tiles - 1) / tiles, g.K / 512);
+  if (tiles < 128 && g.K >= 256) {
+    int64_t want = std::min<int64_t>((512 + tiles - 1) / tiles, g.K / 128);
     if (want > 1) {
       g.kchunk = ((g.K + want - 1) / want + 31) / 32 * 32;
       g.ksplit = (g.K + g.kchunk - 1) / g.kchunk;

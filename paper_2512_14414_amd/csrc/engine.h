@@ -8,6 +8,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.h"
@@ -53,11 +54,29 @@ struct Tape;
 // Stream-ordered device memory.  While a tape records, every allocation is
 // registered with it and frees are deferred until the tape is cleared, so that
 // the values a backward pass needs stay alive.
+//
+// Freed blocks are cached per size class and handed out again: all work of a
+// Dev is queued on its one stream, so a block freed after the kernels that use
+// it were queued may serve any later request on that stream.  (The
+// stream-ordered allocator costs several microseconds of host time per call,
+// and a sweep allocates thousands of workspaces.)  The cache goes back to the
+// device pool when the Dev is destroyed, and before a request that the pool
+// cannot otherwise satisfy.
 struct Dev {
   hipStream_t stream = nullptr;
   Tape* tape = nullptr;
-  void* alloc(size_t bytes);
-  void free(void* p);
+  bool pool_ready = false;
+  std::unordered_map<void*, size_t> live;                    // block -> size class
+  std::unordered_map<size_t, std::vector<void*>> cached;     // size class -> free blocks
+  Dev() = default;
+  Dev(const Dev&) = delete;
+  Dev& operator=(const Dev&) = delete;
+  ~Dev() { release(); }
+  void* alloc(size_t bytes);   // take(), registered with a recording tape
+  void free(void* p);          // give(), deferred while a tape records
+  void* take(size_t bytes);    // a cached block of the size class, else a new one
+  void give(void* p);          // back to the cache
+  void release();              // cached blocks back to the device pool
 };
 
 // Owning device buffer released on the stream.

@@ -192,6 +192,7 @@ void sur_free(sur_net* s) {
   (void)hipStreamSynchronize(s->dev.stream);
   s->params.reset();
   s->stats.reset();
+  s->dev.release();
   (void)hipStreamSynchronize(s->dev.stream);
   delete s;
 }
