@@ -32,10 +32,38 @@ METRIC = "CTMRG sweeps/s + E&grad evals/s at D=6,chi=72 (mixed vs FP64), |dE| vs
 # MI355X peaks: dense matrix cores per path, FP64 vector ALU for the Jacobi and QR families
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "jacobi": 78.6, "qr_panel": 78.6}
 BOUND = {"fp64": "mfma", "fp32": "mfma", "bf16": "mfma", "jacobi": "alu", "qr_panel": "alu"}
+# HBM traffic per launch of the Jacobi round kernel from two rocprofv3 --pmc
+# passes over a one-sweep run of this workload (FETCH_SIZE, then WRITE_SIZE, KiB
+# per dispatch), each scaled by what the counter reads for a copy of known size
+# (bench.py --copy-probe 256: FETCH_SIZE reads half of the bytes copied, so x2;
+# WRITE_SIZE reads them exactly, x1).  Valid for the kernel source it was taken
+# on (hash of the kernel's text), else reported as null.
+TRAFFIC = {"jacobi": {"fetch_kib": 5902.6, "fetch_scale": 2.0, "write_kib": 3986.0, "write_scale": 1.0,
+                      "source_sha256": "1db827e3c7bbded1bdc34ef1b3cb68015e52a6fa6286c418dcd24967c5457624",
+                      "source": ("paper_2512_14414_amd/csrc/kernels.hip", "constexpr int BJ_BW = 8;",
+                                 "hipError_t launch_bjac_round(")}}
 KERNEL = {"fp64": "contract_kernel<MODE_F64> (FP64 MFMA)", "fp32": "contract_kernel<MODE_F32> (FP32 MFMA)",
           "bf16": "contract_kernel<MODE_BF16> (BF16 MFMA, FP32 accumulation)",
           "jacobi": "bjac_round_kernel (block one-sided Jacobi round, FP64)",
           "qr_panel": "panel_kernel (Householder QR panel, FP64)"}
+
+
+def traffic_per_launch(fam):
+    """HBM bytes per launch of family ``fam`` from the counter runs, or None
+    when none were taken or the kernel's source changed since."""
+    import hashlib
+    t = TRAFFIC.get(fam)
+    if t is None:
+        return None
+    path, first, last = t["source"]
+    try:
+        text = open(os.path.join(ROOT, path)).read()
+        a, b = text.index(first), text.index(last)
+    except (OSError, ValueError):
+        return None
+    if hashlib.sha256(text[a:b].encode()).hexdigest() != t["source_sha256"]:
+        return None
+    return round(1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
 
 
 def main():
@@ -175,8 +203,10 @@ def main():
         "peak": PEAK_TFLOPS[fam],
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_TFLOPS[fam], 6),
-        "traffic": None,
+        "traffic": traffic_per_launch(fam),
+        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
         "launches_per_sweep": launches,
+        # event-timed: includes the dispatch gap between back-to-back launches
         "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
         "algorithmic_flops_per_sweep": flops,
         "kernel_ms_per_sweep": round(ms, 3),
