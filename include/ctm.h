@@ -141,7 +141,11 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
 /* Options (key, value):
  *   "svd_cutoff"  relative cutoff below which s^(-1/2) is set to zero (default 1e-10)
  *   "lorentz_eta" relative Lorentzian width of the SVD derivative (default 1e-12)
- *   "check_finite" 1 to test the environment for NaN/Inf after every sweep (default 1) */
+ *   "check_finite" 1 to test the environment for NaN/Inf after every sweep (default 1)
+ *   "streams"     2 (default) to run the odd rows of a column step (half systems,
+ *                 their QR) on a second stream created by the library, joined
+ *                 back before the SVD, in sweeps that are not differentiated;
+ *                 1 for one stream.  Both give identical results. */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
 /* Live timing of the library's main kernel families.  Between

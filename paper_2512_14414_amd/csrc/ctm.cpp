@@ -90,6 +90,22 @@ struct ctm_ctx {
   // fresh buffer so that the values read before stay intact for the reverse pass.
   std::vector<void*> slot_ptr;
   Tape tape;
+  // Second stream for the independent half of a column step (the odd rows:
+  // half systems, their QR, their part of M) in sweeps that are not recorded;
+  // it has its own allocator cache, and every fork from the main stream is
+  // joined back before the main stream uses its results.
+  Dev side;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int streams = 2;
+
+  void fork() {
+    HIP_CHECK(hipEventRecord(ev_fork, dev.stream));
+    HIP_CHECK(hipStreamWaitEvent(side.stream, ev_fork, 0));
+  }
+  void join() {
+    HIP_CHECK(hipEventRecord(ev_join, side.stream));
+    HIP_CHECK(hipStreamWaitEvent(dev.stream, ev_join, 0));
+  }
 
   int ny(int f) const { return (f & 1) ? NX : NY; }
   int nx(int f) const { return (f & 1) ? NY : NX; }
@@ -313,8 +329,7 @@ void init_env(ctm_ctx* c) {
 // Half systems of the cut between rows I and I+1 at column step J of frame f
 // (Fig. CTMRG c): N[(h w), (e z)] from the upper quadrants and S[(h v), (e x)]
 // from the lower ones, written as float64 row-major matrices.
-void half_systems(ctm_ctx* c, int f, int I, int J, double* Nout, double* Sout) {
-  Dev& dev = c->dev;
+void half_systems(ctm_ctx* c, Dev& dev, int f, int I, int J, double* Nout, double* Sout) {
   const int64_t chi = c->chi;
   const int m = c->mode;
   // upper-left quadrant: C1 T1 T4 s at (I, J)  ->  UL[c, r, e, z]
@@ -534,9 +549,43 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     if (cnt[p]) NS[p] = DBuf(&dev, (size_t)2 * cnt[p] * kd[p] * mn[p] * 8);
   auto Nptr = [&](int p, int b) { return (double*)NS[p].p + (size_t)b * kd[p] * mn[p]; };
   auto Sptr = [&](int p, int b) { return (double*)NS[p].p + (size_t)(cnt[p] + b) * kd[p] * mn[p]; };
+  const int64_t kk = rec ? r : chi;   // singular vectors kept per row
+  HQR qr[2];
+  DBuf L[2];   // R^T of N (first cnt) and S (next cnt): column-major kd x r
+  DBuf Mb, sv, Uk, Vk, w;
+  {
+    TapePause hold(dev);   // workspaces of the projector block, not recorded buffers
+    Mb = DBuf(&dev, (size_t)a * r * r * 8);
+    sv = DBuf(&dev, (size_t)a * r * 8);
+    Uk = DBuf(&dev, (size_t)a * r * kk * 8);
+    Vk = DBuf(&dev, (size_t)a * r * kk * 8);
+    w = DBuf(&dev, (size_t)a * chi * 8);
+    for (int p = 0; p < 2; ++p)
+      if (cnt[p]) L[p] = DBuf(&dev, (size_t)2 * cnt[p] * kd[p] * r * 8);
+  }
+  // not recorded and both parities present: the odd rows (half systems, QR,
+  // their part of M) run on the second stream; the results are identical.
+  // Every block of the main stream's cache that the second stream writes (NS,
+  // L, Mb) is taken before the fork: a block freed after it may still be in
+  // use by main-stream kernels queued after the fork.
+  const bool two = !rec && c->streams > 1 && cnt[0] && cnt[1];
+  Dev& pdev1 = two ? c->side : dev;
+  // joins the second stream back also when an error leaves this scope early
+  struct SideJoin {
+    ctm_ctx* c = nullptr;
+    ~SideJoin() {
+      if (!c) return;
+      (void)hipEventRecord(c->ev_join, c->side.stream);
+      (void)hipStreamWaitEvent(c->dev.stream, c->ev_join, 0);
+    }
+  } side_guard;
+  if (two) {
+    c->fork();
+    side_guard.c = c;
+  }
   for (int I = 0; I < a; ++I) {
     int p = I & 1, b = I >> 1;
-    half_systems(c, f, I, J, Nptr(p, b), Sptr(p, b));
+    half_systems(c, p ? pdev1 : dev, f, I, J, Nptr(p, b), Sptr(p, b));
   }
   TapePause pause(dev);   // the block below is one recorded operation
   std::vector<ProjRow> rows(rec ? a : 0);
@@ -555,24 +604,23 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
       R.P = P64 + (size_t)I * maxkd * chi;
       R.Q = Q64 + (size_t)I * maxkd * chi;
     }
-  const int64_t kk = rec ? r : chi;   // singular vectors kept per row
-  HQR qr[2];
-  DBuf L[2];   // R^T of N (first cnt) and S (next cnt): column-major kd x r
-  DBuf Mb(&dev, (size_t)a * r * r * 8), sv(&dev, (size_t)a * r * 8), Uk(&dev, (size_t)a * r * kk * 8),
-      Vk(&dev, (size_t)a * r * kk * 8), w(&dev, (size_t)a * chi * 8);
   for (int p = 0; p < 2; ++p) {
     if (!cnt[p]) continue;
+    Dev& pd = p ? pdev1 : dev;
     const int64_t sz = kd[p] * mn[p];
     qr[p].A = (double*)NS[p].p;
     qr[p].m = mn[p]; qr[p].n = kd[p]; qr[p].rs = kd[p]; qr[p].cs = 1; qr[p].stride = sz; qr[p].batch = 2 * cnt[p];
-    hqr_factor(dev, qr[p]);
-    L[p] = DBuf(&dev, (size_t)2 * cnt[p] * kd[p] * r * 8);
+    hqr_factor(pd, qr[p]);
     HIP_CHECK(qrk::launch_extract_rt((const double*)NS[p].p, kd[p], 1, sz, kd[p], r, (double*)L[p].p, kd[p] * r,
-                                     2 * cnt[p], dev.stream));
+                                     2 * cnt[p], pd.stream));
     TRef Mv{(double*)Mb.p + (size_t)p * r * r, T_F64, {cnt[p], r, r}, {2 * r * r, 1, r}, "bij"};
     TRef Lnv{L[p].p, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "bai"};
     TRef Lsv{(double*)L[p].p + (size_t)cnt[p] * kd[p] * r, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "baj"};
-    contract(dev, m, Mv, Lnv, Lsv);
+    contract(pd, m, Mv, Lnv, Lsv);
+  }
+  if (two) {
+    side_guard.c = nullptr;
+    c->join();
   }
   // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
   jacobi_svd(c, (double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
@@ -1145,6 +1193,11 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int 
     c->mode = precision == CTM_BF16 ? ctmk::MODE_BF16 : (precision == CTM_FP32 ? ctmk::MODE_F32 : ctmk::MODE_F64);
     if (rocblas_create_handle(&c->blas) != rocblas_status_success) throw Error(CTM_EHIP, "rocblas_create_handle failed");
     RB_CHECK(rocblas_set_stream(c->blas, c->dev.stream));
+    hipStream_t side = nullptr;
+    HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    c->side.stream = side;
+    HIP_CHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     c->flag = DBuf(&c->dev, 64);
     c->dscal = DBuf(&c->dev, 64);
     HIP_CHECK(hipMemsetAsync(c->flag.p, 0, 64, c->dev.stream));
@@ -1274,6 +1327,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   if (k == "svd_cutoff" && value >= 0) c->cutoff = value;
   else if (k == "lorentz_eta" && value >= 0) c->eta = value;
   else if (k == "check_finite") c->check_finite = value != 0;
+  else if (k == "streams" && (value == 1 || value == 2)) c->streams = (int)value;
   else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }
   return CTM_OK;
 }
@@ -1317,6 +1371,15 @@ void ctm_free(ctm_ctx* c) {
   c->tape.clear();
   c->dev.release();
   (void)hipStreamSynchronize(c->dev.stream);
+  if (c->side.stream) {
+    (void)hipStreamSynchronize(c->side.stream);
+    c->side.release();
+    (void)hipStreamSynchronize(c->side.stream);
+    (void)hipStreamDestroy(c->side.stream);
+    c->side.stream = nullptr;
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;
 }

@@ -888,22 +888,6 @@ constexpr int BJ_GK = 8;            // Gram k-steps (4 rows each) in flight per 
 constexpr int BJ_TPW = 4;           // tiles per wave held in registers across the inner Jacobi
 static_assert(BJ_C == 16, "the pair is one 16-wide MFMA tile");
 
-// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
-// each (about one unit in the last place, against the ten-odd
-// dependent instructions of the correctly rounded division): the rotation
-// angle of a Jacobi step need not be correctly rounded, only (c, s) consistent
-// with it, and s = c t keeps c^2 + s^2 = 1 to rounding.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return fma(fma(-x, r, 1.0), r, r);
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(0.5 * fma(-x * y, y, 1.0), y, y);   // y (1 + (1 - x y^2) / 2)
-  return fma(0.5 * fma(-x * y, y, 1.0), y, y);
-}
-
 // LDS traffic between the lanes of one wave: order the accesses without a
 // workgroup barrier (the other waves are not taking part).
 __device__ __forceinline__ void wave_sync() {
@@ -1022,9 +1006,9 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
         double c = 1.0, sn = 0.0;
         if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 &&
             fabs(g01) > tol * sqrt(g00 * g11)) {
-          const double zeta = (g11 - g00) * rcp_nr(2.0 * g01);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-          c = rsq_nr(fma(t, t, 1.0));
+          const double zeta = (g11 - g00) / (2.0 * g01);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
           sn = c * t;
         }
         const unsigned long long live = __ballot(sn != 0.0);

@@ -236,6 +236,22 @@ def test_two_sweeps_from_sites_start(ctm_mod):
     assert abs(E - Eo) < 1e-8 * max(1.0, abs(Eo))
 
 
+@pytest.mark.parametrize("name,sweeps", [("ssm_d6_chi72", 1), ("heis_d4_chi32", 3)])
+def test_second_stream_gives_identical_sweeps(ctm_mod, name, sweeps):
+    """The odd rows of a column step on the library's second stream (the
+    default) and everything on one stream run the same kernels on the same
+    data, so the environments agree bit for bit (2x2 cell and one-tensor cell)."""
+    cfg = synth.CONFIGS[name]
+    A = synth.config_tensors(cfg, 0)
+    envs = []
+    for streams in (1, 2):
+        g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+        g.set_option("streams", streams)
+        g.sweep(sweeps)
+        envs.append(g.get_env().cpu())
+    assert torch.equal(envs[0], envs[1])
+
+
 def test_neel_and_uniform_product_states(ctm_mod):
     A = synth.product_state_tensors([[1.0, 0.0], [0.0, 1.0]])
     g = ctm_mod.CTM(A, [[0, 1], [1, 0]], 2)
