@@ -455,7 +455,7 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   Dev& dev = c->dev;
   const int64_t stride = r * r;
   DBuf X(&dev, (size_t)batch * stride * 8), W(&dev, (size_t)batch * stride * 8),
-      rot(&dev, (size_t)batch * sizeof(int)), tiny2(&dev, (size_t)batch * 8);
+      rot(&dev, (size_t)batch * sizeof(int)), tiny2(&dev, (size_t)batch * 8), ovl(&dev, (size_t)batch * 8);
   HQR qm;
   qm.A = A; qm.m = r; qm.n = r; qm.rs = 1; qm.cs = r; qm.stride = stride; qm.batch = batch;
   hqr_factor(dev, qm);
@@ -463,6 +463,11 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   HIP_CHECK(ctmk::launch_identity((double*)W.p, r, stride, batch, dev.stream));
   HIP_CHECK(ctmk::launch_frob_tiny((const double*)X.p, stride, stride, batch, 2.2e-16, (double*)tiny2.p, dev.stream));
   const double tol = std::max(1e-15, 2.2e-16 * std::sqrt((double)r));
+  // The method converges quadratically at the end: once the largest |cos| of
+  // a pair rotated in a whole sweep is at most sqrt(tol), what that sweep left
+  // is of order tol, which is what a further sweep (rotations at the rounding
+  // level) and the final sweep without rotations would certify.
+  const double stop = std::sqrt(tol);
   const int64_t rounds = ctmk::bjac_rounds(r);
   // algorithmic flops of one round: per block pair of C columns of length r, the
   // Gram matrix (C(C+1)/2 dot products) and the rotation of the pair's columns
@@ -471,21 +476,28 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   const double pairs = (double)(ctmk::bjac_rounds(r) + 1) / 2.0 * batch;
   const double bj_flops = pairs * ((Cw * (Cw + 1) / 2.0) * 2.0 * r + 2.0 * (2.0 * r * Cw * Cw));
   std::vector<int> h(batch);
+  std::vector<double> ho(batch);
   int sweep = 0;
   for (sweep = 1; sweep <= c->jacobi_max_sweeps; ++sweep) {
     HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, batch, dev.stream));
+    fill(dev, view(ovl.p, T_F64, {(int64_t)batch}, "b"), 0.0);
     for (int64_t t = 0; t < rounds; ++t) {
       if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
       HIP_CHECK(ctmk::launch_bjac_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
-                                        (const double*)tiny2.p, 1, (int*)rot.p, dev.stream));
+                                        (const double*)tiny2.p, 1, (int*)rot.p, (double*)ovl.p, dev.stream));
       if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
       g_counters.count(FAM_JACOBI, bj_flops);
     }
     HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, batch * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
+    HIP_CHECK(hipMemcpyAsync(ho.data(), ovl.p, batch * sizeof(double), hipMemcpyDeviceToHost, dev.stream));
     HIP_CHECK(hipStreamSynchronize(dev.stream));
     bool any = false;
-    for (int b = 0; b < batch; ++b) any |= h[b] != 0;
-    if (!any) break;
+    double big = 0.0;
+    for (int b = 0; b < batch; ++b) {
+      any |= h[b] != 0;
+      big = std::max(big, ho[b]);
+    }
+    if (!any || big <= stop) break;
   }
   if (sweep > c->jacobi_max_sweeps) throw Error(CTM_ESOLVER, "Jacobi SVD did not converge");
   // normalised columns of X W are the right vectors of A; the columns of W, times Q, the left ones

@@ -80,7 +80,7 @@ hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int
                                 double* sv, double* U, double* Vk, hipStream_t s);
 
 hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
-                             const double* tiny2, int inner, int* rot, hipStream_t s);
+                             const double* tiny2, int inner, int* rot, double* ovl_max, hipStream_t s);
 int64_t bjac_rounds(int64_t n);
 int bjac_pair_columns();
 

@@ -877,7 +877,9 @@ hipError_t launch_sub_sinv(const double* A, const double* B, int64_t rows, int64
 //    pair's columns of A and V in flight;
 //  * if any rotation was applied, X <- X R and V_pair <- V_pair R, a 16 x C
 //    tile times the C x C matrix R per MFMA chain.
-// The number of rotations is added to rot[b].  The pair threshold is the one
+// The number of rotations is added to rot[b], and the largest |x_p.x_q| /
+// (|x_p||x_q|) of a rotated pair is folded into ovl_max[b] (a float64 stored
+// by atomic maximum on its bit pattern).  The pair threshold is the one
 // of the scalar method, evaluated on dot products of the current columns, so
 // a round with no rotation anywhere certifies the same orthogonality.
 constexpr int BJ_BW = 8;            // columns per block
@@ -898,7 +900,7 @@ __device__ __forceinline__ void wave_sync() {
 
 __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
                                                            int64_t stride, int round, double tol, const double* tiny2,
-                                                           int inner, int* rot) {
+                                                           int inner, int* rot, unsigned long long* ovl_max) {
   constexpr int GS = BJ_C + 1;                  // padded row stride of G and R (column accesses spread over banks)
   __shared__ double part[BJ_NW][BJ_C * BJ_C];   // per-wave Gram partials
   __shared__ double G[BJ_C * GS];
@@ -989,6 +991,7 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     const double t2 = tiny2[b];
     const int pj = lane >> 3, pk = lane & 7;
     int nrot = 0;
+    double ovl = 0.0;   // largest |cos| between two columns this lane rotated
     for (int sw = 0; sw < inner; ++sw) {
       int sweep_rot = 0;
 #pragma unroll 1
@@ -1004,8 +1007,9 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
         const double g00 = G[p * GS + p2], g01 = G[p * GS + q2], g10 = G[q * GS + p2], g11 = G[q * GS + q2];
         const double r00 = R[p * GS + p2], r01 = R[p * GS + q2], r10 = R[q * GS + p2], r11 = R[q * GS + q2];
         double c = 1.0, sn = 0.0;
-        if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 &&
-            fabs(g01) > tol * sqrt(g00 * g11)) {
+        const double sq = sqrt(g00 * g11);
+        if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 && fabs(g01) > tol * sq) {
+          ovl = fmax(ovl, fabs(g01) / sq);
           const double zeta = (g11 - g00) / (2.0 * g01);
           const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -1033,9 +1037,13 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
       nrot += sweep_rot;
       if (sweep_rot == 0) break;
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) ovl = fmax(ovl, __shfl_xor(ovl, o, 64));
     if (lane == 0) {
       nrot_s = nrot;
       if (nrot) atomicAdd(rot + b, nrot);
+      // non-negative doubles order as their bit patterns
+      if (ovl > 0.0) atomicMax(ovl_max + b, (unsigned long long)__double_as_longlong(ovl));
     }
   }
   __syncthreads();
@@ -1074,11 +1082,12 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
 }
 
 hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
-                             const double* tiny2, int inner, int* rot, hipStream_t s) {
+                             const double* tiny2, int inner, int* rot, double* ovl_max, hipStream_t s) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
   const int64_t np = nblk + (nblk & 1);
   dim3 grid((unsigned)(np / 2), (unsigned)batch);
-  bjac_round_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, round, tol, tiny2, inner, rot);
+  bjac_round_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, round, tol, tiny2, inner, rot,
+                                           (unsigned long long*)ovl_max);
   return hipGetLastError();
 }
 
