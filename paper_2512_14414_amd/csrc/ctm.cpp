@@ -329,6 +329,27 @@ void init_env(ctm_ctx* c) {
 // Half systems of the cut between rows I and I+1 at column step J of frame f
 // (Fig. CTMRG c): N[(h w), (e z)] from the upper quadrants and S[(h v), (e x)]
 // from the lower ones, written as float64 row-major matrices.
+// Work queued between construction (with ``two``) and join() may go to the
+// second stream; the main stream waits for it at join(), or when the scope is
+// left early by an error.
+struct SideScope {
+  ctm_ctx* c;
+  bool on;
+  SideScope(ctm_ctx* cc, bool two) : c(cc), on(two) {
+    if (on) c->fork();
+  }
+  void join() {
+    if (!on) return;
+    on = false;
+    c->join();
+  }
+  ~SideScope() {
+    if (!on) return;
+    (void)hipEventRecord(c->ev_join, c->side.stream);
+    (void)hipStreamWaitEvent(c->dev.stream, c->ev_join, 0);
+  }
+};
+
 void half_systems(ctm_ctx* c, Dev& dev, int f, int I, int J, double* Nout, double* Sout) {
   const int64_t chi = c->chi;
   const int m = c->mode;
@@ -582,19 +603,7 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
   // use by main-stream kernels queued after the fork.
   const bool two = !rec && c->streams > 1 && cnt[0] && cnt[1];
   Dev& pdev1 = two ? c->side : dev;
-  // joins the second stream back also when an error leaves this scope early
-  struct SideJoin {
-    ctm_ctx* c = nullptr;
-    ~SideJoin() {
-      if (!c) return;
-      (void)hipEventRecord(c->ev_join, c->side.stream);
-      (void)hipStreamWaitEvent(c->dev.stream, c->ev_join, 0);
-    }
-  } side_guard;
-  if (two) {
-    c->fork();
-    side_guard.c = c;
-  }
+  SideScope side_scope(c, two);
   for (int I = 0; I < a; ++I) {
     int p = I & 1, b = I >> 1;
     half_systems(c, p ? pdev1 : dev, f, I, J, Nptr(p, b), Sptr(p, b));
@@ -630,10 +639,7 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     TRef Lsv{(double*)L[p].p + (size_t)cnt[p] * kd[p] * r, T_F64, {cnt[p], kd[p], r}, {kd[p] * r, 1, kd[p]}, "baj"};
     contract(pd, m, Mv, Lnv, Lsv);
   }
-  if (two) {
-    side_guard.c = nullptr;
-    c->join();
-  }
+  side_scope.join();
   // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
   jacobi_svd(c, (double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
   HIP_CHECK(ctmk::launch_svd_weights((const double*)sv.p, r, r, (double*)w.p, chi, c->cutoff, a, dev.stream));
@@ -830,29 +836,36 @@ void left_move(ctm_ctx* c, int f) {
       return view(base, c->st, {chi, zd[Ii], chi}, lab);
     };
     std::vector<TRef> outs;
+    // rows are independent here: when not recorded, the odd ones go to the
+    // second stream (their outputs are slots of the environment buffer, their
+    // temporaries from the second stream's cache)
+    const bool two = !c->tape.recording() && c->streams > 1 && a > 1;
+    SideScope side_scope(c, two);
     for (int I = 0; I < a; ++I) {
+      Dev& rd = two && (I & 1) ? c->side : dev;
       TRef s = c->site_t(f, I, J, "yxrz");
       // C1' = [C1 T1] P_{I-1}
-      Tmp X1(&dev, c->st, {chi, s.dim[1], chi}, "axc");
-      contract(dev, m, X1.t, c->slot(f, I, J, 0, "ab"), c->slot(f, I, J, 4, "bxc"));
+      Tmp X1(&rd, c->st, {chi, s.dim[1], chi}, "axc");
+      contract(rd, m, X1.t, c->slot(f, I, J, 0, "ab"), c->slot(f, I, J, 4, "bxc"));
       TRef C1n = c->out_slot(f, I, J + 1, 0, "kc");
-      contract(dev, m, C1n, PQ(P64, Pst, I - 1, "axk"), X1.t);
+      contract(rd, m, C1n, PQ(P64, Pst, I - 1, "axk"), X1.t);
       // T4' = Q_{I-1}^T [T4 s] P_I
-      Tmp G1(&dev, c->st, {chi, chi, s.dim[1], s.dim[2], s.dim[3]}, "eaxrz");
-      contract(dev, m, G1.t, c->slot(f, I, J, 7, "eya"), s);
-      Tmp G2(&dev, c->st, {chi, chi, s.dim[2], s.dim[3]}, "emrz");
-      contract(dev, m, G2.t, PQ(Q64, Qst, I - 1, "axm"), G1.t);
+      Tmp G1(&rd, c->st, {chi, chi, s.dim[1], s.dim[2], s.dim[3]}, "eaxrz");
+      contract(rd, m, G1.t, c->slot(f, I, J, 7, "eya"), s);
+      Tmp G2(&rd, c->st, {chi, chi, s.dim[2], s.dim[3]}, "emrz");
+      contract(rd, m, G2.t, PQ(Q64, Qst, I - 1, "axm"), G1.t);
       TRef T4n = c->out_slot(f, I, J + 1, 7, "krm");
-      contract(dev, m, T4n, PQ(P64, Pst, I, "ezk"), G2.t);
+      contract(rd, m, T4n, PQ(P64, Pst, I, "ezk"), G2.t);
       // C4' = [C4 T3] Q_I
-      Tmp V1(&dev, c->st, {chi, s.dim[3], chi}, "cwa");
-      contract(dev, m, V1.t, c->slot(f, I, J, 6, "cwb"), c->slot(f, I, J, 3, "ba"));
+      Tmp V1(&rd, c->st, {chi, s.dim[3], chi}, "cwa");
+      contract(rd, m, V1.t, c->slot(f, I, J, 6, "cwb"), c->slot(f, I, J, 3, "ba"));
       TRef C4n = c->out_slot(f, I, J + 1, 3, "ck");
-      contract(dev, m, C4n, V1.t, PQ(Q64, Qst, I, "awk"));
+      contract(rd, m, C4n, V1.t, PQ(Q64, Qst, I, "awk"));
       outs.push_back(C1n);
       outs.push_back(T4n);
       outs.push_back(C4n);
     }
+    side_scope.join();
     normalize_all(c, outs);
   }
 }
