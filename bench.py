@@ -48,6 +48,26 @@ KERNEL = {"fp64": "contract_kernel<MODE_F64> (FP64 MFMA)", "fp32": "contract_ker
           "qr_panel": "panel_kernel (Householder QR panel, FP64)"}
 
 
+# what the GPU tests establish against the CPU oracle at each benchmark shape
+ORACLE_CHECK = {
+    "ssm_d6_chi72": "tested: |dE| <= 1e-10 after sweeps from a weakly entangled start (tests/test_gpu_parity.py)",
+    "heis_d4_chi32": "tested: |dE| <= 1e-10, dE/dA to 1e-8 of max|dE/dA| after 40 oracle sweeps (tests/test_gpu_grad.py)",
+    "heis_d9_chi100": "tested: corner spectra after one sweep within the oracle's own spread (energy not run on the CPU "
+                      "at this size)",
+    "heis_d2_chi8": "tested: energy and dE/dA against the oracle (tests/test_gpu_parity.py, tests/test_gpu_grad.py)",
+}
+
+
+def workload_name(name, cfg):
+    if cfg["model"] == "ssm":
+        model = f"Shastry-Sutherland J_dimer={cfg['J_dimer']:g} J_nn={cfg['J_nn']:g}"
+    else:
+        model = f"Heisenberg J={cfg.get('J', 1.0):g}"
+    dist = "uniform[-1,1]" if cfg["dist"] == "uniform" else "N(0,1)"
+    return (f"{name}: {model}, {cfg['Lx']}x{cfg['Ly']} cell of {cfg['n_tensors']} tensors, d={cfg['d']} "
+            f"D={cfg['D']} chi={cfg['chi']}, {dist} seed 0, normalised; step = 1 CTMRG sweep")
+
+
 def traffic_per_launch(fam):
     """HBM bytes per launch of family ``fam`` from the counter runs, or None
     when none were taken or the kernel's source changed since."""
@@ -137,7 +157,7 @@ def main():
     log(f"[bench] profiled sweep {t_prof * 1e3:.1f} ms: {prof}")
 
     # ---- energy (2x2 reduced density matrices of all four plaquettes)
-    E, t_energy = None, None
+    E, t_energy, prof_energy = None, None, None
     if not args.no_energy:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -145,6 +165,12 @@ def main():
         torch.cuda.synchronize()
         t_energy = time.perf_counter() - t0
         log(f"[bench] energy {E:.10f} in {t_energy * 1e3:.1f} ms")
+        # the same evaluation with the families timed: the density-matrix joins
+        # are the largest contractions of the path
+        g.profile_begin()
+        g.energy(H, terms)
+        prof_energy = g.profile_end()
+        log(f"[bench] energy families: {prof_energy}")
 
     # ---- energy + gradient throughput, production precision and FP64, from one shared environment
     egrad = {}
@@ -176,21 +202,23 @@ def main():
     # (noise 0.3 on a product state) after 4 FP64 sweeps from the sites start
     accuracy = None
     if not args.no_egrad and args.precision != "fp64":
+        g.close()
         An = synth.near_product_tensors(len(A), 2, cfg["D"], 5, 0.3)
         h64 = ctm.CTM(An, cfg["pattern"], chi, precision="fp64")
         h64.sweep(4)
         env_np = h64.get_env()
         E64, g64v = h64.energy_grad(args.egrad_sweeps, H, terms)
-        hmx = ctm.CTM(An, cfg["pattern"], chi, precision=args.precision)
-        hmx.set_env(env_np)
-        Emx, gmx = hmx.energy_grad(args.egrad_sweeps, H, terms)
-        accuracy = {"state": "weakly entangled (product + 0.3 noise, seed 5), same shape, 4 FP64 sweeps",
-                    "E_fp64": E64, "dE": abs(Emx - E64), "dgrad_max": (gmx - g64v).abs().max().item(),
-                    "grad_max": g64v.abs().max().item(),
-                    "fp64_vs_oracle": "tested: |dE| <= 1e-10 at this shape (tests/test_gpu_parity.py)"}
-        log(f"[bench] mixed vs fp64: {accuracy}")
         h64.close()
-        hmx.close()
+        accuracy = {"state": "weakly entangled (product + 0.3 noise, seed 5), same shape, 4 FP64 sweeps",
+                    "E_fp64": E64, "grad_max": g64v.abs().max().item(),
+                    "fp64_vs_oracle": ORACLE_CHECK.get(args.config, "not tested at this shape")}
+        for prec in dict.fromkeys((args.precision, "fp32")):
+            hmx = ctm.CTM(An, cfg["pattern"], chi, precision=prec)
+            hmx.set_env(env_np)
+            Emx, gmx = hmx.energy_grad(args.egrad_sweeps, H, terms)
+            hmx.close()
+            accuracy[prec] = {"dE": abs(Emx - E64), "dgrad_max": (gmx - g64v).abs().max().item()}
+        log(f"[bench] mixed vs fp64: {accuracy}")
 
     # ---- roofline of the kernel family with the largest share of the profiled sweep
     fam = max(prof, key=lambda k: prof[k][0])
@@ -243,11 +271,14 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: Shastry-Sutherland J_dimer=1 J_nn=0.8, 2x2 cell of 4 tensors, "
-                               f"d=2 D=6 chi=72, uniform[-1,1] seed 0; step = 1 CTMRG sweep",
+        "config": {"workload": workload_name(args.config, cfg),
                    "precision": args.precision, "projectors": "fp64 QR+SVD"},
         "fp64_sweeps_per_s": None if fp64_sweeps_per_s is None else round(fp64_sweeps_per_s, 4),
         "energy_s": None if t_energy is None else round(t_energy, 4),
+        "energy_families": None if prof_energy is None else {
+            k: {"ms": round(v[0], 3), "tflops": round(v[1] / (v[0] * 1e-3) / 1e12, 3) if v[0] > 0 else 0.0,
+                "frac_of_peak": round(v[1] / (v[0] * 1e-3) / 1e12 / PEAK_TFLOPS[k], 5) if v[0] > 0 else 0.0}
+            for k, v in prof_energy.items() if v[2] > 0},
         "egrad_per_s": None if eg is None else round(1.0 / eg, 4),
         "egrad_per_s_fp64": None if e64 is None else round(1.0 / e64, 4),
         "egrad_sweeps": args.egrad_sweeps,

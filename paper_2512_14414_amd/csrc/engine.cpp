@@ -106,6 +106,37 @@ static size_t size_class(size_t b) {
   return b <= mid ? mid : 2 * p;
 }
 
+// Registry of the live Devs; never destroyed, so that a Dev outliving the
+// library's static objects at process exit still finds it.
+static std::mutex& devs_mu() {
+  static std::mutex* m = new std::mutex();
+  return *m;
+}
+static std::set<Dev*>& devs() {
+  static std::set<Dev*>* s = new std::set<Dev*>();
+  return *s;
+}
+
+Dev::Dev() {
+  std::lock_guard<std::mutex> lock(devs_mu());
+  devs().insert(this);
+}
+
+Dev::~Dev() {
+  release();
+  std::lock_guard<std::mutex> lock(devs_mu());
+  devs().erase(this);
+}
+
+// Every cache of the process back to the pool, then wait until the frees are done.
+static void release_all_caches() {
+  {
+    std::lock_guard<std::mutex> lock(devs_mu());
+    for (Dev* d : devs()) d->release();
+  }
+  (void)hipDeviceSynchronize();
+}
+
 void* Dev::take(size_t bytes) {
   if (!pool_ready) {
     retain_pool_memory();
@@ -123,8 +154,7 @@ void* Dev::take(size_t bytes) {
   hipError_t e = hipMallocAsync(&p, sz, stream);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
-    release();
-    (void)hipStreamSynchronize(stream);
+    release_all_caches();
     e = hipMallocAsync(&p, sz, stream);
   }
   if (e != hipSuccess) throw Error(e == hipErrorOutOfMemory ? -2 : -3, std::string("hipMallocAsync: ") + hipGetErrorString(e));

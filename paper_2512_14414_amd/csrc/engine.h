@@ -61,17 +61,19 @@ struct Tape;
 // stream-ordered allocator costs several microseconds of host time per call,
 // and a sweep allocates thousands of workspaces.)  The cache goes back to the
 // device pool when the Dev is destroyed, and before a request that the pool
-// cannot otherwise satisfy.
+// cannot otherwise satisfy: then the caches of every live Dev of the process
+// are returned (the contexts of a process are used from one thread at a time)
+// and the device is synchronised before the request is retried.
 struct Dev {
   hipStream_t stream = nullptr;
   Tape* tape = nullptr;
   bool pool_ready = false;
   std::unordered_map<void*, size_t> live;                    // block -> size class
   std::unordered_map<size_t, std::vector<void*>> cached;     // size class -> free blocks
-  Dev() = default;
+  Dev();
   Dev(const Dev&) = delete;
   Dev& operator=(const Dev&) = delete;
-  ~Dev() { release(); }
+  ~Dev();
   void* alloc(size_t bytes);   // take(), registered with a recording tape
   void free(void* p);          // give(), deferred while a tape records
   void* take(size_t bytes);    // a cached block of the size class, else a new one
