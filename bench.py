@@ -38,8 +38,8 @@ BOUND = {"fp64": "mfma", "fp32": "mfma", "bf16": "mfma", "jacobi": "alu", "qr_pa
 # (bench.py --copy-probe 256: FETCH_SIZE reads half of the bytes copied, so x2;
 # WRITE_SIZE reads them exactly, x1).  Valid for the kernel source it was taken
 # on (hash of the kernel's text), else reported as null.
-TRAFFIC = {"jacobi": {"fetch_kib": 5902.6, "fetch_scale": 2.0, "write_kib": 3986.0, "write_scale": 1.0,
-                      "source_sha256": "1db827e3c7bbded1bdc34ef1b3cb68015e52a6fa6286c418dcd24967c5457624",
+TRAFFIC = {"jacobi": {"fetch_kib": 5912.0, "fetch_scale": 2.0, "write_kib": 4634.4, "write_scale": 1.0,
+                      "source_sha256": "444bb97d22d40f4c675e7ed6dab8c2764e7092fbc66fffdce57e2a3997ee3b35",
                       "source": ("paper_2512_14414_amd/csrc/kernels.hip", "constexpr int BJ_BW = 8;",
                                  "hipError_t launch_bjac_round(")}}
 KERNEL = {"fp64": "contract_kernel<MODE_F64> (FP64 MFMA)", "fp32": "contract_kernel<MODE_F32> (FP32 MFMA)",
