@@ -145,7 +145,10 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *   "streams"     2 (default) to run the odd rows of a column step (half systems,
  *                 their QR) on a second stream created by the library, joined
  *                 back before the SVD, in sweeps that are not differentiated;
- *                 1 for one stream.  Both give identical results. */
+ *                 1 for one stream.  Both give identical results.
+ *   "rowmajor_bf16" 1 (default) to run large BF16-mode products of plain
+ *                 row-major operands on the dedicated 128 x 128-tile kernel, 0
+ *                 for the general contraction kernel; a process-wide switch. */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
 /* Live timing of the library's main kernel families.  Between

@@ -1353,6 +1353,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "lorentz_eta" && value >= 0) c->eta = value;
   else if (k == "check_finite") c->check_finite = value != 0;
   else if (k == "streams" && (value == 1 || value == 2)) c->streams = (int)value;
+  else if (k == "rowmajor_bf16") ctmk::g_rowmajor_path = value != 0;
   else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }
   return CTM_OK;
 }

@@ -284,8 +284,145 @@ static hipError_t launch_mode(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Large BF16 products of plain row-major operands: C[m][n] = alpha
+// sum_k A[m][k] B[k][n] (+ C), A, B, C float32 in memory, products of bf16
+// (rounded to nearest even) accumulated in float32.  A 128 x 128 tile per
+// workgroup, 4 waves of 64 x 64 (4 x 4 tiles of v_mfma_f32_16x16x16bf16_1k),
+// BK = 32.  The operands are read as float4, rounded, and kept in LDS as
+// As[m][k] and Bs[n][k] (k contiguous, rows padded to 40 elements), so that a
+// lane's MFMA fragment (four consecutive k) is one 8-byte read.  Tiles go to
+// the XCDs in contiguous ranges (consecutive workgroups are dealt round-robin
+// to the eight XCDs) and, within a range, in groups of eight row tiles, so
+// that neighbouring workgroups of one XCD share operand tiles in its L2.
+constexpr int GB_BM = 128, GB_BN = 128, GB_BK = 32, GB_LD = GB_BK + 8;
+
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
+  uint2 r;
+  r.x = (uint32_t)f32_to_bf16_rne(a) | ((uint32_t)f32_to_bf16_rne(b) << 16);
+  r.y = (uint32_t)f32_to_bf16_rne(c) | ((uint32_t)f32_to_bf16_rne(d) << 16);
+  return r;
+}
+
+__global__ __launch_bounds__(256) void gemm_bf16_rowmajor_kernel(GemmArgs g) {
+  __shared__ __align__(16) unsigned short As[GB_BM * GB_LD];
+  __shared__ __align__(16) unsigned short Bs[GB_BN * GB_LD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+  const int64_t tiles_m = (g.M + GB_BM - 1) / GB_BM, tiles_n = (g.N + GB_BN - 1) / GB_BN;
+  const int64_t T = tiles_m * tiles_n;
+  const int64_t per_xcd = (T + 7) / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= T) return;
+  constexpr int64_t GROUP = 8;
+  const int64_t in_group = GROUP * tiles_n;
+  const int64_t first_m = (t / in_group) * GROUP;
+  const int64_t gsize = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
+  const int64_t tm = first_m + (t % in_group) % gsize, tn = (t % in_group) / gsize;
+  const int64_t m0 = tm * GB_BM, n0 = tn * GB_BN;
+  const int64_t bz = blockIdx.y;
+  const float* A = (const float*)g.A + bz * g.a_b_i;
+  const float* B = (const float*)g.B + bz * g.b_b_i;
+  float* C = (float*)g.C + bz * g.c_b_i;
+  const int64_t lda = g.a_m_i, ldb = g.b_k_i, ldc = g.c_m_i;
+
+  // A: thread -> rows tid/8 + 32 i (i < 4), columns k0 + 4 (tid % 8) .. +3
+  // B: thread -> rows k0 + 4 (tid / 32) + j (j < 4), columns n0 + 4 (tid % 32) .. +3
+  const int a_r = tid >> 3, a_k = (tid & 7) * 4;
+  const int b_n = (tid & 31) * 4, b_k = (tid >> 5) * 4;
+  float4 ra[4], rb[4];
+  // out-of-range elements read the operand's first element (always valid) and are zeroed after the load
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t m = m0 + a_r + 32 * i, k = k0 + a_k;
+      const bool ok = m < g.M && k < g.K;
+      const float4 v = *(const float4*)(A + (ok ? m * lda + k : 0));
+      ra[i] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t k = k0 + b_k + j, n = n0 + b_n;
+      const bool ok = k < g.K && n < g.N;
+      const float4 v = *(const float4*)(B + (ok ? k * ldb + n : 0));
+      rb[j] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      *(uint2*)&As[(a_r + 32 * i) * GB_LD + a_k] = pack_bf16x4(ra[i].x, ra[i].y, ra[i].z, ra[i].w);
+    // the 4 x 4 block (k rows, n columns) goes in transposed: row n of Bs holds k contiguous
+    *(uint2*)&Bs[(b_n + 0) * GB_LD + b_k] = pack_bf16x4(rb[0].x, rb[1].x, rb[2].x, rb[3].x);
+    *(uint2*)&Bs[(b_n + 1) * GB_LD + b_k] = pack_bf16x4(rb[0].y, rb[1].y, rb[2].y, rb[3].y);
+    *(uint2*)&Bs[(b_n + 2) * GB_LD + b_k] = pack_bf16x4(rb[0].z, rb[1].z, rb[2].z, rb[3].z);
+    *(uint2*)&Bs[(b_n + 3) * GB_LD + b_k] = pack_bf16x4(rb[0].w, rb[1].w, rb[2].w, rb[3].w);
+  };
+
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+  load(0);
+  for (int64_t k0 = 0; k0 < g.K; k0 += GB_BK) {
+    stash();
+    __syncthreads();
+    if (k0 + GB_BK < g.K) load(k0 + GB_BK);   // next tile in flight while the matrix cores work
+#pragma unroll
+    for (int ks = 0; ks < GB_BK; ks += 16) {
+      s4_t af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = *(const s4_t*)&As[(wm + 16 * i + lr) * GB_LD + ks + 4 * lq];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = *(const s4_t*)&Bs[(wn + 16 * j + lr) * GB_LD + ks + 4 * lq];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout: register e of lane (lr, lq) is row 4 lq + e, column lr of the 16 x 16 tile
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t n = n0 + wn + 16 * j + lr;
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t m = m0 + wm + 16 * i + 4 * lq + e;
+        if (m >= g.M) continue;
+        float v = (float)(g.alpha * (double)acc[i][j][e]);
+        if (g.beta) v += C[m * ldc + n];
+        C[m * ldc + n] = v;
+      }
+    }
+}
+
+// The products that take the row-major path: one level per index group, unit
+// stride along k in A and along n in B and C, 16-byte aligned rows, no column
+// scale or K split, and large enough to fill the chip.
+static bool rowmajor_bf16_ok(const GemmArgs& g) {
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  return g.m_in == g.M && g.n_in == g.N && g.k_in == g.K && (g.batch == 1 || g.b_in == g.batch) &&
+         g.a_k_i == 1 && g.b_n_i == 1 && g.c_n_i == 1 && !g.colscale && g.ksplit <= 1 &&
+         g.a_m_i % 4 == 0 && g.b_k_i % 4 == 0 && g.a_b_i % 4 == 0 && g.b_b_i % 4 == 0 && g.K % 4 == 0 &&
+         g.N % 4 == 0 && al16(g.A) && al16(g.B) && g.M >= 512 && g.N >= 512 && g.K >= 128;
+}
+
+bool g_rowmajor_path = true;
+
 hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (mode == MODE_BF16 && g_rowmajor_path && rowmajor_bf16_ok(g)) {
+    const int64_t T = ((g.M + GB_BM - 1) / GB_BM) * ((g.N + GB_BN - 1) / GB_BN);
+    const int64_t blocks = 8 * ((T + 7) / 8);
+    if (blocks > 2147483647LL || g.batch > 65535) return hipErrorInvalidValue;
+    gemm_bf16_rowmajor_kernel<<<dim3((unsigned)blocks, (unsigned)g.batch), 256, 0, s>>>(g);
+    return hipGetLastError();
+  }
   if (mode == MODE_F64) return launch_mode<MODE_F64>(g, s);
   if (mode == MODE_F32) return launch_mode<MODE_F32>(g, s);
   return launch_mode<MODE_BF16>(g, s);
