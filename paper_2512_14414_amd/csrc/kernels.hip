@@ -25,13 +25,6 @@ __device__ __forceinline__ int64_t split_off(int64_t i, int64_t inner, int64_t s
   return o * so + (i - o * inner) * si;
 }
 
-__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
 constexpr int BM = 64, NT = 256;
 
 template <int MODE> struct Cfg;
@@ -42,7 +35,9 @@ template <> struct Cfg<MODE_BF16> { typedef float T; typedef unsigned short L; s
 template <int MODE> __device__ __forceinline__ typename Cfg<MODE>::L to_lds(typename Cfg<MODE>::T v);
 template <> __device__ __forceinline__ double to_lds<MODE_F64>(double v) { return v; }
 template <> __device__ __forceinline__ float to_lds<MODE_F32>(float v) { return v; }
-template <> __device__ __forceinline__ unsigned short to_lds<MODE_BF16>(float v) { return f32_to_bf16_rne(v); }
+template <> __device__ __forceinline__ unsigned short to_lds<MODE_BF16>(float v) {
+  return __builtin_bit_cast(unsigned short, (__bf16)v);   // nearest even (v_cvt_pk_bf16_f32)
+}
 
 // One workgroup computes a 64 x BN tile of C (BN = 32 WN) for one batch
 // entry; the four waves each own a 32 x 16WN quarter made of 2 x WN blocks of
@@ -288,7 +283,7 @@ static hipError_t launch_mode(const GemmArgs& g, hipStream_t s) {
 // Large BF16 products of plain row-major operands: C[m][n] = alpha
 // sum_k A[m][k] B[k][n] (+ C), A, B, C float32 in memory, products of bf16
 // (rounded to nearest even) accumulated in float32.  A 128 x 128 tile per
-// workgroup, 4 waves of 64 x 64 (4 x 4 tiles of v_mfma_f32_16x16x16bf16_1k),
+// workgroup, 4 waves of 64 x 64 (4 x 4 tiles of v_mfma_f32_16x16x32_bf16),
 // BK = 32.  The operands are read as float4, rounded, and kept in LDS as
 // As[m][k] and Bs[n][k] (k contiguous, rows padded to 40 elements), so that a
 // lane's MFMA fragment (four consecutive k) is one 8-byte read.  Tiles go to
@@ -297,10 +292,13 @@ static hipError_t launch_mode(const GemmArgs& g, hipStream_t s) {
 // that neighbouring workgroups of one XCD share operand tiles in its L2.
 constexpr int GB_BM = 128, GB_BN = 128, GB_BK = 32, GB_LD = GB_BK + 8;
 
+// four floats rounded to bf16 (nearest even, v_cvt_pk_bf16_f32) and packed
 __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
+  typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+  const bf2_t lo = {(__bf16)a, (__bf16)b}, hi = {(__bf16)c, (__bf16)d};
   uint2 r;
-  r.x = (uint32_t)f32_to_bf16_rne(a) | ((uint32_t)f32_to_bf16_rne(b) << 16);
-  r.y = (uint32_t)f32_to_bf16_rne(c) | ((uint32_t)f32_to_bf16_rne(d) << 16);
+  r.x = __builtin_bit_cast(uint32_t, lo);
+  r.y = __builtin_bit_cast(uint32_t, hi);
   return r;
 }
 
@@ -369,17 +367,19 @@ __global__ __launch_bounds__(256) void gemm_bf16_rowmajor_kernel(GemmArgs g) {
     stash();
     __syncthreads();
     if (k0 + GB_BK < g.K) load(k0 + GB_BK);   // next tile in flight while the matrix cores work
+    {
+      // v_mfma_f32_16x16x32_bf16: lane (lr, lq) supplies row lr and k = 8 lq .. 8 lq + 7 of the
+      // A fragment, column lr and the same k of the B fragment (one 16-byte LDS read each)
+      typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+      bf8_t af[4], bf[4];
 #pragma unroll
-    for (int ks = 0; ks < GB_BK; ks += 16) {
-      s4_t af[4], bf[4];
+      for (int i = 0; i < 4; ++i) af[i] = *(const bf8_t*)&As[(wm + 16 * i + lr) * GB_LD + 8 * lq];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = *(const s4_t*)&As[(wm + 16 * i + lr) * GB_LD + ks + 4 * lq];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bf[j] = *(const s4_t*)&Bs[(wn + 16 * j + lr) * GB_LD + ks + 4 * lq];
+      for (int j = 0; j < 4; ++j) bf[j] = *(const bf8_t*)&Bs[(wn + 16 * j + lr) * GB_LD + 8 * lq];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
