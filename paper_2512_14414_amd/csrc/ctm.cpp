@@ -1132,31 +1132,47 @@ void sites_adjoint_to_A(ctm_ctx* c, const void* site_adj, double* grad) {
 // pass recomputes one sweep at a time under the tape and propagates the
 // environment adjoint back through it, so the tape never holds more than one
 // sweep.  The environment is left at the result of the n sweeps.
+// E after n sweeps from the current environment and dE/dA.  The last sweep
+// and the energy are recorded on one tape during the forward pass (one
+// sweep's tape takes a few GB at D = 6, chi = 72); the sweeps before it are run
+// without a tape from snapshots of their starting environments and recomputed
+// under the tape in reverse order (checkpointing at sweep granularity).
 double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, const ctm_term* terms, double* grad) {
   Dev& dev = c->dev;
   const size_t eb = (size_t)c->env_elems * type_size(c->st);
+  const size_t es = type_size(c->st);
   std::vector<DBuf> snap;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i + 1 < n; ++i) {
     snap.emplace_back(&dev, eb);
     HIP_CHECK(hipMemcpyAsync(snap.back().p, c->env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
     for (int f : MOVE_FRAMES) left_move(c, f);
   }
-  HIP_CHECK(ctmk::launch_nonfinite(c->st, c->env.p, c->env_elems, (int*)c->flag.p, dev.stream));
   DBuf final_env(&dev, eb);
-  HIP_CHECK(hipMemcpyAsync(final_env.p, c->env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
   DBuf site_adj(&dev, c->site_buf.bytes), env_adj(&dev, eb), env_adj2(&dev, eb);
   HIP_CHECK(hipMemsetAsync(site_adj.p, 0, site_adj.bytes, dev.stream));
   HIP_CHECK(hipMemsetAsync(env_adj.p, 0, eb, dev.stream));
-  // energy at the final environment
+  // the last sweep and the energy at its environment, on one tape
   c->tape.begin(&dev);
   c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
   c->tape.reg(c->env.p, eb, env_adj.p);
+  if (n > 0)
+    for (int f : MOVE_FRAMES) left_move(c, f);
   double E = energy_impl(c, H_bond, n_terms, terms);
-  c->tape.backward();
+  {
+    // the environment after the sweep sits in the fresh buffers of the slots
+    TapePause pause(dev);
+    for (size_t idx = 0; idx < c->slot_ptr.size(); ++idx) {
+      const int64_t ne = c->slot_elems(idx);
+      copy_into(dev, view((char*)final_env.p + c->slot_off[idx] * es, c->st, {ne}, "q"),
+                view(c->slot_ptr[idx], c->st, {ne}, "q"));
+    }
+    HIP_CHECK(ctmk::launch_nonfinite(c->st, final_env.p, c->env_elems, (int*)c->flag.p, dev.stream));
+  }
+  c->tape.backward();   // env_adj: dE / d(environment before the last sweep)
   c->tape.clear();
-  // sweeps in reverse order
-  const size_t es = type_size(c->st);
-  for (int i = n - 1; i >= 0; --i) {
+  c->reset_slot_ptrs();
+  // earlier sweeps in reverse order, recomputed from their snapshots
+  for (int i = n - 2; i >= 0; --i) {
     HIP_CHECK(hipMemcpyAsync(c->env.p, snap[i].p, eb, hipMemcpyDeviceToDevice, dev.stream));
     c->reset_slot_ptrs();
     HIP_CHECK(hipMemsetAsync(env_adj2.p, 0, eb, dev.stream));
