@@ -302,9 +302,18 @@ __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
   return r;
 }
 
+// A_KC: A has unit stride along k (row-major A[m][k]), else along m (A[k][m]
+// column by column); B_NC: B has unit stride along n (row-major B[k][n]),
+// else along k.  The tile loads follow the unit stride (float4), and blocks
+// read along the other index are transposed in registers on the way to LDS.
+template <bool A_KC, bool B_NC>
 __global__ __launch_bounds__(256) void gemm_bf16_rowmajor_kernel(GemmArgs g) {
   __shared__ __align__(16) unsigned short As[GB_BM * GB_LD];
   __shared__ __align__(16) unsigned short Bs[GB_BN * GB_LD];
+  // offsets of the tile's lines (rows of A or C, columns of B or C; an index
+  // split in two levels is resolved here once), NONE past the edge
+  __shared__ int64_t a_line[GB_BM], b_line[GB_BN], c_row[GB_BM], c_col[GB_BN];
+  constexpr int64_t NONE = INT64_MIN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
   const int64_t tiles_m = (g.M + GB_BM - 1) / GB_BM, tiles_n = (g.N + GB_BN - 1) / GB_BN;
   const int64_t T = tiles_m * tiles_n;
@@ -321,39 +330,81 @@ __global__ __launch_bounds__(256) void gemm_bf16_rowmajor_kernel(GemmArgs g) {
   const float* A = (const float*)g.A + bz * g.a_b_i;
   const float* B = (const float*)g.B + bz * g.b_b_i;
   float* C = (float*)g.C + bz * g.c_b_i;
-  const int64_t lda = g.a_m_i, ldb = g.b_k_i, ldc = g.c_m_i;
+  const int64_t lda = A_KC ? 0 : g.a_k_i, ldb = B_NC ? g.b_k_i : 0;
+  if (tid < GB_BM) {
+    const int64_t m = m0 + tid;
+    a_line[tid] = m < g.M ? split_off(m, g.m_in, g.a_m_o, g.a_m_i) : NONE;
+    c_row[tid] = m < g.M ? split_off(m, g.m_in, g.c_m_o, g.c_m_i) : NONE;
+  } else {
+    const int j = tid - GB_BM;
+    const int64_t n = n0 + j;
+    b_line[j] = n < g.N ? split_off(n, g.n_in, g.b_n_o, g.b_n_i) : NONE;
+    c_col[j] = n < g.N ? split_off(n, g.n_in, g.c_n_o, g.c_n_i) : NONE;
+  }
+  __syncthreads();
 
-  // A: thread -> rows tid/8 + 32 i (i < 4), columns k0 + 4 (tid % 8) .. +3
-  // B: thread -> rows k0 + 4 (tid / 32) + j (j < 4), columns n0 + 4 (tid % 32) .. +3
-  const int a_r = tid >> 3, a_k = (tid & 7) * 4;
-  const int b_n = (tid & 31) * 4, b_k = (tid >> 5) * 4;
+  // along the unit stride: thread -> lines tid/8 + 32 i (i < 4), elements 4 (tid % 8) .. +3 of the 32
+  // across it: thread -> lines 4 (tid % 32) .. +3, elements 4 (tid / 32) + j (j < 4)
+  const int s_r = tid >> 3, s_k = (tid & 7) * 4;
+  const int x_n = (tid & 31) * 4, x_k = (tid >> 5) * 4;
   float4 ra[4], rb[4];
   // out-of-range elements read the operand's first element (always valid) and are zeroed after the load
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t m = m0 + a_r + 32 * i, k = k0 + a_k;
-      const bool ok = m < g.M && k < g.K;
-      const float4 v = *(const float4*)(A + (ok ? m * lda + k : 0));
+      int64_t off;
+      bool ok;
+      if (A_KC) {   // line m of A, k contiguous
+        const int64_t lo = a_line[s_r + 32 * i], k = k0 + s_k;
+        ok = lo != NONE && k < g.K;
+        off = lo + k;
+      } else {      // m contiguous (one level): four rows m .. m + 3 at one k
+        const int64_t k = k0 + x_k + i, m = m0 + x_n;
+        ok = k < g.K && m < g.M;
+        off = k * lda + m;
+      }
+      const float4 v = *(const float4*)(A + (ok ? off : 0));
       ra[i] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int64_t k = k0 + b_k + j, n = n0 + b_n;
-      const bool ok = k < g.K && n < g.N;
-      const float4 v = *(const float4*)(B + (ok ? k * ldb + n : 0));
+      int64_t off;
+      bool ok;
+      if (B_NC) {   // n contiguous within its inner group: four columns n .. n + 3 at one k
+        const int64_t lo = b_line[x_n], k = k0 + x_k + j;
+        ok = lo != NONE && k < g.K;
+        off = k * ldb + lo;
+      } else {      // line n of B, k contiguous
+        const int64_t lo = b_line[s_r + 32 * j], k = k0 + s_k;
+        ok = lo != NONE && k < g.K;
+        off = lo + k;
+      }
+      const float4 v = *(const float4*)(B + (ok ? off : 0));
       rb[j] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
+  // a 4 x 4 block read across the k-contiguous LDS rows goes in transposed
+  auto put_transposed = [](unsigned short* S, int line, int k, const float4* r) {
+    *(uint2*)&S[(line + 0) * GB_LD + k] = pack_bf16x4(r[0].x, r[1].x, r[2].x, r[3].x);
+    *(uint2*)&S[(line + 1) * GB_LD + k] = pack_bf16x4(r[0].y, r[1].y, r[2].y, r[3].y);
+    *(uint2*)&S[(line + 2) * GB_LD + k] = pack_bf16x4(r[0].z, r[1].z, r[2].z, r[3].z);
+    *(uint2*)&S[(line + 3) * GB_LD + k] = pack_bf16x4(r[0].w, r[1].w, r[2].w, r[3].w);
+  };
   auto stash = [&]() {
+    if (A_KC) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      *(uint2*)&As[(a_r + 32 * i) * GB_LD + a_k] = pack_bf16x4(ra[i].x, ra[i].y, ra[i].z, ra[i].w);
-    // the 4 x 4 block (k rows, n columns) goes in transposed: row n of Bs holds k contiguous
-    *(uint2*)&Bs[(b_n + 0) * GB_LD + b_k] = pack_bf16x4(rb[0].x, rb[1].x, rb[2].x, rb[3].x);
-    *(uint2*)&Bs[(b_n + 1) * GB_LD + b_k] = pack_bf16x4(rb[0].y, rb[1].y, rb[2].y, rb[3].y);
-    *(uint2*)&Bs[(b_n + 2) * GB_LD + b_k] = pack_bf16x4(rb[0].z, rb[1].z, rb[2].z, rb[3].z);
-    *(uint2*)&Bs[(b_n + 3) * GB_LD + b_k] = pack_bf16x4(rb[0].w, rb[1].w, rb[2].w, rb[3].w);
+      for (int i = 0; i < 4; ++i)
+        *(uint2*)&As[(s_r + 32 * i) * GB_LD + s_k] = pack_bf16x4(ra[i].x, ra[i].y, ra[i].z, ra[i].w);
+    } else {
+      put_transposed(As, x_n, x_k, ra);
+    }
+    if (B_NC) {
+      put_transposed(Bs, x_n, x_k, rb);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *(uint2*)&Bs[(s_r + 32 * j) * GB_LD + s_k] = pack_bf16x4(rb[j].x, rb[j].y, rb[j].z, rb[j].w);
+    }
   };
 
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -388,39 +439,55 @@ __global__ __launch_bounds__(256) void gemm_bf16_rowmajor_kernel(GemmArgs g) {
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int64_t n = n0 + wn + 16 * j + lr;
-      if (n >= g.N) continue;
+      const int64_t co = c_col[wn + 16 * j + lr];
+      if (co == NONE) continue;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t m = m0 + wm + 16 * i + 4 * lq + e;
-        if (m >= g.M) continue;
+        const int64_t ro = c_row[wm + 16 * i + 4 * lq + e];
+        if (ro == NONE) continue;
         float v = (float)(g.alpha * (double)acc[i][j][e]);
-        if (g.beta) v += C[m * ldc + n];
-        C[m * ldc + n] = v;
+        if (g.beta) v += C[ro + co];
+        C[ro + co] = v;
       }
     }
 }
 
-// The products that take the row-major path: one level per index group, unit
-// stride along k in A and along n in B and C, 16-byte aligned rows, no column
-// scale or K split, and large enough to fill the chip.
-static bool rowmajor_bf16_ok(const GemmArgs& g) {
+// The products that take this path: one level for k (and for m when A has
+// unit stride along m), a unit stride along k or m in A and along n or k in B
+// (an index split in two levels keeps its lines 16-byte aligned), any layout
+// of C, no column scale or K split, and large enough to fill the chip.
+// Returns the variant (0..3: A_KC + 2 B_NC) or -1.
+static int rowmajor_bf16_variant(const GemmArgs& g) {
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-  return g.m_in == g.M && g.n_in == g.N && g.k_in == g.K && (g.batch == 1 || g.b_in == g.batch) &&
-         g.a_k_i == 1 && g.b_n_i == 1 && g.c_n_i == 1 && !g.colscale && g.ksplit <= 1 &&
-         g.a_m_i % 4 == 0 && g.b_k_i % 4 == 0 && g.a_b_i % 4 == 0 && g.b_b_i % 4 == 0 && g.K % 4 == 0 &&
-         g.N % 4 == 0 && al16(g.A) && al16(g.B) && g.M >= 512 && g.N >= 512 && g.K >= 128;
+  // a two-level index keeps 16-byte alignment when both strides are multiples of 4 floats
+  auto lines4 = [](int64_t n_in, int64_t n, int64_t so, int64_t si) { return si % 4 == 0 && (n_in == n || so % 4 == 0); };
+  if (!(g.k_in == g.K && (g.batch == 1 || g.b_in == g.batch) && !g.colscale && g.ksplit <= 1 && g.a_b_i % 4 == 0 &&
+        g.b_b_i % 4 == 0 && al16(g.A) && al16(g.B) && g.M >= 512 && g.N >= 512 && g.K >= 128 && g.K % 4 == 0))
+    return -1;
+  int v = 0;
+  if (g.a_k_i == 1 && lines4(g.m_in, g.M, g.a_m_o, g.a_m_i)) v |= 1;
+  else if (!(g.a_m_i == 1 && g.m_in == g.M && g.a_k_i % 4 == 0 && g.M % 4 == 0)) return -1;
+  if (g.b_n_i == 1 && g.b_k_i % 4 == 0 && g.n_in % 4 == 0 && (g.n_in == g.N || g.b_n_o % 4 == 0) && g.N % 4 == 0) v |= 2;
+  else if (!(g.b_k_i == 1 && lines4(g.n_in, g.N, g.b_n_o, g.b_n_i))) return -1;
+  return v;
 }
 
 bool g_rowmajor_path = true;
 
 hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (mode == MODE_BF16 && g_rowmajor_path && rowmajor_bf16_ok(g)) {
+  const int v = mode == MODE_BF16 && g_rowmajor_path ? rowmajor_bf16_variant(g) : -1;
+  if (v >= 0) {
     const int64_t T = ((g.M + GB_BM - 1) / GB_BM) * ((g.N + GB_BN - 1) / GB_BN);
     const int64_t blocks = 8 * ((T + 7) / 8);
     if (blocks > 2147483647LL || g.batch > 65535) return hipErrorInvalidValue;
-    gemm_bf16_rowmajor_kernel<<<dim3((unsigned)blocks, (unsigned)g.batch), 256, 0, s>>>(g);
+    const dim3 grid((unsigned)blocks, (unsigned)g.batch);
+    switch (v) {
+      case 0: gemm_bf16_rowmajor_kernel<false, false><<<grid, 256, 0, s>>>(g); break;
+      case 1: gemm_bf16_rowmajor_kernel<true, false><<<grid, 256, 0, s>>>(g); break;
+      case 2: gemm_bf16_rowmajor_kernel<false, true><<<grid, 256, 0, s>>>(g); break;
+      default: gemm_bf16_rowmajor_kernel<true, true><<<grid, 256, 0, s>>>(g); break;
+    }
     return hipGetLastError();
   }
   if (mode == MODE_F64) return launch_mode<MODE_F64>(g, s);
