@@ -809,16 +809,17 @@ hipError_t launch_jacobi_round(double* A, double* V, int64_t n, int64_t stride, 
   return hipGetLastError();
 }
 
-// tiny2[b] = (eps * |A_b|_F)^2, one workgroup per matrix
-__global__ __launch_bounds__(256) void frob_tiny_kernel(const double* A, int64_t len, int64_t stride, double eps,
-                                                        double* tiny2) {
-  __shared__ double red[256];
+// tiny2[b] = (eps * |A_b|_F)^2, one workgroup of 1024 threads per matrix
+// (float64 partial sums per thread, then a fixed-order tree)
+__global__ __launch_bounds__(1024) void frob_tiny_kernel(const double* A, int64_t len, int64_t stride, double eps,
+                                                         double* tiny2) {
+  __shared__ double red[1024];
   const double* Ab = A + (int64_t)blockIdx.x * stride;
   double s = 0;
-  for (int64_t i = threadIdx.x; i < len; i += 256) s += Ab[i] * Ab[i];
+  for (int64_t i = threadIdx.x; i < len; i += 1024) s += Ab[i] * Ab[i];
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -827,7 +828,7 @@ __global__ __launch_bounds__(256) void frob_tiny_kernel(const double* A, int64_t
 
 hipError_t launch_frob_tiny(const double* A, int64_t len, int64_t stride, int batch, double eps, double* tiny2,
                             hipStream_t s) {
-  frob_tiny_kernel<<<batch, 256, 0, s>>>(A, len, stride, eps, tiny2);
+  frob_tiny_kernel<<<batch, 1024, 0, s>>>(A, len, stride, eps, tiny2);
   return hipGetLastError();
 }
 
@@ -863,41 +864,52 @@ hipError_t launch_identity(double* V, int64_t n, int64_t stride, int batch, hipS
 // After convergence: s_j = |a_j|; the k largest (k <= kmax) in descending
 // order go to sv[b][k], their left vectors a_j / s_j to U[b] (n x kmax,
 // column-major) and right vectors to Vk[b] (n x kmax); all n sorted values are
-// written to sv (length n per matrix).  One workgroup per matrix; ranks by
-// counting (n <= 4096), ties broken by column index.
-__global__ __launch_bounds__(256) void jacobi_finish_kernel(const double* A, const double* V, int64_t n, int64_t stride,
-                                                            int64_t kmax, double* sv, double* U, double* Vk) {
-  extern __shared__ double nrm[];
+// written to sv (length n per matrix).  One workgroup of 1024 threads per
+// matrix: a wave per column for the norms (rows across the lanes), ranks by
+// counting (n <= 4096), ties broken by column index, then the selected columns
+// copied with the rows across the threads.
+__global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* A, const double* V, int64_t n, int64_t stride,
+                                                             int64_t kmax, double* sv, double* U, double* Vk) {
+  extern __shared__ double nrm[];             // n norms, then n column indices by rank (as int)
+  int* by_rank = (int*)(nrm + n);
   const int b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* Ab = A + (int64_t)b * stride;
   const double* Vb = V + (int64_t)b * stride;
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+  for (int64_t j = wave; j < n; j += 16) {
     double s = 0;
-    for (int64_t i = 0; i < n; ++i) { double x = Ab[j * n + i]; s += x * x; }
-    nrm[j] = sqrt(s);
+    for (int64_t i = lane; i < n; i += 64) { const double x = Ab[j * n + i]; s += x * x; }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) nrm[j] = sqrt(s);
   }
   __syncthreads();
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-    double v = nrm[j];
+  for (int64_t j = tid; j < n; j += 1024) {
+    const double v = nrm[j];
     int64_t rank = 0;
     for (int64_t i = 0; i < n; ++i) {
-      double w = nrm[i];
+      const double w = nrm[i];
       rank += (w > v) || (w == v && i < j);
     }
     sv[(int64_t)b * n + rank] = v;
-    if (rank < kmax) {
-      double inv = v > 0 ? 1.0 / v : 0.0;
-      double* u = U + (int64_t)b * n * kmax + rank * n;
-      double* vv = Vk + (int64_t)b * n * kmax + rank * n;
-      for (int64_t i = 0; i < n; ++i) { u[i] = Ab[j * n + i] * inv; vv[i] = Vb[j * n + i]; }
-    }
+    by_rank[rank] = (int)j;
+  }
+  __syncthreads();
+  const int64_t kk = kmax < n ? kmax : n;
+  for (int64_t e = tid; e < kk * n; e += 1024) {
+    const int64_t r = e / n, i = e - r * n;
+    const int64_t j = by_rank[r];
+    const double v = nrm[j];
+    const double inv = v > 0 ? 1.0 / v : 0.0;
+    U[(int64_t)b * n * kmax + r * n + i] = Ab[j * n + i] * inv;
+    Vk[(int64_t)b * n * kmax + r * n + i] = Vb[j * n + i];
   }
 }
 
 hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int64_t stride, int batch, int64_t kmax,
                                 double* sv, double* U, double* Vk, hipStream_t s) {
   if (n > 4096) return hipErrorInvalidValue;
-  jacobi_finish_kernel<<<batch, 256, n * sizeof(double), s>>>(A, V, n, stride, kmax, sv, U, Vk);
+  jacobi_finish_kernel<<<batch, 1024, n * (sizeof(double) + sizeof(int)), s>>>(A, V, n, stride, kmax, sv, U, Vk);
   return hipGetLastError();
 }
 
