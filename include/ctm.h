@@ -61,7 +61,7 @@ enum {
   CTM_EINVAL = -1,       /* invalid argument */
   CTM_ENOMEM = -2,       /* device allocation failed */
   CTM_EHIP = -3,         /* HIP runtime or kernel launch error */
-  CTM_ESOLVER = -4,      /* QR or SVD reported failure (rocSOLVER info != 0) */
+  CTM_ESOLVER = -4,      /* the projector SVD did not converge, or a grid barrier wait of its sweep ran out */
   CTM_ENONFINITE = -5    /* NaN or Inf found in the environment or the result */
 };
 
@@ -126,8 +126,9 @@ int ctm_energy(ctm_ctx* ctx, const double* H_bond, int n_terms, const ctm_term* 
  * normalisations, the plaquette density matrices and the projectors, whose
  * SVD derivative uses the Lorentzian-broadened F_ij = D/(D^2 + (eta m)^2),
  * D = s_j^2 - s_i^2, m = max(s_i^2, s_j^2) (option "lorentz_eta").
- * Checkpointing: one environment snapshot per sweep is kept and each sweep is
- * recomputed once during the reverse pass.  Afterwards the environment is
+ * Checkpointing: the last sweep and the energy are recorded in the forward
+ * pass; one environment snapshot is kept per earlier sweep, and each earlier
+ * sweep is recomputed once during the reverse pass.  Afterwards the environment is
  * the one reached by the n_sweeps sweeps.  H_bond, terms as in ctm_energy;
  * E (host) receives the energy. */
 int ctm_energy_grad(ctm_ctx* ctx, const double* A, int n_sweeps, const double* H_bond, int n_terms,
@@ -148,7 +149,13 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *                 1 for one stream.  Both give identical results.
  *   "rowmajor_bf16" 1 (default) to run large BF16-mode products of plain
  *                 row-major operands on the dedicated 128 x 128-tile kernel, 0
- *                 for the general contraction kernel; a process-wide switch. */
+ *                 for the general contraction kernel; a process-wide switch.
+ *   "jacobi_one_launch" 1 (default) to run all rounds of a Jacobi sweep of the
+ *                 projector SVD in one launch with a grid barrier between
+ *                 rounds, when the device holds the whole grid at once (else
+ *                 one launch per round); 0 for one launch per round.  Both give
+ *                 identical results.  A barrier wait that runs out (it is
+ *                 bounded) fails the call with CTM_ESOLVER. */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
 /* Live timing of the library's main kernel families.  Between

@@ -78,6 +78,8 @@ struct ctm_ctx {
   double cutoff = 1e-10, eta = 1e-12;
   int check_finite = 1;
   int jacobi_max_sweeps = 40;
+  bool jacobi_one_launch = true;   // all rounds of a Jacobi sweep in one launch (when the grid fits the device)
+  int64_t sweep_capacity = -1;     // workgroups of that launch the device holds at once (-1: not yet asked)
   int last_jacobi_sweeps = 0;
   DBuf spec_prev, spec_cur, dscal;   // spectra and a few device scalars
   bool have_prev = false;
@@ -475,8 +477,9 @@ void hqr_apply(Dev& dev, const HQR& q, double* C, int64_t crs, int64_t ccs, int6
 int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double* sv, double* U, double* Vk) {
   Dev& dev = c->dev;
   const int64_t stride = r * r;
+  // rot: per-matrix rotation counts, then the two barrier words of the one-launch sweep
   DBuf X(&dev, (size_t)batch * stride * 8), W(&dev, (size_t)batch * stride * 8),
-      rot(&dev, (size_t)batch * sizeof(int)), tiny2(&dev, (size_t)batch * 8), ovl(&dev, (size_t)batch * 8);
+      rot(&dev, (size_t)(batch + 2) * sizeof(int)), tiny2(&dev, (size_t)batch * 8), ovl(&dev, (size_t)batch * 8);
   HQR qm;
   qm.A = A; qm.m = r; qm.n = r; qm.rs = 1; qm.cs = r; qm.stride = stride; qm.batch = batch;
   hqr_factor(dev, qm);
@@ -496,22 +499,34 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   const double Cw = (double)ctmk::bjac_pair_columns();
   const double pairs = (double)(ctmk::bjac_rounds(r) + 1) / 2.0 * batch;
   const double bj_flops = pairs * ((Cw * (Cw + 1) / 2.0) * 2.0 * r + 2.0 * (2.0 * r * Cw * Cw));
-  std::vector<int> h(batch);
+  std::vector<int> h(batch + 2);
   std::vector<double> ho(batch);
+  // one launch per sweep when the device holds all its workgroups at once
+  if (c->sweep_capacity < 0) c->sweep_capacity = ctmk::bjac_sweep_capacity();
+  const bool one_launch = c->jacobi_one_launch && ctmk::bjac_grid(r, batch) <= c->sweep_capacity;
   int sweep = 0;
   for (sweep = 1; sweep <= c->jacobi_max_sweeps; ++sweep) {
-    HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, batch, dev.stream));
+    HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, batch + 2, dev.stream));
     fill(dev, view(ovl.p, T_F64, {(int64_t)batch}, "b"), 0.0);
-    for (int64_t t = 0; t < rounds; ++t) {
+    if (one_launch) {
       if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
-      HIP_CHECK(ctmk::launch_bjac_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
-                                        (const double*)tiny2.p, 1, (int*)rot.p, (double*)ovl.p, dev.stream));
+      HIP_CHECK(ctmk::launch_bjac_sweep((double*)X.p, (double*)W.p, r, stride, batch, tol, (const double*)tiny2.p,
+                                        (int*)rot.p, (double*)ovl.p, (unsigned*)((int*)rot.p + batch), dev.stream));
       if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
-      g_counters.count(FAM_JACOBI, bj_flops);
+      g_counters.count(FAM_JACOBI, bj_flops * (double)rounds);
+    } else {
+      for (int64_t t = 0; t < rounds; ++t) {
+        if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
+        HIP_CHECK(ctmk::launch_bjac_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
+                                          (const double*)tiny2.p, 1, (int*)rot.p, (double*)ovl.p, dev.stream));
+        if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
+        g_counters.count(FAM_JACOBI, bj_flops);
+      }
     }
-    HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, batch * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
+    HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, (batch + 2) * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
     HIP_CHECK(hipMemcpyAsync(ho.data(), ovl.p, batch * sizeof(double), hipMemcpyDeviceToHost, dev.stream));
     HIP_CHECK(hipStreamSynchronize(dev.stream));
+    if (h[batch + 1] != 0) throw Error(CTM_ESOLVER, "Jacobi sweep: a grid barrier wait ran out");
     bool any = false;
     double big = 0.0;
     for (int b = 0; b < batch; ++b) {
@@ -1370,6 +1385,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "check_finite") c->check_finite = value != 0;
   else if (k == "streams" && (value == 1 || value == 2)) c->streams = (int)value;
   else if (k == "rowmajor_bf16") ctmk::g_rowmajor_path = value != 0;
+  else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
   else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }
   return CTM_OK;
 }

@@ -1114,14 +1114,39 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
-                                                           int64_t stride, int round, double tol, const double* tiny2,
-                                                           int inner, int* rot, unsigned long long* ovl_max) {
-  constexpr int GS = BJ_C + 1;                  // padded row stride of G and R (column accesses spread over banks)
-  __shared__ double part[BJ_NW][BJ_C * BJ_C];   // per-wave Gram partials
-  __shared__ double G[BJ_C * GS];
-  __shared__ double R[BJ_C * GS];
-  __shared__ int nrot_s;
+constexpr int BJ_GS = BJ_C + 1;   // padded row stride of G and R (column accesses spread over banks)
+struct BjacShared {
+  double part[BJ_NW][BJ_C * BJ_C];   // per-wave Gram partials
+  double G[BJ_C * BJ_GS];
+  double R[BJ_C * BJ_GS];
+  int nrot;
+};
+
+// Column element loads and stores of a round.  COH: at device scope (each
+// access coherent across the L2s of the device), for rounds that other
+// workgroups of the same launch read after a grid barrier.
+template <bool COH>
+__device__ __forceinline__ double col_load(const double* p) {
+  if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void col_store(double* p, double v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
+// One round for the block pair blockIdx.x of matrix blockIdx.y.  Every thread
+// of the workgroup calls it and leaves it together or after its last barrier.
+template <bool COH>
+__device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V, int64_t n, int64_t nblk, int64_t np,
+                                           int64_t stride, int round, double tol, const double* tiny2, int inner,
+                                           int* rot, unsigned long long* ovl_max) {
+  constexpr int GS = BJ_GS;
+  auto& part = sh.part;
+  double* G = sh.G;
+  double* R = sh.R;
+  int& nrot_s = sh.nrot;
   const int k = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   int64_t P, Q;
   if (k == 0) { P = round; Q = np - 1; }
@@ -1151,7 +1176,7 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
 #pragma unroll
       for (int u = 0; u < BJ_GK; ++u) {
         const int64_t row = (kb + u) * 4 + lq;
-        x[u] = (gl >= 0 && row < n) ? Ab[gl * n + row] : 0.0;
+        x[u] = (gl >= 0 && row < n) ? col_load<COH>(Ab + gl * n + row) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < BJ_GK; ++u) gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], gacc, 0, 0, 0);
@@ -1175,7 +1200,8 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     const double* M = isA ? Ab : Vb;
     const int64_t row = (isA ? t : t - tiles) * 16 + lr;
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) x[ks] = (t < ntask && gA[ks] >= 0 && row < n) ? M[gA[ks] * n + row] : 0.0;
+    for (int ks = 0; ks < 4; ++ks)
+      x[ks] = (t < ntask && gA[ks] >= 0 && row < n) ? col_load<COH>(M + gA[ks] * n + row) : 0.0;
   };
   constexpr int AW = BJ_NW - 1;   // waves applying the rotation
   double pf[BJ_TPW][4];
@@ -1286,7 +1312,7 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
     const int64_t row = (isA ? t : t - tiles) * 16 + lr;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      if (gD[e] >= 0 && row < n) M[gD[e] * n + row] = acc[e];
+      if (gD[e] >= 0 && row < n) col_store<COH>(M + gD[e] * n + row, acc[e]);
   };
 #pragma unroll
   for (int u = 0; u < BJ_TPW; ++u) store_tile(wave - 1 + (int64_t)AW * u, pf[u]);
@@ -1297,6 +1323,61 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
   }
 }
 
+__global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
+                                                           int64_t stride, int round, double tol, const double* tiny2,
+                                                           int inner, int* rot, unsigned long long* ovl_max) {
+  __shared__ BjacShared sh;
+  bjac_round<false>(sh, A, V, n, nblk, np, stride, round, tol, tiny2, inner, rot, ovl_max);
+}
+
+// Barrier over all workgroups of the grid, which must all be resident.
+// bar[0] counts arrivals (monotonic: barrier i completes at (i + 1) x
+// workgroups).  The column data the rounds exchange is loaded and stored at
+// device scope (col_load / col_store<true>), so the barrier needs no cache
+// write-back or invalidation: each wave waits until its stores are
+// acknowledged, then the workgroup arrives and waits for the count.  The wait
+// is bounded: a workgroup that waits longer than BAR_SPINS polls sets bar[1]
+// and every workgroup then leaves the kernel (false returned).
+constexpr unsigned BAR_SPINS = 1u << 21;
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int& ok_s) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { ok = 0; break; }
+      if (++spins > BAR_SPINS) {
+        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ok_s = ok;
+  }
+  __syncthreads();
+  return ok_s != 0;
+}
+
+// Rounds [0, rounds) of one tournament sweep in one launch: the same round as
+// bjac_round_kernel, a grid barrier between consecutive rounds (round t + 1
+// reads the columns round t rotated, in other workgroups).  The launch saves
+// the dispatch gap between dependent kernels; the host launches it only when
+// the occupancy of the device holds the whole grid at once.
+__global__ __launch_bounds__(BJ_NT) void bjac_sweep_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
+                                                           int64_t stride, int rounds, double tol, const double* tiny2,
+                                                           int* rot, unsigned long long* ovl_max, unsigned* bar) {
+  __shared__ BjacShared sh;
+  __shared__ int ok_s;
+  const unsigned wgs = gridDim.x * gridDim.y;
+  for (int t = 0; t < rounds; ++t) {
+    bjac_round<true>(sh, A, V, n, nblk, np, stride, t, tol, tiny2, 1, rot, ovl_max);
+    if (t + 1 < rounds && !grid_barrier(bar, (unsigned)(t + 1) * wgs, ok_s)) return;
+  }
+}
+
 hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
                              const double* tiny2, int inner, int* rot, double* ovl_max, hipStream_t s) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
@@ -1304,6 +1385,30 @@ hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, in
   dim3 grid((unsigned)(np / 2), (unsigned)batch);
   bjac_round_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, round, tol, tiny2, inner, rot,
                                            (unsigned long long*)ovl_max);
+  return hipGetLastError();
+}
+
+// Workgroups of bjac_sweep_kernel the device holds at once (0 if unknown).
+int64_t bjac_sweep_capacity() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bjac_sweep_kernel, BJ_NT, 0) != hipSuccess) return 0;
+  return (int64_t)cus * per_cu;
+}
+
+int64_t bjac_grid(int64_t n, int batch) {
+  const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
+  return (nblk + (nblk & 1)) / 2 * batch;
+}
+
+hipError_t launch_bjac_sweep(double* A, double* V, int64_t n, int64_t stride, int batch, double tol,
+                             const double* tiny2, int* rot, double* ovl_max, unsigned* bar, hipStream_t s) {
+  const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
+  const int64_t np = nblk + (nblk & 1);
+  dim3 grid((unsigned)(np / 2), (unsigned)batch);
+  bjac_sweep_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, (int)(np - 1), tol, tiny2, rot,
+                                           (unsigned long long*)ovl_max, bar);
   return hipGetLastError();
 }
 

@@ -252,6 +252,24 @@ def test_second_stream_gives_identical_sweeps(ctm_mod, name, sweeps):
     assert torch.equal(envs[0], envs[1])
 
 
+@pytest.mark.parametrize("name,sweeps", [("heis_d2_chi8", 2), ("ssm_d6_chi72", 1), ("heis_d9_chi100", 1)])
+def test_one_launch_jacobi_sweeps_match_per_round_launches(ctm_mod, name, sweeps):
+    """All rounds of a Jacobi sweep in one launch (grid barrier between
+    rounds, the default) and one launch per round run the same rounds on the
+    same data, so the environments agree bit for bit: 16 x 16 matrices (one
+    round), 432 x 432 (53 rounds, four matrices) and 900 x 900 (113 rounds)."""
+    cfg = synth.CONFIGS[name]
+    A = synth.config_tensors(cfg, 0)
+    envs = []
+    for flag in (0, 1):
+        g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+        g.set_option("jacobi_one_launch", flag)
+        g.sweep(sweeps)
+        envs.append(g.get_env().cpu())
+        del g
+    assert torch.equal(envs[0], envs[1])
+
+
 def test_rowmajor_bf16_products_match_general_kernel(ctm_mod):
     """The density-matrix joins of the D=6, chi=72 energy in BF16 mode (plain
     row-major products, M = N = 10368, K = 2592) on the dedicated kernel and on
