@@ -477,9 +477,10 @@ void hqr_apply(Dev& dev, const HQR& q, double* C, int64_t crs, int64_t ccs, int6
 int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double* sv, double* U, double* Vk) {
   Dev& dev = c->dev;
   const int64_t stride = r * r;
-  // rot: per-matrix rotation counts, then the two barrier words of the one-launch sweep
+  // rot: per-matrix rotation counts, then the synchronisation words of the one-launch sweep
+  const int64_t nsync = ctmk::bjac_sync_words(r, batch);
   DBuf X(&dev, (size_t)batch * stride * 8), W(&dev, (size_t)batch * stride * 8),
-      rot(&dev, (size_t)(batch + 2) * sizeof(int)), tiny2(&dev, (size_t)batch * 8), ovl(&dev, (size_t)batch * 8);
+      rot(&dev, (size_t)(batch + nsync) * sizeof(int)), tiny2(&dev, (size_t)batch * 8), ovl(&dev, (size_t)batch * 8);
   HQR qm;
   qm.A = A; qm.m = r; qm.n = r; qm.rs = 1; qm.cs = r; qm.stride = stride; qm.batch = batch;
   hqr_factor(dev, qm);
@@ -499,14 +500,14 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   const double Cw = (double)ctmk::bjac_pair_columns();
   const double pairs = (double)(ctmk::bjac_rounds(r) + 1) / 2.0 * batch;
   const double bj_flops = pairs * ((Cw * (Cw + 1) / 2.0) * 2.0 * r + 2.0 * (2.0 * r * Cw * Cw));
-  std::vector<int> h(batch + 2);
+  std::vector<int> h(batch + 1);
   std::vector<double> ho(batch);
   // one launch per sweep when the device holds all its workgroups at once
   if (c->sweep_capacity < 0) c->sweep_capacity = ctmk::bjac_sweep_capacity();
   const bool one_launch = c->jacobi_one_launch && ctmk::bjac_grid(r, batch) <= c->sweep_capacity;
   int sweep = 0;
   for (sweep = 1; sweep <= c->jacobi_max_sweeps; ++sweep) {
-    HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, batch + 2, dev.stream));
+    HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, one_launch ? batch + nsync : batch, dev.stream));
     fill(dev, view(ovl.p, T_F64, {(int64_t)batch}, "b"), 0.0);
     if (one_launch) {
       if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
@@ -523,10 +524,10 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
         g_counters.count(FAM_JACOBI, bj_flops);
       }
     }
-    HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, (batch + 2) * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
+    HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, (batch + 1) * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
     HIP_CHECK(hipMemcpyAsync(ho.data(), ovl.p, batch * sizeof(double), hipMemcpyDeviceToHost, dev.stream));
     HIP_CHECK(hipStreamSynchronize(dev.stream));
-    if (h[batch + 1] != 0) throw Error(CTM_ESOLVER, "Jacobi sweep: a grid barrier wait ran out");
+    if (one_launch && h[batch] != 0) throw Error(CTM_ESOLVER, "Jacobi sweep: a wait between rounds ran out");
     bool any = false;
     double big = 0.0;
     for (int b = 0; b < batch; ++b) {

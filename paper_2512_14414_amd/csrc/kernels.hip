@@ -1136,6 +1136,14 @@ __device__ __forceinline__ void col_store(double* p, double v) {
   else *p = v;
 }
 
+// Blocks P < Q of pair k in round `round` of the tournament over np players
+// (the round-robin circle: player np - 1 fixed, the others turned by one).
+__device__ __forceinline__ void bjac_pair(int k, int round, int64_t np, int64_t& P, int64_t& Q) {
+  if (k == 0) { P = round; Q = np - 1; }
+  else { P = (round + k) % (np - 1); Q = (round - k + (np - 1)) % (np - 1); }
+  if (P > Q) { const int64_t t = P; P = Q; Q = t; }
+}
+
 // One round for the block pair blockIdx.x of matrix blockIdx.y.  Every thread
 // of the workgroup calls it and leaves it together or after its last barrier.
 template <bool COH>
@@ -1149,12 +1157,10 @@ __device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V,
   int& nrot_s = sh.nrot;
   const int k = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   int64_t P, Q;
-  if (k == 0) { P = round; Q = np - 1; }
-  else { P = (round + k) % (np - 1); Q = (round - k + (np - 1)) % (np - 1); }
+  bjac_pair(k, round, np, P, Q);
   // a block paired with the padding player (odd block count, or a single
   // block) is still rotated within itself: the missing columns read as absent
   if (P >= nblk && Q >= nblk) return;
-  if (P > Q) { int64_t t = P; P = Q; Q = t; }
   double* Ab = A + (int64_t)b * stride;
   double* Vb = V + (int64_t)b * stride;
   // global column of local column c, or -1 past the end of the matrix
@@ -1330,26 +1336,41 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
   bjac_round<false>(sh, A, V, n, nblk, np, stride, round, tol, tiny2, inner, rot, ovl_max);
 }
 
-// Barrier over all workgroups of the grid, which must all be resident.
-// bar[0] counts arrivals (monotonic: barrier i completes at (i + 1) x
-// workgroups).  The column data the rounds exchange is loaded and stored at
-// device scope (col_load / col_store<true>), so the barrier needs no cache
-// write-back or invalidation: each wave waits until its stores are
-// acknowledged, then the workgroup arrives and waits for the count.  The wait
-// is bounded: a workgroup that waits longer than BAR_SPINS polls sets bar[1]
-// and every workgroup then leaves the kernel (false returned).
+// Ordering of the rounds inside one launch.  Round t + 1 of a pair needs
+// only its two blocks as round t left them, each rotated by one other
+// workgroup of the same matrix, so the workgroups synchronise per block, not
+// per round: ver[b * np + B] counts the rounds finished on block B of matrix b.
+// A workgroup publishes a round by waiting until every wave's stores are
+// acknowledged and then raising the counters of its two blocks; it starts
+// round t once both of its blocks have count t.  The exchanged column data is
+// loaded and stored at device scope (col_load / col_store<true>), so no cache
+// write-back or invalidation is needed.  All workgroups must be resident
+// (round 0 waits for nothing, and by induction every round's producers
+// finish).  The wait is bounded: a workgroup that polls more than BAR_SPINS
+// times sets *abort and every workgroup then leaves the kernel.
 constexpr unsigned BAR_SPINS = 1u << 21;
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int& ok_s) {
+
+__device__ __forceinline__ void publish_blocks(unsigned* ver, int64_t P, int64_t Q, int64_t nblk, unsigned done) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (P < nblk) __hip_atomic_store(ver + P, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (Q < nblk) __hip_atomic_store(ver + Q, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ bool wait_blocks(const unsigned* ver, int64_t P, int64_t Q, int64_t nblk, unsigned need,
+                                            unsigned* abort, int& ok_s) {
+  if (threadIdx.x == 0) {
     int ok = 1;
     unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { ok = 0; break; }
+    for (;;) {
+      const bool p_ready = P >= nblk || __hip_atomic_load(ver + P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+      const bool q_ready = Q >= nblk || __hip_atomic_load(ver + Q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+      if (p_ready && q_ready) break;
+      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { ok = 0; break; }
       if (++spins > BAR_SPINS) {
-        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
@@ -1362,19 +1383,22 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int
 }
 
 // Rounds [0, rounds) of one tournament sweep in one launch: the same round as
-// bjac_round_kernel, a grid barrier between consecutive rounds (round t + 1
-// reads the columns round t rotated, in other workgroups).  The launch saves
-// the dispatch gap between dependent kernels; the host launches it only when
-// the occupancy of the device holds the whole grid at once.
+// bjac_round_kernel, ordered per block as above.  The launch saves the
+// dispatch gap between dependent kernels; the host launches it only when the
+// occupancy of the device holds the whole grid at once.  sync[0] is the abort
+// flag, sync[1 + b * np + B] the round counters; all zero at launch.
 __global__ __launch_bounds__(BJ_NT) void bjac_sweep_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
                                                            int64_t stride, int rounds, double tol, const double* tiny2,
-                                                           int* rot, unsigned long long* ovl_max, unsigned* bar) {
+                                                           int* rot, unsigned long long* ovl_max, unsigned* sync) {
   __shared__ BjacShared sh;
   __shared__ int ok_s;
-  const unsigned wgs = gridDim.x * gridDim.y;
+  unsigned* ver = sync + 1 + (int64_t)blockIdx.y * np;
   for (int t = 0; t < rounds; ++t) {
+    int64_t P, Q;
+    bjac_pair(blockIdx.x, t, np, P, Q);
+    if (t > 0 && !wait_blocks(ver, P, Q, nblk, (unsigned)t, sync, ok_s)) return;
     bjac_round<true>(sh, A, V, n, nblk, np, stride, t, tol, tiny2, 1, rot, ovl_max);
-    if (t + 1 < rounds && !grid_barrier(bar, (unsigned)(t + 1) * wgs, ok_s)) return;
+    if (t + 1 < rounds) publish_blocks(ver, P, Q, nblk, (unsigned)(t + 1));
   }
 }
 
@@ -1402,13 +1426,18 @@ int64_t bjac_grid(int64_t n, int batch) {
   return (nblk + (nblk & 1)) / 2 * batch;
 }
 
+int64_t bjac_sync_words(int64_t n, int batch) {
+  const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
+  return 1 + (nblk + (nblk & 1)) * batch;
+}
+
 hipError_t launch_bjac_sweep(double* A, double* V, int64_t n, int64_t stride, int batch, double tol,
-                             const double* tiny2, int* rot, double* ovl_max, unsigned* bar, hipStream_t s) {
+                             const double* tiny2, int* rot, double* ovl_max, unsigned* sync, hipStream_t s) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
   const int64_t np = nblk + (nblk & 1);
   dim3 grid((unsigned)(np / 2), (unsigned)batch);
   bjac_sweep_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, (int)(np - 1), tol, tiny2, rot,
-                                           (unsigned long long*)ovl_max, bar);
+                                           (unsigned long long*)ovl_max, sync);
   return hipGetLastError();
 }
 
