@@ -150,12 +150,13 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *   "rowmajor_bf16" 1 (default) to run large BF16-mode products of plain
  *                 row-major operands on the dedicated 128 x 128-tile kernel, 0
  *                 for the general contraction kernel; a process-wide switch.
- *   "jacobi_one_launch" 1 (default) to run all rounds of a Jacobi sweep of the
- *                 projector SVD in one launch with a grid barrier between
- *                 rounds, when the device holds the whole grid at once (else
- *                 one launch per round); 0 for one launch per round.  Both give
- *                 identical results.  A barrier wait that runs out (it is
- *                 bounded) fails the call with CTM_ESOLVER. */
+ *   "jacobi_one_launch" 1 (default) to run the whole Jacobi iteration of the
+ *                 projector SVD (all sweeps, the stop test taken on the device)
+ *                 in one launch, when the device holds its grid at once (else
+ *                 one launch per round); 0 for one launch per round and the stop
+ *                 test on the host.  Both give identical results.  No
+ *                 convergence, or a wait between rounds that runs out (waits
+ *                 are bounded), fails the call with CTM_ESOLVER when it returns. */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
 /* Live timing of the library's main kernel families.  Between

@@ -80,7 +80,6 @@ struct ctm_ctx {
   int jacobi_max_sweeps = 40;
   bool jacobi_one_launch = true;   // all rounds of a Jacobi sweep in one launch (when the grid fits the device)
   int64_t sweep_capacity = -1;     // workgroups of that launch the device holds at once (-1: not yet asked)
-  int last_jacobi_sweeps = 0;
   DBuf spec_prev, spec_cur, dscal;   // spectra and a few device scalars
   bool have_prev = false;
   DBuf rdm_buf;
@@ -477,10 +476,18 @@ void hqr_apply(Dev& dev, const HQR& q, double* C, int64_t crs, int64_t ccs, int6
 int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double* sv, double* U, double* Vk) {
   Dev& dev = c->dev;
   const int64_t stride = r * r;
-  // rot: per-matrix rotation counts, then the synchronisation words of the one-launch sweep
-  const int64_t nsync = ctmk::bjac_sync_words(r, batch);
+  const int maxsw = c->jacobi_max_sweeps;
+  // the whole iteration in one launch when the device holds all its workgroups at once
+  if (c->sweep_capacity < 0) c->sweep_capacity = ctmk::bjac_sweep_capacity();
+  const bool one_launch = c->jacobi_one_launch && ctmk::bjac_grid(r, batch) <= c->sweep_capacity;
+  // per-sweep rotation counts and largest rotated |cos| (one slot per sweep in
+  // one launch, one reused slot otherwise), then the sweep count; the
+  // synchronisation words of the one-launch iteration
+  const int64_t slots = one_launch ? (int64_t)maxsw * batch : batch;
+  const int64_t nsync = one_launch ? ctmk::bjac_sync_words(r, batch, maxsw) : 0;
   DBuf X(&dev, (size_t)batch * stride * 8), W(&dev, (size_t)batch * stride * 8),
-      rot(&dev, (size_t)(batch + nsync) * sizeof(int)), tiny2(&dev, (size_t)batch * 8), ovl(&dev, (size_t)batch * 8);
+      rot(&dev, (size_t)(slots + 1 + nsync) * sizeof(int)), tiny2(&dev, (size_t)batch * 8),
+      ovl(&dev, (size_t)slots * 8);
   HQR qm;
   qm.A = A; qm.m = r; qm.n = r; qm.rs = 1; qm.cs = r; qm.stride = stride; qm.batch = batch;
   hqr_factor(dev, qm);
@@ -500,48 +507,54 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   const double Cw = (double)ctmk::bjac_pair_columns();
   const double pairs = (double)(ctmk::bjac_rounds(r) + 1) / 2.0 * batch;
   const double bj_flops = pairs * ((Cw * (Cw + 1) / 2.0) * 2.0 * r + 2.0 * (2.0 * r * Cw * Cw));
-  std::vector<int> h(batch + 1);
-  std::vector<double> ho(batch);
-  // one launch per sweep when the device holds all its workgroups at once
-  if (c->sweep_capacity < 0) c->sweep_capacity = ctmk::bjac_sweep_capacity();
-  const bool one_launch = c->jacobi_one_launch && ctmk::bjac_grid(r, batch) <= c->sweep_capacity;
+  int* rot_p = (int*)rot.p;
   int sweep = 0;
-  for (sweep = 1; sweep <= c->jacobi_max_sweeps; ++sweep) {
-    HIP_CHECK(ctmk::launch_fill_int((int*)rot.p, 0, one_launch ? batch + nsync : batch, dev.stream));
-    fill(dev, view(ovl.p, T_F64, {(int64_t)batch}, "b"), 0.0);
-    if (one_launch) {
-      if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
-      HIP_CHECK(ctmk::launch_bjac_sweep((double*)X.p, (double*)W.p, r, stride, batch, tol, (const double*)tiny2.p,
-                                        (int*)rot.p, (double*)ovl.p, (unsigned*)((int*)rot.p + batch), dev.stream));
-      if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
-      g_counters.count(FAM_JACOBI, bj_flops * (double)rounds);
-    } else {
+  if (one_launch) {
+    // no host synchronisation: failures reach the context's solver flag,
+    // which the calls check when they return
+    HIP_CHECK(ctmk::launch_fill_int(rot_p, 0, slots + 1 + nsync, dev.stream));
+    fill(dev, view(ovl.p, T_F64, {slots}, "b"), 0.0);
+    if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
+    HIP_CHECK(ctmk::launch_bjac_svd((double*)X.p, (double*)W.p, r, stride, batch, maxsw, tol, stop,
+                                    (const double*)tiny2.p, rot_p, (double*)ovl.p, (unsigned*)(rot_p + slots + 1),
+                                    (int*)c->flag.p + 1, rot_p + slots, dev.stream));
+    if (g_counters.timing) {
+      g_counters.record(dev.stream, FAM_JACOBI);
+      // profiling only: the flop count needs the number of sweeps run
+      HIP_CHECK(hipMemcpyAsync(&sweep, rot_p + slots, sizeof(int), hipMemcpyDeviceToHost, dev.stream));
+      HIP_CHECK(hipStreamSynchronize(dev.stream));
+      g_counters.count(FAM_JACOBI, bj_flops * (double)rounds * sweep);
+    }
+  } else {
+    std::vector<int> h(batch);
+    std::vector<double> ho(batch);
+    for (sweep = 1; sweep <= maxsw; ++sweep) {
+      HIP_CHECK(ctmk::launch_fill_int(rot_p, 0, batch, dev.stream));
+      fill(dev, view(ovl.p, T_F64, {(int64_t)batch}, "b"), 0.0);
       for (int64_t t = 0; t < rounds; ++t) {
         if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
         HIP_CHECK(ctmk::launch_bjac_round((double*)X.p, (double*)W.p, r, stride, batch, (int)t, tol,
-                                          (const double*)tiny2.p, 1, (int*)rot.p, (double*)ovl.p, dev.stream));
+                                          (const double*)tiny2.p, 1, rot_p, (double*)ovl.p, dev.stream));
         if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
         g_counters.count(FAM_JACOBI, bj_flops);
       }
+      HIP_CHECK(hipMemcpyAsync(h.data(), rot_p, batch * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
+      HIP_CHECK(hipMemcpyAsync(ho.data(), ovl.p, batch * sizeof(double), hipMemcpyDeviceToHost, dev.stream));
+      HIP_CHECK(hipStreamSynchronize(dev.stream));
+      bool any = false;
+      double big = 0.0;
+      for (int b = 0; b < batch; ++b) {
+        any |= h[b] != 0;
+        big = std::max(big, ho[b]);
+      }
+      if (!any || big <= stop) break;
     }
-    HIP_CHECK(hipMemcpyAsync(h.data(), rot.p, (batch + 1) * sizeof(int), hipMemcpyDeviceToHost, dev.stream));
-    HIP_CHECK(hipMemcpyAsync(ho.data(), ovl.p, batch * sizeof(double), hipMemcpyDeviceToHost, dev.stream));
-    HIP_CHECK(hipStreamSynchronize(dev.stream));
-    if (one_launch && h[batch] != 0) throw Error(CTM_ESOLVER, "Jacobi sweep: a wait between rounds ran out");
-    bool any = false;
-    double big = 0.0;
-    for (int b = 0; b < batch; ++b) {
-      any |= h[b] != 0;
-      big = std::max(big, ho[b]);
-    }
-    if (!any || big <= stop) break;
+    if (sweep > maxsw) throw Error(CTM_ESOLVER, "Jacobi SVD did not converge");
   }
-  if (sweep > c->jacobi_max_sweeps) throw Error(CTM_ESOLVER, "Jacobi SVD did not converge");
   // normalised columns of X W are the right vectors of A; the columns of W, times Q, the left ones
   HIP_CHECK(ctmk::launch_jacobi_finish((const double*)X.p, (const double*)W.p, r, stride, batch, kmax, sv, Vk, U,
                                        dev.stream));
   hqr_apply(dev, qm, U, 1, r, r * kmax, kmax, false);
-  c->last_jacobi_sweeps = sweep;
   return sweep;
 }
 
@@ -926,7 +939,7 @@ void check_flags(ctm_ctx* c) {
   HIP_CHECK(hipStreamSynchronize(c->dev.stream));
   HIP_CHECK(hipMemsetAsync(c->flag.p, 0, 2 * sizeof(int), c->dev.stream));
   if (h[0]) throw Error(CTM_ENONFINITE, "non-finite value in the environment");
-  if (h[1]) throw Error(CTM_ESOLVER, "SVD did not converge (rocsolver info " + std::to_string(h[1]) + ")");
+  if (h[1]) throw Error(CTM_ESOLVER, "SVD did not converge (" + std::to_string(h[1]) + " failed solves)");
 }
 
 // ---------------------------------------------------------------------------

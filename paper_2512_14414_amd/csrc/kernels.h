@@ -84,14 +84,18 @@ hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int
 
 hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
                              const double* tiny2, int inner, int* rot, double* ovl_max, hipStream_t s);
-// All rounds of one tournament sweep in one launch (workgroups ordered per
-// block between rounds).  sync: bjac_sync_words(n, batch) unsigned ints, zero
-// before the launch; sync[0] != 0 after it means a wait ran out (the sweep is
-// incomplete).  Only for grids of at most bjac_sweep_capacity() workgroups
-// (bjac_grid(n, batch)).
-hipError_t launch_bjac_sweep(double* A, double* V, int64_t n, int64_t stride, int batch, double tol,
-                             const double* tiny2, int* rot, double* ovl_max, unsigned* sync, hipStream_t s);
-int64_t bjac_sync_words(int64_t n, int batch);
+// The whole Jacobi iteration in one launch: sweeps of tournament rounds
+// (workgroups ordered per block between rounds) and the host loop's stop rule
+// (no rotation, or largest rotated |cos| <= stop, over the batch) taken on the
+// device after each sweep.  rot: max_sweeps * batch ints, ovl: max_sweeps *
+// batch doubles, sync: bjac_sync_words(n, batch, max_sweeps) unsigned ints, all
+// zero before the launch.  *sweeps (device) receives the sweeps run; no
+// convergence, or a wait that ran out, adds one to *fail (device).  Only for
+// grids of at most bjac_sweep_capacity() workgroups (bjac_grid(n, batch)).
+hipError_t launch_bjac_svd(double* A, double* V, int64_t n, int64_t stride, int batch, int max_sweeps, double tol,
+                           double stop, const double* tiny2, int* rot, double* ovl, unsigned* sync, int* fail,
+                           int* sweeps, hipStream_t s);
+int64_t bjac_sync_words(int64_t n, int batch, int max_sweeps);
 int64_t bjac_sweep_capacity();
 int64_t bjac_grid(int64_t n, int batch);
 int64_t bjac_rounds(int64_t n);

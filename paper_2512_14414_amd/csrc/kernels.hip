@@ -1339,10 +1339,11 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
 // Ordering of the rounds inside one launch.  Round t + 1 of a pair needs
 // only its two blocks as round t left them, each rotated by one other
 // workgroup of the same matrix, so the workgroups synchronise per block, not
-// per round: ver[b * np + B] counts the rounds finished on block B of matrix b.
-// A workgroup publishes a round by waiting until every wave's stores are
-// acknowledged and then raising the counters of its two blocks; it starts
-// round t once both of its blocks have count t.  The exchanged column data is
+// per round: ver[b * np + B] counts the rounds finished on block B of matrix b
+// (across sweeps: round t of sweep s is number s * rounds + t).  A workgroup
+// publishes a round by waiting until every wave's stores are acknowledged and
+// then raising the counters of its two blocks; it starts round number g once
+// both of its blocks have count g.  The exchanged column data is
 // loaded and stored at device scope (col_load / col_store<true>), so no cache
 // write-back or invalidation is needed.  All workgroups must be resident
 // (round 0 waits for nothing, and by induction every round's producers
@@ -1382,23 +1383,91 @@ __device__ __forceinline__ bool wait_blocks(const unsigned* ver, int64_t P, int6
   return ok_s != 0;
 }
 
-// Rounds [0, rounds) of one tournament sweep in one launch: the same round as
-// bjac_round_kernel, ordered per block as above.  The launch saves the
-// dispatch gap between dependent kernels; the host launches it only when the
-// occupancy of the device holds the whole grid at once.  sync[0] is the abort
-// flag, sync[1 + b * np + B] the round counters; all zero at launch.
-__global__ __launch_bounds__(BJ_NT) void bjac_sweep_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
-                                                           int64_t stride, int rounds, double tol, const double* tiny2,
-                                                           int* rot, unsigned long long* ovl_max, unsigned* sync) {
+// Barrier over all workgroups of the grid at the end of a sweep: *count
+// collects arrivals (one counter per sweep, zero at launch).  Bounded like
+// wait_blocks.
+__device__ __forceinline__ bool sweep_barrier(unsigned* count, unsigned target, unsigned* abort, int& ok_s) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { ok = 0; break; }
+      if (++spins > BAR_SPINS) {
+        __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ok_s = ok;
+  }
+  __syncthreads();
+  return ok_s != 0;
+}
+
+// The whole Jacobi iteration in one launch: sweeps of `rounds` rounds (the
+// round of bjac_round_kernel, ordered per block as above), and after each
+// sweep the stop rule on the totals of the whole batch: stop once no pair was
+// rotated or the largest rotated |cos| is at most `stop`, the same decision,
+// from the same sums, as a host loop over per-round launches.  rot and ovl
+// hold one slot per sweep ([sweep][batch]).  sync[0] is the abort flag,
+// sync[1 + b * np + B] the round counters of the blocks (counting across
+// sweeps), then one arrival counter per sweep; everything zero at launch.
+// *sweeps receives the number of sweeps run.  No convergence within
+// max_sweeps, or a wait that ran out, adds one to *fail.  The host launches it
+// only when the occupancy of the device holds the whole grid at once.
+__global__ __launch_bounds__(BJ_NT) void bjac_svd_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
+                                                         int64_t stride, int rounds, int max_sweeps, double tol,
+                                                         double stop, const double* tiny2, int* rot,
+                                                         unsigned long long* ovl, unsigned* sync, int* fail,
+                                                         int* sweeps) {
   __shared__ BjacShared sh;
-  __shared__ int ok_s;
+  __shared__ int ok_s, go_s;
+  const int batch = (int)gridDim.y;
+  const unsigned wgs = gridDim.x * gridDim.y;
   unsigned* ver = sync + 1 + (int64_t)blockIdx.y * np;
-  for (int t = 0; t < rounds; ++t) {
-    int64_t P, Q;
-    bjac_pair(blockIdx.x, t, np, P, Q);
-    if (t > 0 && !wait_blocks(ver, P, Q, nblk, (unsigned)t, sync, ok_s)) return;
-    bjac_round<true>(sh, A, V, n, nblk, np, stride, t, tol, tiny2, 1, rot, ovl_max);
-    if (t + 1 < rounds) publish_blocks(ver, P, Q, nblk, (unsigned)(t + 1));
+  unsigned* arrive = sync + 1 + (int64_t)batch * np;
+  const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    int* rot_s = rot + (int64_t)sw * batch;
+    unsigned long long* ovl_s = ovl + (int64_t)sw * batch;
+    for (int t = 0; t < rounds; ++t) {
+      int64_t P, Q;
+      bjac_pair(blockIdx.x, t, np, P, Q);
+      const unsigned g = (unsigned)sw * (unsigned)rounds + (unsigned)t;
+      if (g > 0 && !wait_blocks(ver, P, Q, nblk, g, sync, ok_s)) {
+        if (threadIdx.x == 0) atomicAdd(fail, 1);
+        return;
+      }
+      bjac_round<true>(sh, A, V, n, nblk, np, stride, t, tol, tiny2, 1, rot_s, ovl_s);
+      publish_blocks(ver, P, Q, nblk, g + 1);
+    }
+    if (!sweep_barrier(arrive + sw, wgs, sync, ok_s)) {
+      if (threadIdx.x == 0) atomicAdd(fail, 1);
+      return;
+    }
+    if (threadIdx.x == 0) {
+      bool any = false;
+      unsigned long long big = 0;   // non-negative doubles order as their bit patterns
+      for (int b = 0; b < batch; ++b) {
+        any |= __hip_atomic_load(rot_s + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        const unsigned long long o = __hip_atomic_load(ovl_s + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        big = o > big ? o : big;
+      }
+      go_s = any && __longlong_as_double((long long)big) > stop;
+    }
+    __syncthreads();
+    if (!go_s) {
+      if (lead) *sweeps = sw + 1;
+      return;
+    }
+  }
+  if (lead) {
+    *sweeps = max_sweeps;
+    atomicAdd(fail, 1);
   }
 }
 
@@ -1412,12 +1481,12 @@ hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, in
   return hipGetLastError();
 }
 
-// Workgroups of bjac_sweep_kernel the device holds at once (0 if unknown).
+// Workgroups of bjac_svd_kernel the device holds at once (0 if unknown).
 int64_t bjac_sweep_capacity() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bjac_sweep_kernel, BJ_NT, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bjac_svd_kernel, BJ_NT, 0) != hipSuccess) return 0;
   return (int64_t)cus * per_cu;
 }
 
@@ -1426,18 +1495,19 @@ int64_t bjac_grid(int64_t n, int batch) {
   return (nblk + (nblk & 1)) / 2 * batch;
 }
 
-int64_t bjac_sync_words(int64_t n, int batch) {
+int64_t bjac_sync_words(int64_t n, int batch, int max_sweeps) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
-  return 1 + (nblk + (nblk & 1)) * batch;
+  return 1 + (nblk + (nblk & 1)) * batch + max_sweeps;
 }
 
-hipError_t launch_bjac_sweep(double* A, double* V, int64_t n, int64_t stride, int batch, double tol,
-                             const double* tiny2, int* rot, double* ovl_max, unsigned* sync, hipStream_t s) {
+hipError_t launch_bjac_svd(double* A, double* V, int64_t n, int64_t stride, int batch, int max_sweeps, double tol,
+                           double stop, const double* tiny2, int* rot, double* ovl, unsigned* sync, int* fail,
+                           int* sweeps, hipStream_t s) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
   const int64_t np = nblk + (nblk & 1);
   dim3 grid((unsigned)(np / 2), (unsigned)batch);
-  bjac_sweep_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, (int)(np - 1), tol, tiny2, rot,
-                                           (unsigned long long*)ovl_max, sync);
+  bjac_svd_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, (int)(np - 1), max_sweeps, tol, stop, tiny2, rot,
+                                         (unsigned long long*)ovl, sync, fail, sweeps);
   return hipGetLastError();
 }
 
