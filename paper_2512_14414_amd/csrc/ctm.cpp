@@ -435,24 +435,45 @@ void hqr_panel_apply(Dev& dev, const HQR& q, int64_t p, double* C, int64_t crs, 
   contract(dev, ctmk::MODE_F64, Cv, Vv, Zv, -1.0, 1);
 }
 
-void hqr_factor(Dev& dev, HQR& q) {
+void hqr_prepare(Dev& dev, HQR& q) {
   q.k = std::min(q.m, q.n);
   q.nb = qrk::panel_width(q.m);
   q.npanel = (q.k + q.nb - 1) / q.nb;
   q.tau = DBuf(&dev, (size_t)std::max<int64_t>(1, q.batch * q.k) * 8);
   q.T = DBuf(&dev, (size_t)std::max<int64_t>(1, q.batch * q.tstride()) * 8);
-  for (int64_t p = 0; p < q.npanel; ++p) {
-    const int64_t j0 = p * q.nb;
-    const int nbp = (int)std::min<int64_t>(q.nb, q.k - j0);
-    double* Tp = (double*)q.T.p + p * q.nb * q.nb;
-    if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
-    HIP_CHECK(qrk::launch_panel(q.A, q.rs, q.cs, q.stride, q.m, q.n, j0, q.batch, (double*)q.tau.p, q.k, Tp,
-                                q.tstride(), dev.stream));
-    if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
-    // Householder panel: about 4 (m - j0) nbp^2 flops per matrix (norms, reflections, T factor)
-    g_counters.count(FAM_PANEL, 4.0 * (double)(q.m - j0) * nbp * nbp * q.batch);
-    hqr_panel_apply(dev, q, p, q.A, q.rs, q.cs, q.stride, j0 + nbp, q.n - (j0 + nbp), true);
+}
+
+// Panel p of the blocked Householder QR and its update of the trailing columns.
+void hqr_step(Dev& dev, HQR& q, int64_t p) {
+  const int64_t j0 = p * q.nb;
+  const int nbp = (int)std::min<int64_t>(q.nb, q.k - j0);
+  double* Tp = (double*)q.T.p + p * q.nb * q.nb;
+  if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
+  HIP_CHECK(qrk::launch_panel(q.A, q.rs, q.cs, q.stride, q.m, q.n, j0, q.batch, (double*)q.tau.p, q.k, Tp,
+                              q.tstride(), dev.stream));
+  if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
+  // Householder panel: about 4 (m - j0) nbp^2 flops per matrix (norms, reflections, T factor)
+  g_counters.count(FAM_PANEL, 4.0 * (double)(q.m - j0) * nbp * nbp * q.batch);
+  hqr_panel_apply(dev, q, p, q.A, q.rs, q.cs, q.stride, j0 + nbp, q.n - (j0 + nbp), true);
+}
+
+void hqr_factor(Dev& dev, HQR& q) {
+  hqr_prepare(dev, q);
+  for (int64_t p = 0; p < q.npanel; ++p) hqr_step(dev, q, p);
+}
+
+// Factorisations on (possibly) different streams, their panels queued
+// alternately: queued one after the other, the second stream would wait for
+// the host to queue all of the first one's launches.
+void hqr_factor_all(Dev* const* devs, HQR* const* qs, int count) {
+  int64_t most = 0;
+  for (int i = 0; i < count; ++i) {
+    hqr_prepare(*devs[i], *qs[i]);
+    most = std::max(most, qs[i]->npanel);
   }
+  for (int64_t p = 0; p < most; ++p)
+    for (int i = 0; i < count; ++i)
+      if (p < qs[i]->npanel) hqr_step(*devs[i], *qs[i], p);
 }
 
 // C_b <- Q_b C_b (trans: Q_b^T C_b) for the m x ncols matrices C + b*cstride
@@ -654,13 +675,24 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
       R.P = P64 + (size_t)I * maxkd * chi;
       R.Q = Q64 + (size_t)I * maxkd * chi;
     }
+  {
+    Dev* fdev[2];
+    HQR* fq[2];
+    int nf = 0;
+    for (int p = 0; p < 2; ++p) {
+      if (!cnt[p]) continue;
+      const int64_t sz = kd[p] * mn[p];
+      qr[p].A = (double*)NS[p].p;
+      qr[p].m = mn[p]; qr[p].n = kd[p]; qr[p].rs = kd[p]; qr[p].cs = 1; qr[p].stride = sz; qr[p].batch = 2 * cnt[p];
+      fdev[nf] = p ? &pdev1 : &dev;
+      fq[nf++] = &qr[p];
+    }
+    hqr_factor_all(fdev, fq, nf);
+  }
   for (int p = 0; p < 2; ++p) {
     if (!cnt[p]) continue;
     Dev& pd = p ? pdev1 : dev;
     const int64_t sz = kd[p] * mn[p];
-    qr[p].A = (double*)NS[p].p;
-    qr[p].m = mn[p]; qr[p].n = kd[p]; qr[p].rs = kd[p]; qr[p].cs = 1; qr[p].stride = sz; qr[p].batch = 2 * cnt[p];
-    hqr_factor(pd, qr[p]);
     HIP_CHECK(qrk::launch_extract_rt((const double*)NS[p].p, kd[p], 1, sz, kd[p], r, (double*)L[p].p, kd[p] * r,
                                      2 * cnt[p], pd.stream));
     TRef Mv{(double*)Mb.p + (size_t)p * r * r, T_F64, {cnt[p], r, r}, {2 * r * r, 1, r}, "bij"};

@@ -1236,7 +1236,7 @@ __device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V,
   // round's update G <- J^T G J, R <- R J is local to the lane once it has the
   // rotations of pairs j and k, which lane (j, j) computes from its block
   if (tid < 64) {
-    const double t2 = tiny2[b];
+    const double t2 = tiny2[b], tol2 = tol * tol;
     const int pj = lane >> 3, pk = lane & 7;
     int nrot = 0;
     double ovl = 0.0;   // largest |cos| between two columns this lane rotated
@@ -1255,13 +1255,21 @@ __device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V,
         const double g00 = G[p * GS + p2], g01 = G[p * GS + q2], g10 = G[q * GS + p2], g11 = G[q * GS + q2];
         const double r00 = R[p * GS + p2], r01 = R[p * GS + q2], r10 = R[q * GS + p2], r11 = R[q * GS + q2];
         double c = 1.0, sn = 0.0;
-        const double sq = sqrt(g00 * g11);
-        if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 && fabs(g01) > tol * sq) {
-          ovl = fmax(ovl, fabs(g01) / sq);
-          const double zeta = (g11 - g00) / (2.0 * g01);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = c * t;
+        // the pair test |g01| > tol sqrt(g00 g11) in squares (g00, g11 > t2 keep the product normal)
+        if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 &&
+            g01 * g01 > tol2 * (g00 * g11)) {
+          // |cos| of the pair, for the stop test only: the hardware reciprocal square root suffices
+          ovl = fmax(ovl, fabs(g01) * __builtin_amdgcn_rsq(g00 * g11));
+          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = d / (2 g01), d = g11 - g00,
+          // written with den = |d| + sqrt(d^2 + 4 g01^2): t = +-2 g01 / den, and
+          // c = 1 / sqrt(1 + t^2) = den / sqrt(den^2 + 4 g01^2), s = c t (two square roots, one division;
+          // the squares stay finite for Gram entries below 1e150, far above those of the normalised
+          // half systems)
+          const double d = g11 - g00, e = 2.0 * g01;
+          const double den = fabs(d) + sqrt(d * d + e * e);
+          const double rn = 1.0 / sqrt(den * den + e * e);
+          c = den * rn;
+          sn = (d >= 0.0 ? e : -e) * rn;
         }
         const unsigned long long live = __ballot(sn != 0.0);
         if (live) {
