@@ -1144,6 +1144,16 @@ __device__ __forceinline__ void bjac_pair(int k, int round, int64_t np, int64_t&
   if (P > Q) { const int64_t t = P; P = Q; Q = t; }
 }
 
+// 1 / sqrt(x) for normal x > 0: the hardware estimate and two Newton steps
+// y <- y (3 - x y^2) / 2, which converge quadratically to a few ulp.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 // One round for the block pair blockIdx.x of matrix blockIdx.y.  Every thread
 // of the workgroup calls it and leaves it together or after its last barrier.
 template <bool COH>
@@ -1262,12 +1272,13 @@ __device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V,
           ovl = fmax(ovl, fabs(g01) * __builtin_amdgcn_rsq(g00 * g11));
           // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = d / (2 g01), d = g11 - g00,
           // written with den = |d| + sqrt(d^2 + 4 g01^2): t = +-2 g01 / den, and
-          // c = 1 / sqrt(1 + t^2) = den / sqrt(den^2 + 4 g01^2), s = c t (two square roots, one division;
-          // the squares stay finite for Gram entries below 1e150, far above those of the normalised
-          // half systems)
+          // c = 1 / sqrt(1 + t^2) = den / sqrt(den^2 + 4 g01^2), s = c t (two reciprocal square
+          // roots; the squares stay finite for Gram entries below 1e150, far above those of the
+          // normalised half systems)
           const double d = g11 - g00, e = 2.0 * g01;
-          const double den = fabs(d) + sqrt(d * d + e * e);
-          const double rn = 1.0 / sqrt(den * den + e * e);
+          const double x1 = fma(d, d, e * e);
+          const double den = fabs(d) + x1 * rsqrt_refined(x1);
+          const double rn = rsqrt_refined(fma(den, den, e * e));
           c = den * rn;
           sn = (d >= 0.0 ? e : -e) * rn;
         }
