@@ -1248,6 +1248,9 @@ __device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V,
   if (tid < 64) {
     const double t2 = tiny2[b], tol2 = tol * tol;
     const int pj = lane >> 3, pk = lane & 7;
+    unsigned present = 0;   // bit c: local column c lies inside the matrix
+#pragma unroll
+    for (int cc = 0; cc < BJ_C; ++cc) present |= (gcol(cc) >= 0 ? 1u : 0u) << cc;
     int nrot = 0;
     double ovl = 0.0;   // largest |cos| between two columns this lane rotated
     for (int sw = 0; sw < inner; ++sw) {
@@ -1265,9 +1268,11 @@ __device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V,
         const double g00 = G[p * GS + p2], g01 = G[p * GS + q2], g10 = G[q * GS + p2], g11 = G[q * GS + q2];
         const double r00 = R[p * GS + p2], r01 = R[p * GS + q2], r10 = R[q * GS + p2], r11 = R[q * GS + q2];
         double c = 1.0, sn = 0.0;
-        // the pair test |g01| > tol sqrt(g00 g11) in squares (g00, g11 > t2 keep the product normal)
-        if (pj == pk && gcol(p) >= 0 && gcol(q) >= 0 && fmin(g00, g11) > t2 && g01 != 0.0 &&
-            g01 * g01 > tol2 * (g00 * g11)) {
+        // the pair test |g01| > tol sqrt(g00 g11) in squares (g00, g11 > t2 keep the product
+        // normal), all conditions evaluated without short circuit: one branch
+        const bool rotate = (pj == pk) & (((present >> p) & (present >> q) & 1u) != 0u) & (fmin(g00, g11) > t2) &
+                            (g01 != 0.0) & (g01 * g01 > tol2 * (g00 * g11));
+        if (rotate) {
           // |cos| of the pair, for the stop test only: the hardware reciprocal square root suffices
           ovl = fmax(ovl, fabs(g01) * __builtin_amdgcn_rsq(g00 * g11));
           // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = d / (2 g01), d = g11 - g00,
