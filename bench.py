@@ -32,19 +32,22 @@ METRIC = "CTMRG sweeps/s + E&grad evals/s at D=6,chi=72 (mixed vs FP64), |dE| vs
 # MI355X peaks: dense matrix cores per path, FP64 vector ALU for the Jacobi and QR families
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "jacobi": 78.6, "qr_panel": 78.6}
 BOUND = {"fp64": "mfma", "fp32": "mfma", "bf16": "mfma", "jacobi": "alu", "qr_panel": "alu"}
-# HBM traffic per launch of the Jacobi round kernel from two rocprofv3 --pmc
-# passes over a one-sweep run of this workload (FETCH_SIZE, then WRITE_SIZE, KiB
-# per dispatch), each scaled by what the counter reads for a copy of known size
+# HBM traffic per launch of the Jacobi kernel (one launch runs the whole
+# iteration of one batched SVD) from two rocprofv3 --pmc passes over this
+# workload's sweeps (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged
+# over the 16 dispatches of the event-timed sweep: dispatches 113-128 after the
+# default 2 warm-up and 5 timed sweeps), each scaled by what the counter reads
+# for a copy of known size
 # (bench.py --copy-probe 256: FETCH_SIZE reads half of the bytes copied, so x2;
 # WRITE_SIZE reads them exactly, x1).  Valid for the kernel source it was taken
 # on (hash of the kernel's text), else reported as null.
-TRAFFIC = {"jacobi": {"fetch_kib": 5912.0, "fetch_scale": 2.0, "write_kib": 4634.4, "write_scale": 1.0,
-                      "source_sha256": "444bb97d22d40f4c675e7ed6dab8c2764e7092fbc66fffdce57e2a3997ee3b35",
+TRAFFIC = {"jacobi": {"fetch_kib": 2759505.9, "fetch_scale": 2.0, "write_kib": 4929495.3, "write_scale": 1.0,
+                      "source_sha256": "e05ea28b394c17fd4130431c55999845cfc69bc3510d2fd0410744b26dc47cb2",
                       "source": ("paper_2512_14414_amd/csrc/kernels.hip", "constexpr int BJ_BW = 8;",
                                  "hipError_t launch_bjac_round(")}}
 KERNEL = {"fp64": "contract_kernel<MODE_F64> (FP64 MFMA)", "fp32": "contract_kernel<MODE_F32> (FP32 MFMA)",
           "bf16": "contract_kernel<MODE_BF16> (BF16 MFMA, FP32 accumulation)",
-          "jacobi": "bjac_round_kernel (block one-sided Jacobi round, FP64)",
+          "jacobi": "bjac_svd_kernel (block one-sided Jacobi, all sweeps of one batched SVD per launch, FP64)",
           "qr_panel": "panel_kernel (Householder QR panel, FP64)"}
 
 
@@ -234,7 +237,7 @@ def main():
         "traffic": traffic_per_launch(fam),
         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
         "launches_per_sweep": launches,
-        # event-timed: includes the dispatch gap between back-to-back launches
+        # event-timed on the library's stream (includes the dispatch gap before each launch)
         "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
         "algorithmic_flops_per_sweep": flops,
         "kernel_ms_per_sweep": round(ms, 3),

@@ -490,8 +490,12 @@ void hqr_apply(Dev& dev, const HQR& q, double* C, int64_t crs, int64_t ccs, int6
 // X = R^T are rotated until mutually orthogonal, X W = U_X diag(s), so that
 // A = (Q W) diag(s) U_X^T.  Starting from R^T instead of A cuts the number of
 // Jacobi sweeps about threefold on the graded spectra of CTMRG.  The sweeps
-// are blocked: each launch treats one round of a tournament over blocks of
-// columns, one wave per block pair (see bjac_round_kernel).  Outputs: all
+// are blocked: each round of a tournament over blocks of columns rotates every
+// block pair in one workgroup.  When the device holds the whole grid, one
+// launch runs all rounds and sweeps and takes the stop test itself
+// (bjac_svd_kernel), so the host does not wait for the SVD; otherwise each
+// round is a launch (bjac_round_kernel) and the host tests after each sweep.
+// Both run the same rounds and give identical results.  Outputs: all
 // r singular values, descending, to sv[b]; the kmax leading left vectors to
 // U[b] and right vectors to Vk[b] (column-major r x kmax).  A is overwritten.
 int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double* sv, double* U, double* Vk) {
