@@ -156,7 +156,11 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *                 one launch per round); 0 for one launch per round and the stop
  *                 test on the host.  Both give identical results.  No
  *                 convergence, or a wait between rounds that runs out (waits
- *                 are bounded), fails the call with CTM_ESOLVER when it returns. */
+ *                 are bounded), fails the call with CTM_ESOLVER when it returns.
+ *   "qr_fused_vy" 1 (default) to have the Householder panel kernel write the
+ *                 dense factors of its block reflector for the trailing update
+ *                 itself, 0 for a separate launch; a process-wide switch.  Both
+ *                 give identical results. */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
 /* Live timing of the library's main kernel families.  Between

@@ -416,23 +416,38 @@ struct HQR {
   int64_t tstride() const { return npanel * nb * nb; }
 };
 
+// Whether the panel kernel writes the dense V and Y of its block reflector
+// itself (one launch less per panel); a process-wide switch, the results are
+// identical.
+bool g_qr_fused_vy = true;
+
+// C <- C - V (Y^T C) with the dense V, Y of panel p (L = m - j0 rows of nb per
+// matrix): two FP64 MFMA products.
+void hqr_panel_update(Dev& dev, const HQR& q, int64_t p, double* C, int64_t crs, int64_t ccs, int64_t cstride,
+                      int64_t c0, int64_t ncols, void* V, void* Y) {
+  const int64_t j0 = p * q.nb, L = q.m - j0;
+  const int64_t nb = q.nb, B = q.batch;
+  DBuf Z(&dev, (size_t)B * nb * ncols * 8);
+  TRef Vv{V, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
+  TRef Yv{Y, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
+  TRef Cv{C + j0 * crs + c0 * ccs, T_F64, {B, L, ncols}, {cstride, crs, ccs}, "brn"};
+  TRef Zv{Z.p, T_F64, {B, nb, ncols}, {nb * ncols, ncols, 1}, "bcn"};
+  contract(dev, ctmk::MODE_F64, Zv, Yv, Cv);
+  contract(dev, ctmk::MODE_F64, Cv, Vv, Zv, -1.0, 1);
+}
+
 // C_b[j0:m, c0:c0+ncols] <- H_p^T C_b (trans) or H_p C_b for the block
-// reflector H_p = I - V T V^T of panel p: C <- C - V (Y^T C), two FP64 MFMA products.
+// reflector H_p = I - V T V^T of panel p: C <- C - V (Y^T C).
 void hqr_panel_apply(Dev& dev, const HQR& q, int64_t p, double* C, int64_t crs, int64_t ccs, int64_t cstride,
                      int64_t c0, int64_t ncols, bool trans) {
   const int64_t j0 = p * q.nb, L = q.m - j0;
   const int nbp = (int)std::min<int64_t>(q.nb, q.k - j0);
   if (ncols <= 0 || L <= 0) return;
   const int64_t nb = q.nb, B = q.batch;
-  DBuf V(&dev, (size_t)B * L * nb * 8), Y(&dev, (size_t)B * L * nb * 8), Z(&dev, (size_t)B * nb * ncols * 8);
+  DBuf V(&dev, (size_t)B * L * nb * 8), Y(&dev, (size_t)B * L * nb * 8);
   HIP_CHECK(qrk::launch_build_vy(q.A, q.rs, q.cs, q.stride, q.m, j0, nbp, q.nb, (const double*)q.T.p + p * nb * nb,
                                  q.tstride(), trans, (double*)V.p, (double*)Y.p, q.batch, dev.stream));
-  TRef Vv{V.p, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
-  TRef Yv{Y.p, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
-  TRef Cv{C + j0 * crs + c0 * ccs, T_F64, {B, L, ncols}, {cstride, crs, ccs}, "brn"};
-  TRef Zv{Z.p, T_F64, {B, nb, ncols}, {nb * ncols, ncols, 1}, "bcn"};
-  contract(dev, ctmk::MODE_F64, Zv, Yv, Cv);
-  contract(dev, ctmk::MODE_F64, Cv, Vv, Zv, -1.0, 1);
+  hqr_panel_update(dev, q, p, C, crs, ccs, cstride, c0, ncols, V.p, Y.p);
 }
 
 void hqr_prepare(Dev& dev, HQR& q) {
@@ -448,13 +463,23 @@ void hqr_step(Dev& dev, HQR& q, int64_t p) {
   const int64_t j0 = p * q.nb;
   const int nbp = (int)std::min<int64_t>(q.nb, q.k - j0);
   double* Tp = (double*)q.T.p + p * q.nb * q.nb;
+  const int64_t L = q.m - j0, ncols = q.n - (j0 + nbp);
+  // the trailing update's V and Y, written by the panel kernel itself
+  const bool fused = g_qr_fused_vy && ncols > 0 && L > 0;
+  DBuf V, Y;
+  if (fused) {
+    V = DBuf(&dev, (size_t)q.batch * L * q.nb * 8);
+    Y = DBuf(&dev, (size_t)q.batch * L * q.nb * 8);
+  }
   if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
   HIP_CHECK(qrk::launch_panel(q.A, q.rs, q.cs, q.stride, q.m, q.n, j0, q.batch, (double*)q.tau.p, q.k, Tp,
-                              q.tstride(), dev.stream));
+                              q.tstride(), fused ? (double*)V.p : nullptr, fused ? (double*)Y.p : nullptr,
+                              dev.stream));
   if (g_counters.timing) g_counters.record(dev.stream, FAM_PANEL);
   // Householder panel: about 4 (m - j0) nbp^2 flops per matrix (norms, reflections, T factor)
   g_counters.count(FAM_PANEL, 4.0 * (double)(q.m - j0) * nbp * nbp * q.batch);
-  hqr_panel_apply(dev, q, p, q.A, q.rs, q.cs, q.stride, j0 + nbp, q.n - (j0 + nbp), true);
+  if (fused) hqr_panel_update(dev, q, p, q.A, q.rs, q.cs, q.stride, j0 + nbp, ncols, V.p, Y.p);
+  else hqr_panel_apply(dev, q, p, q.A, q.rs, q.cs, q.stride, j0 + nbp, ncols, true);
 }
 
 void hqr_factor(Dev& dev, HQR& q) {
@@ -1436,6 +1461,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "streams" && (value == 1 || value == 2)) c->streams = (int)value;
   else if (k == "rowmajor_bf16") ctmk::g_rowmajor_path = value != 0;
   else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
+  else if (k == "qr_fused_vy") g_qr_fused_vy = value != 0;
   else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }
   return CTM_OK;
 }

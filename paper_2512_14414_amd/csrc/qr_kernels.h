@@ -10,9 +10,11 @@ int panel_width(int64_t m);
 
 // Factorise the panel of columns j0 .. j0+nb-1 (nb = panel_width(m)) of every
 // matrix; writes tau[b*tau_stride + j] and the nb x nb T of the block
-// reflector (row-major) at T + b*T_stride.
+// reflector (row-major) at T + b*T_stride.  If V is not NULL, also writes V
+// and Y = V T as launch_build_vy does with trans set (Y too must be given).
 hipError_t launch_panel(double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m, int64_t n, int64_t j0, int batch,
-                        double* tau, int64_t tau_stride, double* T, int64_t T_stride, hipStream_t s);
+                        double* tau, int64_t tau_stride, double* T, int64_t T_stride, double* V, double* Y,
+                        hipStream_t s);
 
 // Dense V (L x nb) and Y = V T (trans) or V T^T of the panel at (j0, j0), L = m - j0,
 // both row-major per matrix (stride L*nb), for C <- C - V (Y^T C).

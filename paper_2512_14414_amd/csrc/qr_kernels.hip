@@ -74,10 +74,14 @@ __device__ __forceinline__ double wave_reduce(double* x) {
 // straight-line code once, and the kernel would wait on instruction fetch.
 // Column c of the register panel is read and replaced by select chains over
 // the (unrolled) column index, which keeps the panel in registers.
+// With V and Y given, the kernel also writes the dense factors of the
+// panel's block reflector for the trailing update (what build_vy_kernel
+// writes with trans set: V with its unit diagonal, Y = V T; L = m - j0 rows of
+// NB per matrix, stride L * NB), from the panel still in registers.
 template <int RPT, int NB, int NTT>
 __global__ __launch_bounds__(NTT) void panel_kernel(double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m,
                                                     int64_t n, int64_t j0, double* tau, int64_t tau_stride, double* T,
-                                                    int64_t T_stride) {
+                                                    int64_t T_stride, double* V, double* Y) {
   constexpr int NW = NTT / 64;
   static_assert(NB * NB <= NTT && 64 % NB == 0, "panel shape");
   __shared__ double red[NW];
@@ -206,6 +210,29 @@ __global__ __launch_bounds__(NTT) void panel_kernel(double* A, int64_t rs, int64
     }
     if (i < nbp) tau[(int64_t)b * tau_stride + j0 + i] = taus_s[i];
   }
+  if (V == nullptr) return;
+  __syncthreads();   // every row of Tr
+  const int64_t L = m - j0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = tid + NTT * q;
+    if (r >= L) continue;
+    double v[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[c] = c >= nbp ? 0.0 : (r == c ? 1.0 : (r > c ? a[q][c] : 0.0));
+    double* Vr = V + ((int64_t)b * L + r) * NB;
+    double* Yr = Y + ((int64_t)b * L + r) * NB;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Vr[c] = v[c];
+    // the sums of build_vy_kernel, in its order
+#pragma unroll 1
+    for (int c = 0; c < NB; ++c) {
+      double y = 0.0;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) y += v[l] * Tr[l][c];
+      Yr[c] = y;
+    }
+  }
 }
 
 // Dense factors of a panel's block reflector for the update C <- C - V (Y^T C):
@@ -260,7 +287,8 @@ static int panel_threads(int64_t rows) {
 int panel_width(int64_t m) { return m <= 1024 ? 16 : 8; }
 
 hipError_t launch_panel(double* A, int64_t rs, int64_t cs, int64_t stride, int64_t m, int64_t n, int64_t j0, int batch,
-                        double* tau, int64_t tau_stride, double* T, int64_t T_stride, hipStream_t s) {
+                        double* tau, int64_t tau_stride, double* T, int64_t T_stride, double* V, double* Y,
+                        hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   const int64_t rows = m - j0 > 0 ? m - j0 : 1;
   const int nb = panel_width(m);
@@ -269,13 +297,13 @@ hipError_t launch_panel(double* A, int64_t rs, int64_t cs, int64_t stride, int64
   // rows of the panel: local row r = tid + NTT*q covers m - j0 rows
   if (nb == 16) {
     switch (nt) {
-      case 256: panel_kernel<1, 16, 256><<<batch, 256, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
-      case 512: panel_kernel<1, 16, 512><<<batch, 512, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
-      case 1024: panel_kernel<2, 16, 512><<<batch, 512, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride); break;
+      case 256: panel_kernel<1, 16, 256><<<batch, 256, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride, V, Y); break;
+      case 512: panel_kernel<1, 16, 512><<<batch, 512, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride, V, Y); break;
+      case 1024: panel_kernel<2, 16, 512><<<batch, 512, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride, V, Y); break;
       default: return hipErrorInvalidValue;
     }
   } else {
-    panel_kernel<8, 8, 256><<<batch, 256, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride);
+    panel_kernel<8, 8, 256><<<batch, 256, 0, s>>>(A, rs, cs, stride, m, n, j0, tau, tau_stride, T, T_stride, V, Y);
   }
   return hipGetLastError();
 }

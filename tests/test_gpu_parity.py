@@ -270,6 +270,30 @@ def test_one_launch_jacobi_sweeps_match_per_round_launches(ctm_mod, name, sweeps
     assert torch.equal(envs[0], envs[1])
 
 
+@pytest.mark.parametrize("name", ["ssm_d6_chi72", "heis_d9_chi100"])
+def test_panel_kernel_writing_the_reflector_factors_matches_separate_launch(ctm_mod, name):
+    """The Householder panel kernel writing V and Y = V T of its block
+    reflector itself (the default) and the separate kernel that builds them
+    from the stored panel compute the same sums in the same order, so one sweep
+    gives identical environments (sixteen-column panels at D = 6, eight-column
+    panels of 1800-row half systems at D = 9)."""
+    cfg = synth.CONFIGS[name]
+    A = synth.config_tensors(cfg, 0)
+    envs = []
+    try:
+        for flag in (0, 1):
+            g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+            g.set_option("qr_fused_vy", flag)
+            g.sweep(1)
+            envs.append(g.get_env().cpu())
+            del g
+    finally:
+        g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+        g.set_option("qr_fused_vy", 1)
+        del g
+    assert torch.equal(envs[0], envs[1])
+
+
 def test_rowmajor_bf16_products_match_general_kernel(ctm_mod):
     """The density-matrix joins of the D=6, chi=72 energy in BF16 mode (plain
     row-major products, M = N = 10368, K = 2592) on the dedicated kernel and on
