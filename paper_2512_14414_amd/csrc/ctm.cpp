@@ -420,6 +420,12 @@ struct HQR {
 // itself (one launch less per panel); a process-wide switch, the results are
 // identical.
 bool g_qr_fused_vy = true;
+// Whether a panel's trailing update runs as one launch (panel_update_kernel)
+// instead of two MFMA products with a split sum; a process-wide switch, off by
+// default: the same sums in another order move the FP64 energy gradient at
+// ill-conditioned states by more than the test bar set from the oracle's own
+// spread.
+bool g_qr_one_update = false;
 
 // C <- C - V (Y^T C) with the dense V, Y of panel p (L = m - j0 rows of nb per
 // matrix): two FP64 MFMA products.
@@ -427,6 +433,11 @@ void hqr_panel_update(Dev& dev, const HQR& q, int64_t p, double* C, int64_t crs,
                       int64_t c0, int64_t ncols, void* V, void* Y) {
   const int64_t j0 = p * q.nb, L = q.m - j0;
   const int64_t nb = q.nb, B = q.batch;
+  if (g_qr_one_update) {
+    HIP_CHECK(qrk::launch_panel_update(C + j0 * crs + c0 * ccs, crs, ccs, cstride, L, ncols, q.nb, (const double*)V,
+                                       (const double*)Y, q.batch, dev.stream));
+    return;
+  }
   DBuf Z(&dev, (size_t)B * nb * ncols * 8);
   TRef Vv{V, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
   TRef Yv{Y, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};
@@ -1462,6 +1473,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "rowmajor_bf16") ctmk::g_rowmajor_path = value != 0;
   else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
   else if (k == "qr_fused_vy") g_qr_fused_vy = value != 0;
+  else if (k == "qr_one_update") g_qr_one_update = value != 0;
   else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }
   return CTM_OK;
 }

@@ -22,6 +22,12 @@ hipError_t launch_build_vy(const double* A, int64_t rs, int64_t cs, int64_t stri
                            int nb, const double* T, int64_t T_stride, bool trans, double* V, double* Y, int batch,
                            hipStream_t s);
 
+// C_b[i][j] -= (V (Y^T C_b))[i][j] for i < L, j < ncols in one launch (element
+// (i, j) at C + b*cstride + i*crs + j*ccs; V, Y row-major L x nb per matrix,
+// stride L*nb; nb 16 or 8).
+hipError_t launch_panel_update(double* C, int64_t crs, int64_t ccs, int64_t cstride, int64_t L, int64_t ncols, int nb,
+                               const double* V, const double* Y, int batch, hipStream_t s);
+
 // Column-major n x k L_b = R_b^T (zero above the diagonal) of the factorised A_b.
 hipError_t launch_extract_rt(const double* A, int64_t rs, int64_t cs, int64_t stride, int64_t n, int64_t k, double* L,
                              int64_t lstride, int batch, hipStream_t s);

@@ -273,6 +273,79 @@ __global__ __launch_bounds__(256) void build_vy_kernel(const double* A, int64_t 
   }
 }
 
+// Trailing update with a panel's block reflector in one launch:
+// C_b[i][j] -= sum_c V[i][c] Z[c][j] with Z[c][j] = sum_i Y[i][c] C_b[i][j],
+// i < L, j < ncols (element (i, j) at C + b*cstride + i*crs + j*ccs; V, Y
+// row-major L x NB per matrix, stride L*NB).  A workgroup owns 16 columns of
+// one matrix: its 256 threads form Z for them over 16 row groups, reduce the
+// groups through LDS, then update the columns.  ROWFAST: consecutive threads
+// take consecutive rows (column-major C), else consecutive columns.  Plain
+// FP64 FMAs: the work per column is small (2 L NB flops each way) and the
+// product shapes (NB rows of Z) suit no matrix-core tile.
+template <int NB, bool ROWFAST>
+__global__ __launch_bounds__(256) void panel_update_kernel(double* C, int64_t crs, int64_t ccs, int64_t cstride,
+                                                           int64_t L, int64_t ncols, const double* V, const double* Y) {
+  constexpr int TJ = 16, NT = 256, RG = NT / TJ;
+  __shared__ double part[RG][NB][TJ + 1];
+  __shared__ double Zs[NB][TJ];
+  const int b = blockIdx.y, t = threadIdx.x;
+  const int jl = ROWFAST ? t / RG : t % TJ;
+  const int rg = ROWFAST ? t % RG : t / TJ;
+  const int64_t j = (int64_t)blockIdx.x * TJ + jl;
+  const bool jok = j < ncols;
+  double* Cb = C + (int64_t)b * cstride + (jok ? j : 0) * ccs;
+  const double* Yb = Y + (int64_t)b * L * NB;
+  const double* Vb = V + (int64_t)b * L * NB;
+  double z[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) z[c] = 0.0;
+  if (jok)
+    for (int64_t i = rg; i < L; i += RG) {
+      const double x = Cb[i * crs];
+      const double* yr = Yb + i * NB;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) z[c] += yr[c] * x;
+    }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) part[rg][c][jl] = z[c];
+  __syncthreads();
+  if (t < NB * TJ) {
+    const int c = t / TJ, jj = t % TJ;
+    double sum = 0.0;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) sum += part[g][c][jj];
+    Zs[c][jj] = sum;
+  }
+  __syncthreads();
+  if (!jok) return;
+  double zc[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) zc[c] = Zs[c][jl];
+  for (int64_t i = rg; i < L; i += RG) {
+    const double* vr = Vb + i * NB;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc += vr[c] * zc[c];
+    Cb[i * crs] -= acc;
+  }
+}
+
+hipError_t launch_panel_update(double* C, int64_t crs, int64_t ccs, int64_t cstride, int64_t L, int64_t ncols, int nb,
+                               const double* V, const double* Y, int batch, hipStream_t s) {
+  if (L <= 0 || ncols <= 0 || batch <= 0) return hipSuccess;
+  if (batch > 65535 || (nb != 16 && nb != 8)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)batch);
+  const bool rowfast = crs == 1 && ccs != 1;
+  if (nb == 16) {
+    if (rowfast) panel_update_kernel<16, true><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
+    else panel_update_kernel<16, false><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
+  } else {
+    if (rowfast) panel_update_kernel<8, true><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
+    else panel_update_kernel<8, false><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
+  }
+  return hipGetLastError();
+}
+
 // Panel shapes: RPT rows per thread in a workgroup of NTT threads, one
 // register row per thread up to 1024 rows (more threads rather than more
 // rows per thread: the per-thread panel must stay in registers).
