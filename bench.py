@@ -41,7 +41,8 @@ BOUND = {"fp64": "mfma", "fp32": "mfma", "bf16": "mfma", "jacobi": "alu", "qr_pa
 # (bench.py --copy-probe 256: FETCH_SIZE reads half of the bytes copied, so x2;
 # WRITE_SIZE reads them exactly, x1).  Valid for the kernel source it was taken
 # on (hash of the kernel's text), else reported as null.
-TRAFFIC = {"jacobi": {"fetch_kib": 2759505.9, "fetch_scale": 2.0, "write_kib": 4929495.3, "write_scale": 1.0,
+TRAFFIC = {"jacobi": {"workload": "ssm_d6_chi72", "precision": "bf16",
+                      "fetch_kib": 2759505.9, "fetch_scale": 2.0, "write_kib": 4929495.3, "write_scale": 1.0,
                       "source_sha256": "e05ea28b394c17fd4130431c55999845cfc69bc3510d2fd0410744b26dc47cb2",
                       "source": ("paper_2512_14414_amd/csrc/kernels.hip", "constexpr int BJ_BW = 8;",
                                  "hipError_t launch_bjac_round(")}}
@@ -71,12 +72,13 @@ def workload_name(name, cfg):
             f"D={cfg['D']} chi={cfg['chi']}, {dist} seed 0, normalised; step = 1 CTMRG sweep")
 
 
-def traffic_per_launch(fam):
+def traffic_per_launch(fam, config, precision):
     """HBM bytes per launch of family ``fam`` from the counter runs, or None
-    when none were taken or the kernel's source changed since."""
+    when none were taken for this workload and precision or the kernel's
+    source changed since."""
     import hashlib
     t = TRAFFIC.get(fam)
-    if t is None:
+    if t is None or t["workload"] != config or t["precision"] != precision:
         return None
     path, first, last = t["source"]
     try:
@@ -234,7 +236,7 @@ def main():
         "peak": PEAK_TFLOPS[fam],
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_TFLOPS[fam], 6),
-        "traffic": traffic_per_launch(fam),
+        "traffic": traffic_per_launch(fam, args.config, args.precision),
         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
         "launches_per_sweep": launches,
         # event-timed on the library's stream (includes the dispatch gap before each launch)
