@@ -157,6 +157,9 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *                 test on the host.  Both give identical results.  No
  *                 convergence, or a wait between rounds that runs out (waits
  *                 are bounded), fails the call with CTM_ESOLVER when it returns.
+ *   "jacobi_max_sweeps" the most Jacobi sweeps of one projector SVD (1..1000,
+ *                 default 40); an SVD that needs more fails the call with
+ *                 CTM_ESOLVER.
  *   "qr_fused_vy" 1 (default) to have the Householder panel kernel write the
  *                 dense factors of its block reflector for the trailing update
  *                 itself, 0 for a separate launch; a process-wide switch.  Both

@@ -1010,8 +1010,9 @@ void check_flags(ctm_ctx* c) {
   HIP_CHECK(hipMemcpyAsync(h, c->flag.p, sizeof(h), hipMemcpyDeviceToHost, c->dev.stream));
   HIP_CHECK(hipStreamSynchronize(c->dev.stream));
   HIP_CHECK(hipMemsetAsync(c->flag.p, 0, 2 * sizeof(int), c->dev.stream));
-  if (h[0]) throw Error(CTM_ENONFINITE, "non-finite value in the environment");
+  // a failed solve first: it is the cause of whatever else went wrong after it
   if (h[1]) throw Error(CTM_ESOLVER, "SVD did not converge (" + std::to_string(h[1]) + " failed solves)");
+  if (h[0]) throw Error(CTM_ENONFINITE, "non-finite value in the environment");
 }
 
 // ---------------------------------------------------------------------------
@@ -1472,6 +1473,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "streams" && (value == 1 || value == 2)) c->streams = (int)value;
   else if (k == "rowmajor_bf16") ctmk::g_rowmajor_path = value != 0;
   else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
+  else if (k == "jacobi_max_sweeps" && value >= 1 && value <= 1000) c->jacobi_max_sweeps = (int)value;
   else if (k == "qr_fused_vy") g_qr_fused_vy = value != 0;
   else if (k == "qr_one_update") g_qr_one_update = value != 0;
   else { c->err = "unknown option or bad value: " + k; return CTM_EINVAL; }

@@ -330,6 +330,28 @@ def test_one_launch_panel_update_matches_mfma_products(ctm_mod):
     assert (r1 - r0).abs().max().item() <= 1e-10 * scale
 
 
+@pytest.mark.parametrize("one_launch", [1, 0])
+def test_jacobi_without_convergence_fails_the_call(ctm_mod, one_launch):
+    """An SVD that does not converge within the allowed sweeps fails the call
+    with CTM_ESOLVER, on both Jacobi paths (one launch: the kernel counts the
+    failure on the device and the call reports it when it returns; per round:
+    the host loop raises), and the context stays usable.  One sweep is far too
+    few for the 432 x 432 projector matrices, so the limit is reached while
+    every wave still ends normally."""
+    cfg = synth.CONFIGS["ssm_d6_chi72"]
+    A = synth.config_tensors(cfg, 0)
+    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+    g.set_option("jacobi_one_launch", one_launch)
+    g.set_option("jacobi_max_sweeps", 1)
+    with pytest.raises(ctm_mod.CTMError) as err:
+        g.sweep(1)
+    assert err.value.code == -4
+    g.set_option("jacobi_max_sweeps", 40)
+    g.reset_env()
+    g.sweep(1)
+    assert torch.isfinite(g.get_env()).all()
+
+
 def test_rowmajor_bf16_products_match_general_kernel(ctm_mod):
     """The density-matrix joins of the D=6, chi=72 energy in BF16 mode (plain
     row-major products, M = N = 10368, K = 2592) on the dedicated kernel and on
