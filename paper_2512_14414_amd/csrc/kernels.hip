@@ -472,10 +472,148 @@ static int rowmajor_bf16_variant(const GemmArgs& g) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// Large FP64 products with A contiguous along k and B along n: C[m][n] = alpha
+// sum_k A[m][k] B[k][n] (+ C), e.g. the density-matrix joins and their
+// adjoints in FP64 mode.  A 128 x 128 tile per workgroup, 4 waves of 64 x 64
+// (4 x 4 tiles of v_mfma_f64_16x16x4f64), BK = 16, the next K tile in
+// registers while the matrix cores work.  Operands are read as pairs of
+// doubles and kept in LDS as As[k][m] and Bs[k][n], so that a lane's MFMA
+// operand (A[m = lr][k = lq], B[k = lq][n = lr]) is a read along m or n.  Tile
+// order and line tables as in the BF16 kernel.
+constexpr int GD_BM = 128, GD_BN = 128, GD_BK = 16, GD_LD = GD_BM + 2;
+
+__global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
+  __shared__ __align__(16) double As[GD_BK * GD_LD];
+  __shared__ __align__(16) double Bs[GD_BK * GD_LD];
+  __shared__ int64_t a_line[GD_BM], b_line[GD_BN], c_row[GD_BM], c_col[GD_BN];
+  constexpr int64_t NONE = INT64_MIN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+  const int64_t tiles_m = (g.M + GD_BM - 1) / GD_BM, tiles_n = (g.N + GD_BN - 1) / GD_BN;
+  const int64_t T = tiles_m * tiles_n;
+  const int64_t per_xcd = (T + 7) / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= T) return;
+  constexpr int64_t GROUP = 8;
+  const int64_t in_group = GROUP * tiles_n;
+  const int64_t first_m = (t / in_group) * GROUP;
+  const int64_t gsize = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
+  const int64_t tm = first_m + (t % in_group) % gsize, tn = (t % in_group) / gsize;
+  const int64_t m0 = tm * GD_BM, n0 = tn * GD_BN;
+  const int64_t bz = blockIdx.y;
+  const double* A = (const double*)g.A + bz * g.a_b_i;
+  const double* B = (const double*)g.B + bz * g.b_b_i;
+  double* C = (double*)g.C + bz * g.c_b_i;
+  const int64_t ldb = g.b_k_i;
+  if (tid < GD_BM) {
+    const int64_t m = m0 + tid;
+    a_line[tid] = m < g.M ? split_off(m, g.m_in, g.a_m_o, g.a_m_i) : NONE;
+    c_row[tid] = m < g.M ? split_off(m, g.m_in, g.c_m_o, g.c_m_i) : NONE;
+  } else {
+    const int j = tid - GD_BM;
+    const int64_t n = n0 + j;
+    b_line[j] = n < g.N ? split_off(n, g.n_in, g.b_n_o, g.b_n_i) : NONE;
+    c_col[j] = n < g.N ? split_off(n, g.n_in, g.c_n_o, g.c_n_i) : NONE;
+  }
+  __syncthreads();
+  // A: thread -> lines a_r + 32 i (i < 4), k pair 2 (tid % 8); B: thread -> columns
+  // pair 2 (tid % 64), k rows b_k + 4 j (j < 4).  Pairs never straddle an index
+  // group or the end (even extents and strides, checked on the host).
+  const int a_r = tid >> 3, a_k = (tid & 7) * 2;
+  const int b_n = (tid & 63) * 2, b_k = tid >> 6;
+  double2 ra[4], rb[4];
+  // out-of-range pairs read the operand's first pair (always valid) and are zeroed after the load
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t lo = a_line[a_r + 32 * i], k = k0 + a_k;
+      const bool ok = lo != NONE && k < g.K;
+      const double2 v = *(const double2*)(A + (ok ? lo + k : 0));
+      ra[i] = ok ? v : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t lo = b_line[b_n], k = k0 + b_k + 4 * j;
+      const bool ok = lo != NONE && k < g.K;
+      const double2 v = *(const double2*)(B + (ok ? k * ldb + lo : 0));
+      rb[j] = ok ? v : make_double2(0.0, 0.0);
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      As[a_k * GD_LD + a_r + 32 * i] = ra[i].x;
+      As[(a_k + 1) * GD_LD + a_r + 32 * i] = ra[i].y;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(double2*)&Bs[(b_k + 4 * j) * GD_LD + b_n] = rb[j];
+  };
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  d4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int64_t k0 = 0; k0 < g.K; k0 += GD_BK) {
+    stash();
+    __syncthreads();
+    if (k0 + GD_BK < g.K) load(k0 + GD_BK);
+#pragma unroll
+    for (int kk = 0; kk < GD_BK / 4; ++kk) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[(4 * kk + lq) * GD_LD + wm + 16 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = Bs[(4 * kk + lq) * GD_LD + wn + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of v_mfma_f64_16x16x4f64: register e of lane (lr, lq) is row lq + 4 e, column lr
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t co = c_col[wn + 16 * j + lr];
+      if (co == NONE) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t ro = c_row[wm + 16 * i + lq + 4 * e];
+        if (ro == NONE) continue;
+        double v = g.alpha * acc[i][j][e];
+        if (g.beta) v += C[ro + co];
+        C[ro + co] = v;
+      }
+    }
+}
+
+// The FP64 products that take the kernel above: one level for k, A contiguous
+// along k and B along n with every pair of doubles 16-byte aligned inside one
+// index group, any layout of C, no column scale or K split, large enough.
+static bool rowmajor_f64_ok(const GemmArgs& g) {
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  return g.k_in == g.K && (g.batch == 1 || g.b_in == g.batch) && !g.colscale && g.ksplit <= 1 && g.a_b_i % 2 == 0 &&
+         g.b_b_i % 2 == 0 && al16(g.A) && al16(g.B) && g.M >= 512 && g.N >= 512 && g.K >= 64 && g.K % 2 == 0 &&
+         g.a_k_i == 1 && g.a_m_i % 2 == 0 && (g.m_in == g.M || g.a_m_o % 2 == 0) && g.b_n_i == 1 &&
+         g.b_k_i % 2 == 0 && g.n_in % 2 == 0 && (g.n_in == g.N || g.b_n_o % 2 == 0) && g.N % 2 == 0;
+}
+
 bool g_rowmajor_path = true;
+bool g_rowmajor_f64 = true;
 
 hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (mode == MODE_F64 && g_rowmajor_f64 && rowmajor_f64_ok(g)) {
+    const int64_t T = ((g.M + GD_BM - 1) / GD_BM) * ((g.N + GD_BN - 1) / GD_BN);
+    const int64_t blocks = 8 * ((T + 7) / 8);
+    if (blocks > 2147483647LL || g.batch > 65535) return hipErrorInvalidValue;
+    gemm_f64_rowmajor_kernel<<<dim3((unsigned)blocks, (unsigned)g.batch), 256, 0, s>>>(g);
+    return hipGetLastError();
+  }
   const int v = mode == MODE_BF16 && g_rowmajor_path ? rowmajor_bf16_variant(g) : -1;
   if (v >= 0) {
     const int64_t T = ((g.M + GB_BM - 1) / GB_BM) * ((g.N + GB_BN - 1) / GB_BN);
