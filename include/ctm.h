@@ -150,9 +150,10 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *   "rowmajor_bf16" 1 (default) to run large BF16-mode products of plain
  *                 row-major operands on the dedicated 128 x 128-tile kernel, 0
  *                 for the general contraction kernel; a process-wide switch.
- *   "rowmajor_f64" 1 (default) to run large FP64 products with A contiguous
- *                 along k and B along n on the dedicated 128 x 128-tile kernel,
- *                 0 for the general contraction kernel; a process-wide switch.
+ *   "rowmajor_f64", "rowmajor_f32" 1 (default) to run large FP64 (FP32-mode)
+ *                 products with A contiguous along k and B along n on the
+ *                 dedicated 128 x 128-tile kernel, 0 for the general contraction
+ *                 kernel; process-wide switches.
  *   "jacobi_one_launch" 1 (default) to run the whole Jacobi iteration of the
  *                 projector SVD (all sweeps, the stop test taken on the device)
  *                 in one launch, when the device holds its grid at once (else

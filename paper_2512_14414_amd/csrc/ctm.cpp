@@ -1473,6 +1473,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "streams" && (value == 1 || value == 2)) c->streams = (int)value;
   else if (k == "rowmajor_bf16") ctmk::g_rowmajor_path = value != 0;
   else if (k == "rowmajor_f64") ctmk::g_rowmajor_f64 = value != 0;
+  else if (k == "rowmajor_f32") ctmk::g_rowmajor_f32 = value != 0;
   else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
   else if (k == "jacobi_max_sweeps" && value >= 1 && value <= 1000) c->jacobi_max_sweeps = (int)value;
   else if (k == "qr_fused_vy") g_qr_fused_vy = value != 0;

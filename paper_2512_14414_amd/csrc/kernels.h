@@ -56,9 +56,10 @@ struct EnergyTerm {
 // Large BF16 products of plain row-major operands take a dedicated kernel
 // (gemm_bf16_rowmajor_kernel) unless this process-wide switch is off.
 extern bool g_rowmajor_path;
-// FP64 products with A contiguous along k and B along n, M, N >= 512, on a
-// dedicated 128 x 128-tile kernel (else the general one); process-wide.
+// FP64 (FP32) products with A contiguous along k and B along n, M, N >= 512,
+// on a dedicated 128 x 128-tile kernel (else the general one); process-wide.
 extern bool g_rowmajor_f64;
+extern bool g_rowmajor_f32;
 hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s);
 hipError_t launch_permute(const PermArgs& p, int in_type, const void* in, int out_type, void* out, hipStream_t s);
 hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s);

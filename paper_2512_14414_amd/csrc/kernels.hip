@@ -473,27 +473,31 @@ static int rowmajor_bf16_variant(const GemmArgs& g) {
 }
 
 // ---------------------------------------------------------------------------
-// Large FP64 products with A contiguous along k and B along n: C[m][n] = alpha
-// sum_k A[m][k] B[k][n] (+ C), e.g. the density-matrix joins and their
-// adjoints in FP64 mode.  A 128 x 128 tile per workgroup, 4 waves of 64 x 64
-// (4 x 4 tiles of v_mfma_f64_16x16x4f64), BK = 16, the next K tile in
-// registers while the matrix cores work.  Operands are read as pairs of
-// doubles and kept in LDS as As[k][m] and Bs[k][n], so that a lane's MFMA
-// operand (A[m = lr][k = lq], B[k = lq][n = lr]) is a read along m or n.  Tile
-// order and line tables as in the BF16 kernel.
+// Large FP64 or FP32 products with A contiguous along k and B along n: C[m][n]
+// = alpha sum_k A[m][k] B[k][n] (+ C), e.g. the density-matrix joins and their
+// adjoints in FP64 and FP32 mode.  A 128 x 128 tile per workgroup, 4 waves of
+// 64 x 64 (4 x 4 tiles of v_mfma_f64_16x16x4f64 or v_mfma_f32_16x16x4f32),
+// BK = 16, the next K tile in registers while the matrix cores work.  Operands
+// are read as pairs and kept in LDS as As[k][m] and Bs[k][n], so that a lane's
+// MFMA operand (A[m = lr][k = lq], B[k = lq][n = lr]) is a read along m or n.
+// Tile order and line tables as in the BF16 kernel.
 constexpr int GD_BM = 128, GD_BN = 128, GD_BK = 16, GD_LD = GD_BM + 2;
 
-__global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
-  __shared__ __align__(16) double As[GD_BK * GD_LD];
-  __shared__ __align__(16) double Bs[GD_BK * GD_LD];
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_mfma_rowmajor_kernel(GemmArgs g) {
+  constexpr bool F64 = std::is_same<T, double>::value;
+  typedef typename std::conditional<F64, double2, float2>::type pair_t;
+  typedef typename std::conditional<F64, d4_t, f4_t>::type acc_t;
+  __shared__ __align__(16) T As[GD_BK * GD_LD];
+  __shared__ __align__(16) T Bs[GD_BK * GD_LD];
   __shared__ int64_t a_line[GD_BM], b_line[GD_BN], c_row[GD_BM], c_col[GD_BN];
   constexpr int64_t NONE = INT64_MIN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
   const int64_t tiles_m = (g.M + GD_BM - 1) / GD_BM, tiles_n = (g.N + GD_BN - 1) / GD_BN;
-  const int64_t T = tiles_m * tiles_n;
-  const int64_t per_xcd = (T + 7) / 8;
+  const int64_t Tt = tiles_m * tiles_n;
+  const int64_t per_xcd = (Tt + 7) / 8;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (t >= T) return;
+  if (t >= Tt) return;
   constexpr int64_t GROUP = 8;
   const int64_t in_group = GROUP * tiles_n;
   const int64_t first_m = (t / in_group) * GROUP;
@@ -501,9 +505,9 @@ __global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
   const int64_t tm = first_m + (t % in_group) % gsize, tn = (t % in_group) / gsize;
   const int64_t m0 = tm * GD_BM, n0 = tn * GD_BN;
   const int64_t bz = blockIdx.y;
-  const double* A = (const double*)g.A + bz * g.a_b_i;
-  const double* B = (const double*)g.B + bz * g.b_b_i;
-  double* C = (double*)g.C + bz * g.c_b_i;
+  const T* A = (const T*)g.A + bz * g.a_b_i;
+  const T* B = (const T*)g.B + bz * g.b_b_i;
+  T* C = (T*)g.C + bz * g.c_b_i;
   const int64_t ldb = g.b_k_i;
   if (tid < GD_BM) {
     const int64_t m = m0 + tid;
@@ -521,22 +525,35 @@ __global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
   // group or the end (even extents and strides, checked on the host).
   const int a_r = tid >> 3, a_k = (tid & 7) * 2;
   const int b_n = (tid & 63) * 2, b_k = tid >> 6;
-  double2 ra[4], rb[4];
-  // out-of-range pairs read the operand's first pair (always valid) and are zeroed after the load
+  pair_t ra[4], rb[4];
+  // A line past the edge of the tile reads the operand's first pair instead
+  // (always valid), which only reaches outputs that are not written.  FP32: K
+  // is a multiple of BK, so every k read lies inside the sum.  FP64: pairs
+  // past K are zeroed (written this way, the FP64 instance keeps its operands
+  // in registers; without the select it spilled and ran at 25 instead of 41
+  // TFLOP/s).
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t lo = a_line[a_r + 32 * i], k = k0 + a_k;
-      const bool ok = lo != NONE && k < g.K;
-      const double2 v = *(const double2*)(A + (ok ? lo + k : 0));
-      ra[i] = ok ? v : make_double2(0.0, 0.0);
+      if constexpr (F64) {
+        const bool ok = lo != NONE && k < g.K;
+        const double2 v = *(const double2*)(A + (ok ? lo + k : 0));
+        ra[i] = ok ? v : make_double2(0.0, 0.0);
+      } else {
+        ra[i] = *(const pair_t*)(A + (lo != NONE ? lo + k : 0));
+      }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t lo = b_line[b_n], k = k0 + b_k + 4 * j;
-      const bool ok = lo != NONE && k < g.K;
-      const double2 v = *(const double2*)(B + (ok ? k * ldb + lo : 0));
-      rb[j] = ok ? v : make_double2(0.0, 0.0);
+      if constexpr (F64) {
+        const bool ok = lo != NONE && k < g.K;
+        const double2 v = *(const double2*)(B + (ok ? k * ldb + lo : 0));
+        rb[j] = ok ? v : make_double2(0.0, 0.0);
+      } else {
+        rb[j] = *(const pair_t*)(B + (lo != NONE ? k * ldb + lo : 0));
+      }
     }
   };
   auto stash = [&]() {
@@ -546,14 +563,14 @@ __global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
       As[(a_k + 1) * GD_LD + a_r + 32 * i] = ra[i].y;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) *(double2*)&Bs[(b_k + 4 * j) * GD_LD + b_n] = rb[j];
+    for (int j = 0; j < 4; ++j) *(pair_t*)&Bs[(b_k + 4 * j) * GD_LD + b_n] = rb[j];
   };
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  d4_t acc[4][4];
+  acc_t acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{(T)0, (T)0, (T)0, (T)0};
   load(0);
   for (int64_t k0 = 0; k0 < g.K; k0 += GD_BK) {
     stash();
@@ -561,7 +578,7 @@ __global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
     if (k0 + GD_BK < g.K) load(k0 + GD_BK);
 #pragma unroll
     for (int kk = 0; kk < GD_BK / 4; ++kk) {
-      double af[4], bf[4];
+      T af[4], bf[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) af[i] = As[(4 * kk + lq) * GD_LD + wm + 16 * i + lr];
 #pragma unroll
@@ -569,11 +586,14 @@ __global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          if constexpr (F64) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          else acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
-  // D layout of v_mfma_f64_16x16x4f64: register e of lane (lr, lq) is row lq + 4 e, column lr
+  // D layout, register e of lane (lr, lq): column lr, row lq + 4 e (FP64) or 4 lq + e (FP32)
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -582,36 +602,42 @@ __global__ __launch_bounds__(256) void gemm_f64_rowmajor_kernel(GemmArgs g) {
       if (co == NONE) continue;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t ro = c_row[wm + 16 * i + lq + 4 * e];
+        const int64_t ro = c_row[wm + 16 * i + (F64 ? lq + 4 * e : 4 * lq + e)];
         if (ro == NONE) continue;
-        double v = g.alpha * acc[i][j][e];
+        T v = (T)(g.alpha * (double)acc[i][j][e]);
         if (g.beta) v += C[ro + co];
         C[ro + co] = v;
       }
     }
 }
 
-// The FP64 products that take the kernel above: one level for k, A contiguous
-// along k and B along n with every pair of doubles 16-byte aligned inside one
-// index group, any layout of C, no column scale or K split, large enough.
-static bool rowmajor_f64_ok(const GemmArgs& g) {
+// The FP64 / FP32 products that take the kernel above: one level for k (even;
+// for FP32 a multiple of BK), A contiguous along k and B along n with every pair aligned
+// inside one index group, any layout of C, no column scale or K split, large
+// enough.
+static bool rowmajor_mfma_ok(const GemmArgs& g, bool f64) {
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   return g.k_in == g.K && (g.batch == 1 || g.b_in == g.batch) && !g.colscale && g.ksplit <= 1 && g.a_b_i % 2 == 0 &&
-         g.b_b_i % 2 == 0 && al16(g.A) && al16(g.B) && g.M >= 512 && g.N >= 512 && g.K >= 64 && g.K % 2 == 0 &&
+         g.b_b_i % 2 == 0 && al16(g.A) && al16(g.B) && g.M >= 512 && g.N >= 512 && g.K >= 64 &&
+         g.K % (f64 ? 2 : GD_BK) == 0 &&
          g.a_k_i == 1 && g.a_m_i % 2 == 0 && (g.m_in == g.M || g.a_m_o % 2 == 0) && g.b_n_i == 1 &&
          g.b_k_i % 2 == 0 && g.n_in % 2 == 0 && (g.n_in == g.N || g.b_n_o % 2 == 0) && g.N % 2 == 0;
 }
 
 bool g_rowmajor_path = true;
 bool g_rowmajor_f64 = true;
+bool g_rowmajor_f32 = true;
 
 hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (mode == MODE_F64 && g_rowmajor_f64 && rowmajor_f64_ok(g)) {
+  const bool mf64 = mode == MODE_F64 && g_rowmajor_f64, mf32 = mode == MODE_F32 && g_rowmajor_f32;
+  if ((mf64 || mf32) && rowmajor_mfma_ok(g, mf64)) {
     const int64_t T = ((g.M + GD_BM - 1) / GD_BM) * ((g.N + GD_BN - 1) / GD_BN);
     const int64_t blocks = 8 * ((T + 7) / 8);
     if (blocks > 2147483647LL || g.batch > 65535) return hipErrorInvalidValue;
-    gemm_f64_rowmajor_kernel<<<dim3((unsigned)blocks, (unsigned)g.batch), 256, 0, s>>>(g);
+    const dim3 grid((unsigned)blocks, (unsigned)g.batch);
+    if (mf64) gemm_mfma_rowmajor_kernel<double><<<grid, 256, 0, s>>>(g);
+    else gemm_mfma_rowmajor_kernel<float><<<grid, 256, 0, s>>>(g);
     return hipGetLastError();
   }
   const int v = mode == MODE_BF16 && g_rowmajor_path ? rowmajor_bf16_variant(g) : -1;

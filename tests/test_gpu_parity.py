@@ -377,6 +377,31 @@ def test_rowmajor_f64_products_match_general_kernel(ctm_mod):
     assert (r1 - r0).abs().max().item() <= 1e-12 * scale
 
 
+def test_rowmajor_f32_products_match_general_kernel(ctm_mod):
+    """FP32 mode, D = 6, chi = 72 shape: the density-matrix joins on the
+    dedicated kernel and on the general one, the same FP32 products summed in
+    another order: RDMs to FP32 accumulation error (1e-5 of their largest
+    entry), energies to 1e-6."""
+    cfg = synth.CONFIGS["ssm_d6_chi72"]
+    A = synth.near_product_tensors(cfg["n_tensors"], 2, cfg["D"], 5, 0.3)
+    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"], precision="fp32")
+    g.sweep(2)
+    terms = synth.config_terms(cfg)
+    out = []
+    try:
+        for flag in (1, 0):
+            g.set_option("rowmajor_f32", flag)
+            E = g.energy(H, terms)
+            out.append((E, torch.as_tensor(g.last_rdms()).clone()))
+    finally:
+        g.set_option("rowmajor_f32", 1)
+    (E1, r1), (E0, r0) = out
+    scale = r0.abs().max().item()
+    print(f"rowmajor f32 vs general: |dE| {abs(E1 - E0):.2e}, max |d rho| {(r1 - r0).abs().max().item():.2e} of {scale:.2e}")
+    assert abs(E1 - E0) < 1e-6
+    assert (r1 - r0).abs().max().item() <= 1e-5 * scale
+
+
 def test_rowmajor_bf16_products_match_general_kernel(ctm_mod):
     """The density-matrix joins of the D=6, chi=72 energy in BF16 mode (plain
     row-major products, M = N = 10368, K = 2592) on the dedicated kernel and on
