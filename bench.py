@@ -11,7 +11,8 @@ A step is one CTMRG sweep (left, right, up and down moves: 64 projector
 computations and the environment updates); ``value`` is sweeps per second.
 The same line reports: the energy+gradient evaluations per second (energy
 after one differentiated sweep from the current environment, and its
-gradient by the hand-written reverse pass), the same in FP64 mode, the
+gradient by the hand-written reverse pass), the same in FP64 and in FP32 mode
+(the mode whose gradient is accurate enough to optimise with), the
 mixed-precision error of E and dE/dA against FP64 mode (on a weakly
 entangled state of the same shape, from one shared environment), the roofline of the kernel family that dominates a sweep
 (timed live with HIP events on the library's stream), and the CPU oracle
@@ -182,7 +183,10 @@ def main():
     env_shared = g.get_env()
     g64 = ctm.CTM(A, cfg["pattern"], chi, precision="fp64")
     if not args.no_egrad:
-        for label, ctx in ((args.precision, g), ("fp64", g64)):
+        # FP32 mode too: the mode whose gradient is usable (the BF16 one is not)
+        g32 = ctm.CTM(A, cfg["pattern"], chi, precision="fp32") if args.precision not in ("fp32", "fp64") else None
+        runs = [(args.precision, g), ("fp64", g64)] + ([("fp32", g32)] if g32 is not None else [])
+        for label, ctx in runs:
             ctx.set_env(env_shared)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -190,6 +194,8 @@ def main():
             torch.cuda.synchronize()
             egrad[label] = time.perf_counter() - t0
             log(f"[bench] E&grad {label}: {egrad[label]:.2f} s")
+        if g32 is not None:
+            g32.close()
     fp64_sweeps_per_s = None
     if args.precision != "fp64" and args.fp64_steps > 0:
         g64.set_env(env_shared)
@@ -263,6 +269,7 @@ def main():
 
     eg = egrad.get(args.precision)
     e64 = egrad.get("fp64")
+    e32 = egrad.get("fp32")
     out = {
         "metric": METRIC,
         "value": round(sweeps_per_s, 4),
@@ -286,6 +293,7 @@ def main():
             for k, v in prof_energy.items() if v[2] > 0},
         "egrad_per_s": None if eg is None else round(1.0 / eg, 4),
         "egrad_per_s_fp64": None if e64 is None else round(1.0 / e64, 4),
+        "egrad_per_s_fp32": None if e32 is None else round(1.0 / e32, 4),
         "egrad_sweeps": args.egrad_sweeps,
         "egrad_speedup_vs_fp64": None if (eg is None or e64 is None) else round(e64 / eg, 3),
         "mixed_vs_fp64": accuracy,
