@@ -168,10 +168,12 @@ int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
  *                 dense factors of its block reflector for the trailing update
  *                 itself, 0 for a separate launch; a process-wide switch.  Both
  *                 give identical results.
- *   "qr_one_update" 1 to run each panel's trailing update of the Householder
- *                 QR as one launch (FP64 FMAs, 16 columns per workgroup) instead
- *                 of two matrix-core products with a split sum (0, default); a
- *                 process-wide switch.  Same arithmetic summed in another order. */
+ *   "qr_one_update" 1 (default) to run each panel's trailing update of the
+ *                 Householder QR as one launch (16 columns per workgroup), 0
+ *                 for two matrix-core products with a split sum; a
+ *                 process-wide switch.  Both give identical results: the one
+ *                 launch repeats the products' MFMA chains, K split and order
+ *                 of partial sums. */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
 /* Live timing of the library's main kernel families.  Between

@@ -420,12 +420,10 @@ struct HQR {
 // itself (one launch less per panel); a process-wide switch, the results are
 // identical.
 bool g_qr_fused_vy = true;
-// Whether a panel's trailing update runs as one launch (panel_update_kernel)
-// instead of two MFMA products with a split sum; a process-wide switch, off by
-// default: the same sums in another order move the FP64 energy gradient at
-// ill-conditioned states by more than the test bar set from the oracle's own
-// spread.
-bool g_qr_one_update = false;
+// Whether a panel's trailing update runs as one launch
+// (panel_update_mfma_kernel, the same arithmetic element for element) instead
+// of the two matrix-core products with a split sum; a process-wide switch.
+bool g_qr_one_update = true;
 
 // C <- C - V (Y^T C) with the dense V, Y of panel p (L = m - j0 rows of nb per
 // matrix): two FP64 MFMA products.
@@ -434,9 +432,29 @@ void hqr_panel_update(Dev& dev, const HQR& q, int64_t p, double* C, int64_t crs,
   const int64_t j0 = p * q.nb, L = q.m - j0;
   const int64_t nb = q.nb, B = q.batch;
   if (g_qr_one_update) {
-    HIP_CHECK(qrk::launch_panel_update(C + j0 * crs + c0 * ccs, crs, ccs, cstride, L, ncols, q.nb, (const double*)V,
-                                       (const double*)Y, q.batch, dev.stream));
-    return;
+    // the split over K that the contraction planner takes for Z = Y^T C (nb x
+    // ncols outputs per matrix, K = L), so that the sums are the same
+    const int64_t tiles = ((nb + 63) / 64) * ((ncols + 63) / 64) * B;
+    int64_t kchunk = L, ksplit = 1;
+    if (tiles < 128 && L >= 256) {
+      const int64_t want = std::min<int64_t>((512 + tiles - 1) / tiles, L / 128);
+      if (want > 1) {
+        kchunk = ((L + want - 1) / want + 31) / 32 * 32;
+        ksplit = (L + kchunk - 1) / kchunk;
+      }
+    }
+    if (ksplit <= qrk::panel_update_max_split()) {
+      // booked with the FP64 contractions it stands for (two products of 2 L nb ncols flops)
+      g_counters.launches++;
+      g_counters.flops += 4.0 * (double)L * nb * ncols * B;
+      g_counters.count(ctmk::MODE_F64, 4.0 * (double)L * nb * ncols * B);
+      if (g_counters.timing) g_counters.record(dev.stream, ctmk::MODE_F64);
+      HIP_CHECK(qrk::launch_panel_update_mfma(C + j0 * crs + c0 * ccs, crs, ccs, cstride, L, ncols, q.nb,
+                                              (const double*)V, (const double*)Y, q.batch, kchunk, (int)ksplit,
+                                              dev.stream));
+      if (g_counters.timing) g_counters.record(dev.stream, ctmk::MODE_F64);
+      return;
+    }
   }
   DBuf Z(&dev, (size_t)B * nb * ncols * 8);
   TRef Vv{V, T_F64, {B, L, nb}, {L * nb, nb, 1}, "brc"};

@@ -24,9 +24,15 @@ hipError_t launch_build_vy(const double* A, int64_t rs, int64_t cs, int64_t stri
 
 // C_b[i][j] -= (V (Y^T C_b))[i][j] for i < L, j < ncols in one launch (element
 // (i, j) at C + b*cstride + i*crs + j*ccs; V, Y row-major L x nb per matrix,
-// stride L*nb; nb 16 or 8).
-hipError_t launch_panel_update(double* C, int64_t crs, int64_t ccs, int64_t cstride, int64_t L, int64_t ncols, int nb,
-                               const double* V, const double* Y, int batch, hipStream_t s);
+// stride L*nb; nb 16 or 8) with, element for element, the arithmetic of the
+// two matrix-core products it replaces: Z = Y^T C split over K in
+// ksplit chunks of kchunk rows (ksplit <= 1: no split) as the contraction
+// planner splits it, then C <- (-(V Z)) + C.  ksplit at most
+// panel_update_max_split(), kchunk a multiple of 4.
+hipError_t launch_panel_update_mfma(double* C, int64_t crs, int64_t ccs, int64_t cstride, int64_t L, int64_t ncols,
+                                    int nb, const double* V, const double* Y, int batch, int64_t kchunk, int ksplit,
+                                    hipStream_t s);
+int panel_update_max_split();
 
 // Column-major n x k L_b = R_b^T (zero above the diagonal) of the factorised A_b.
 hipError_t launch_extract_rt(const double* A, int64_t rs, int64_t cs, int64_t stride, int64_t n, int64_t k, double* L,

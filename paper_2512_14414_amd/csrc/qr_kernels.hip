@@ -273,78 +273,101 @@ __global__ __launch_bounds__(256) void build_vy_kernel(const double* A, int64_t 
   }
 }
 
-// Trailing update with a panel's block reflector in one launch:
-// C_b[i][j] -= sum_c V[i][c] Z[c][j] with Z[c][j] = sum_i Y[i][c] C_b[i][j],
-// i < L, j < ncols (element (i, j) at C + b*cstride + i*crs + j*ccs; V, Y
-// row-major L x NB per matrix, stride L*NB).  A workgroup owns 16 columns of
-// one matrix: its 256 threads form Z for them over 16 row groups, reduce the
-// groups through LDS, then update the columns.  ROWFAST: consecutive threads
-// take consecutive rows (column-major C), else consecutive columns.  Plain
-// FP64 FMAs: the work per column is small (2 L NB flops each way) and the
-// product shapes (NB rows of Z) suit no matrix-core tile.
-template <int NB, bool ROWFAST>
-__global__ __launch_bounds__(256) void panel_update_kernel(double* C, int64_t crs, int64_t ccs, int64_t cstride,
-                                                           int64_t L, int64_t ncols, const double* V, const double* Y) {
-  constexpr int TJ = 16, NT = 256, RG = NT / TJ;
-  __shared__ double part[RG][NB][TJ + 1];
-  __shared__ double Zs[NB][TJ];
-  const int b = blockIdx.y, t = threadIdx.x;
-  const int jl = ROWFAST ? t / RG : t % TJ;
-  const int rg = ROWFAST ? t % RG : t / TJ;
-  const int64_t j = (int64_t)blockIdx.x * TJ + jl;
+// Trailing update with a panel's block reflector in one launch,
+// C_b[i][j] -= (V (Y^T C_b))[i][j] for i < L, j < ncols (element (i, j) at
+// C + b*cstride + i*crs + j*ccs; V, Y row-major L x NB per matrix, stride
+// L*NB), with the arithmetic of the two matrix-core products it replaces,
+// element for element: Z = Y^T C as MFMA chains over
+// k in groups of four from each chunk start (chunks of kchunk rows when
+// ksplit > 1, summed in order from 0.0 as the split-K reduction does), then
+// C <- (-(V Z)) + C with the chain over the NB columns of V.  A workgroup of
+// 512 threads owns 16 columns of one matrix: its 8 waves take the chunks in
+// turn, their partials meet in LDS, then the waves take 16-row tiles of the
+// update.  The 16 x 16 MFMA tiles follow v_mfma_f64_16x16x4f64: operand
+// lane (lr, lq) holds A[m = lr][k = lq] and B[k = lq][n = lr]; result register
+// e is row lq + 4 e, column lr.
+constexpr int PU_MAX_SPLIT = 32;
+template <int NB>
+__global__ __launch_bounds__(512) void panel_update_mfma_kernel(double* C, int64_t crs, int64_t ccs, int64_t cstride,
+                                                                int64_t L, int64_t ncols, const double* V,
+                                                                const double* Y, int64_t kchunk, int ksplit) {
+  typedef double d4_t __attribute__((ext_vector_type(4)));
+  constexpr int NW = 8;
+  __shared__ double part[PU_MAX_SPLIT][16][16];
+  __shared__ double Zs[16][17];
+  const int b = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+  const int64_t j0 = (int64_t)blockIdx.x * 16;
+  const int64_t j = j0 + lr;
   const bool jok = j < ncols;
-  double* Cb = C + (int64_t)b * cstride + (jok ? j : 0) * ccs;
+  double* Cb = C + (int64_t)b * cstride;
   const double* Yb = Y + (int64_t)b * L * NB;
   const double* Vb = V + (int64_t)b * L * NB;
-  double z[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) z[c] = 0.0;
-  if (jok)
-    for (int64_t i = rg; i < L; i += RG) {
-      const double x = Cb[i * crs];
-      const double* yr = Yb + i * NB;
-#pragma unroll
-      for (int c = 0; c < NB; ++c) z[c] += yr[c] * x;
+  const int nsplit = ksplit > 1 ? ksplit : 1;
+  const int64_t chunk = ksplit > 1 ? kchunk : L;
+  // ---- partial Z of each chunk: rows c of Z are A's rows (Y^T), columns the workgroup's
+  for (int sp = wave; sp < nsplit; sp += NW) {
+    const int64_t kbeg = (int64_t)sp * chunk, kend = kbeg + chunk < L ? kbeg + chunk : L;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 4) {
+      const int64_t k = k0 + lq;
+      const bool kok = k < kend;
+      const double a = (kok && lr < NB) ? Yb[k * NB + lr] : 0.0;
+      const double x = (kok && jok) ? Cb[k * crs + j * ccs] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x, acc, 0, 0, 0);
     }
 #pragma unroll
-  for (int c = 0; c < NB; ++c) part[rg][c][jl] = z[c];
-  __syncthreads();
-  if (t < NB * TJ) {
-    const int c = t / TJ, jj = t % TJ;
-    double sum = 0.0;
-#pragma unroll
-    for (int g = 0; g < RG; ++g) sum += part[g][c][jj];
-    Zs[c][jj] = sum;
+    for (int e = 0; e < 4; ++e) part[sp][lq + 4 * e][lr] = acc[e];
   }
   __syncthreads();
-  if (!jok) return;
-  double zc[NB];
+  if (tid < 256) {
+    const int c = tid >> 4, n = tid & 15;
+    double z;
+    if (ksplit > 1) {
+      z = 0.0;
+      for (int sp = 0; sp < nsplit; ++sp) z += part[sp][c][n];
+    } else {
+      z = part[0][c][n];
+    }
+    Zs[c][n] = z;
+  }
+  __syncthreads();
+  // ---- C <- (-(V Z)) + C over 16-row tiles
+  const int64_t rtiles = (L + 15) / 16;
+  for (int64_t rt = wave; rt < rtiles; rt += NW) {
+    const int64_t r0 = rt * 16;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int c = 0; c < NB; ++c) zc[c] = Zs[c][jl];
-  for (int64_t i = rg; i < L; i += RG) {
-    const double* vr = Vb + i * NB;
-    double acc = 0.0;
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+      const int64_t r = r0 + lr;
+      const double a = r < L ? Vb[r * NB + k0 + lq] : 0.0;
+      const double z = Zs[k0 + lq][lr];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z, acc, 0, 0, 0);
+    }
+    if (!jok) continue;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) acc += vr[c] * zc[c];
-    Cb[i * crs] -= acc;
+    for (int e = 0; e < 4; ++e) {
+      const int64_t r = r0 + lq + 4 * e;
+      if (r < L) {
+        double* p = Cb + r * crs + j * ccs;
+        *p = -acc[e] + *p;
+      }
+    }
   }
 }
 
-hipError_t launch_panel_update(double* C, int64_t crs, int64_t ccs, int64_t cstride, int64_t L, int64_t ncols, int nb,
-                               const double* V, const double* Y, int batch, hipStream_t s) {
+hipError_t launch_panel_update_mfma(double* C, int64_t crs, int64_t ccs, int64_t cstride, int64_t L, int64_t ncols,
+                                    int nb, const double* V, const double* Y, int batch, int64_t kchunk, int ksplit,
+                                    hipStream_t s) {
   if (L <= 0 || ncols <= 0 || batch <= 0) return hipSuccess;
-  if (batch > 65535 || (nb != 16 && nb != 8)) return hipErrorInvalidValue;
+  if (batch > 65535 || (nb != 16 && nb != 8) || ksplit > PU_MAX_SPLIT || (ksplit > 1 && kchunk % 4 != 0))
+    return hipErrorInvalidValue;
   const dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)batch);
-  const bool rowfast = crs == 1 && ccs != 1;
-  if (nb == 16) {
-    if (rowfast) panel_update_kernel<16, true><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
-    else panel_update_kernel<16, false><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
-  } else {
-    if (rowfast) panel_update_kernel<8, true><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
-    else panel_update_kernel<8, false><<<grid, 256, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y);
-  }
+  if (nb == 16) panel_update_mfma_kernel<16><<<grid, 512, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y, kchunk, ksplit);
+  else panel_update_mfma_kernel<8><<<grid, 512, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y, kchunk, ksplit);
   return hipGetLastError();
 }
+
+int panel_update_max_split() { return PU_MAX_SPLIT; }
 
 // Panel shapes: RPT rows per thread in a workgroup of NTT threads, one
 // register row per thread up to 1024 rows (more threads rather than more
