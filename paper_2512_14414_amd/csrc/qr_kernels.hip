@@ -287,6 +287,7 @@ __global__ __launch_bounds__(256) void build_vy_kernel(const double* A, int64_t 
 // lane (lr, lq) holds A[m = lr][k = lq] and B[k = lq][n = lr]; result register
 // e is row lq + 4 e, column lr.
 constexpr int PU_MAX_SPLIT = 32;
+constexpr int PU_AHEAD = 8;
 template <int NB>
 __global__ __launch_bounds__(512) void panel_update_mfma_kernel(double* C, int64_t crs, int64_t ccs, int64_t cstride,
                                                                 int64_t L, int64_t ncols, const double* V,
@@ -308,12 +309,21 @@ __global__ __launch_bounds__(512) void panel_update_mfma_kernel(double* C, int64
   for (int sp = wave; sp < nsplit; sp += NW) {
     const int64_t kbeg = (int64_t)sp * chunk, kend = kbeg + chunk < L ? kbeg + chunk : L;
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 4) {
-      const int64_t k = k0 + lq;
-      const bool kok = k < kend;
-      const double a = (kok && lr < NB) ? Yb[k * NB + lr] : 0.0;
-      const double x = (kok && jok) ? Cb[k * crs + j * ccs] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x, acc, 0, 0, 0);
+    // the operands of PU_AHEAD groups of 4 rows are loaded before their MFMAs
+    // run (in the same order as one group at a time): the chain then waits on
+    // memory once per PU_AHEAD groups
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 4 * PU_AHEAD) {
+      double a[PU_AHEAD], x[PU_AHEAD];
+#pragma unroll
+      for (int u = 0; u < PU_AHEAD; ++u) {
+        const int64_t k = k0 + 4 * u + lq;
+        const bool kok = k < kend;
+        a[u] = (kok && lr < NB) ? Yb[k * NB + lr] : 0.0;
+        x[u] = (kok && jok) ? Cb[k * crs + j * ccs] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PU_AHEAD; ++u)
+        if (k0 + 4 * u < kend) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], x[u], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) part[sp][lq + 4 * e][lr] = acc[e];
@@ -335,6 +345,12 @@ __global__ __launch_bounds__(512) void panel_update_mfma_kernel(double* C, int64
   const int64_t rtiles = (L + 15) / 16;
   for (int64_t rt = wave; rt < rtiles; rt += NW) {
     const int64_t r0 = rt * 16;
+    double c[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t r = r0 + lq + 4 * e;
+      c[e] = (jok && r < L) ? Cb[r * crs + j * ccs] : 0.0;
+    }
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k0 = 0; k0 < NB; k0 += 4) {
@@ -347,10 +363,7 @@ __global__ __launch_bounds__(512) void panel_update_mfma_kernel(double* C, int64
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t r = r0 + lq + 4 * e;
-      if (r < L) {
-        double* p = Cb + r * crs + j * ccs;
-        *p = -acc[e] + *p;
-      }
+      if (r < L) Cb[r * crs + j * ccs] = -acc[e] + c[e];
     }
   }
 }
