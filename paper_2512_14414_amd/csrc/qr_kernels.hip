@@ -20,11 +20,62 @@
 namespace qrk {
 
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// The value v of lane (lane ^ MASK) of the wave, moved through registers
+// rather than the LDS crossbar: DPP quad permutes for masks 1 and 2, a row
+// rotation by 8 for mask 8, row shifts by 4 either way for mask 4 (each lane
+// takes the one whose source is its partner), and gfx950's lane swaps between
+// rows (16) and halves (32) of the wave.  Every lane receives exactly its
+// partner's value, as from a shuffle.
+template <int MASK>
+__device__ __forceinline__ double xor_lane(double v, int lane) {
+  const unsigned lo = (unsigned)__double_as_longlong(v), hi = (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+  unsigned rlo, rhi;
+  if constexpr (MASK == 1 || MASK == 2 || MASK == 8) {
+    // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror:8
+    constexpr int ctrl = MASK == 1 ? 0xB1 : MASK == 2 ? 0x4E : 0x128;
+    rlo = (unsigned)__builtin_amdgcn_update_dpp((int)lo, (int)lo, ctrl, 0xF, 0xF, false);
+    rhi = (unsigned)__builtin_amdgcn_update_dpp((int)hi, (int)hi, ctrl, 0xF, 0xF, false);
+  } else if constexpr (MASK == 4) {
+    // row_shl:4 gives lane i the value of lane i + 4, row_shr:4 that of lane i - 4
+    const unsigned ulo = (unsigned)__builtin_amdgcn_update_dpp((int)lo, (int)lo, 0x104, 0xF, 0xF, false);
+    const unsigned uhi = (unsigned)__builtin_amdgcn_update_dpp((int)hi, (int)hi, 0x104, 0xF, 0xF, false);
+    const unsigned dlo = (unsigned)__builtin_amdgcn_update_dpp((int)lo, (int)lo, 0x114, 0xF, 0xF, false);
+    const unsigned dhi = (unsigned)__builtin_amdgcn_update_dpp((int)hi, (int)hi, 0x114, 0xF, 0xF, false);
+    const bool up = (lane & 4) == 0;
+    rlo = up ? ulo : dlo;
+    rhi = up ? uhi : dhi;
+  } else if constexpr (MASK == 16) {
+    // odd rows of the first operand swap with even rows of the second: with both
+    // equal to v, [0] holds rows 0,0,2,2 and [1] rows 1,1,3,3
+    const auto plo = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto phi = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const bool odd = lane & 16;
+    rlo = odd ? plo[0] : plo[1];
+    rhi = odd ? phi[0] : phi[1];
+  } else {
+    static_assert(MASK == 32, "lane mask");
+    // upper half of the first operand swaps with the lower half of the second:
+    // [0] holds halves 0,0 and [1] halves 1,1
+    const auto plo = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto phi = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const bool upper = lane & 32;
+    rlo = upper ? plo[0] : plo[1];
+    rhi = upper ? phi[0] : phi[1];
+  }
+  return __longlong_as_double((long long)(((unsigned long long)rhi << 32) | rlo));
 }
+
+template <int MASK>
+__device__ __forceinline__ double xor_sum_levels(double v, int lane) {
+  if constexpr (MASK >= 1) {
+    v += xor_lane<MASK>(v, lane);
+    return xor_sum_levels<MASK / 2>(v, lane);
+  } else {
+    return v;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return xor_sum_levels<32>(v, threadIdx.x & 63); }
 
 // Sums v over a workgroup of NTT threads; every thread receives the total.  ``red`` holds NTT/64 doubles.
 template <int NTT>
@@ -53,7 +104,7 @@ __device__ __forceinline__ void halving(double* x, int lane) {
     for (int i = 0; i < H; ++i) {
       const double send = hi ? x[i] : x[i + H];
       const double keep = hi ? x[i + H] : x[i];
-      x[i] = keep + __shfl_xor(send, MASK, 64);
+      x[i] = keep + xor_lane<MASK>(send, lane);
     }
     halving<H / 2, MASK / 2>(x, lane);
   }
@@ -64,10 +115,7 @@ __device__ __forceinline__ double wave_reduce(double* x) {
   static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "power of two");
   const int lane = threadIdx.x & 63;
   halving<NV / 2, 32>(x, lane);
-  double v = x[0];
-#pragma unroll
-  for (int o = 32 / NV; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return xor_sum_levels<32 / NV>(x[0], lane);
 }
 
 // The column loop is a real loop: unrolled, each column would run its own
