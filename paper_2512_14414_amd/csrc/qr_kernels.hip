@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void build_vy_kernel(const double* A, int64_t 
 // lane (lr, lq) holds A[m = lr][k = lq] and B[k = lq][n = lr]; result register
 // e is row lq + 4 e, column lr.
 constexpr int PU_MAX_SPLIT = 32;
-constexpr int PU_AHEAD = 8;
+constexpr int PU_AHEAD = 16;
 template <int NB>
 __global__ __launch_bounds__(512) void panel_update_mfma_kernel(double* C, int64_t crs, int64_t ccs, int64_t cstride,
                                                                 int64_t L, int64_t ncols, const double* V,
@@ -389,29 +389,36 @@ __global__ __launch_bounds__(512) void panel_update_mfma_kernel(double* C, int64
     Zs[c][n] = z;
   }
   __syncthreads();
-  // ---- C <- (-(V Z)) + C over 16-row tiles
+  // ---- C <- (-(V Z)) + C over 16-row tiles, two tiles per wave at a time
+  // (their loads issued before either chain)
   const int64_t rtiles = (L + 15) / 16;
-  for (int64_t rt = wave; rt < rtiles; rt += NW) {
-    const int64_t r0 = rt * 16;
-    double c[4];
+  for (int64_t rt0 = wave; rt0 < rtiles; rt0 += 2 * NW) {
+    double av[2][NB / 4], c[2][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t r = r0 + lq + 4 * e;
-      c[e] = (jok && r < L) ? Cb[r * crs + j * ccs] : 0.0;
-    }
-    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r0 = (rt0 + h * NW) * 16;
 #pragma unroll
-    for (int k0 = 0; k0 < NB; k0 += 4) {
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = r0 + lq + 4 * e;
+        c[h][e] = (jok && r < L) ? Cb[r * crs + j * ccs] : 0.0;
+      }
       const int64_t r = r0 + lr;
-      const double a = r < L ? Vb[r * NB + k0 + lq] : 0.0;
-      const double z = Zs[k0 + lq][lr];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z, acc, 0, 0, 0);
-    }
-    if (!jok) continue;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t r = r0 + lq + 4 * e;
-      if (r < L) Cb[r * crs + j * ccs] = -acc[e] + c[e];
+      for (int g = 0; g < NB / 4; ++g) av[h][g] = r < L ? Vb[r * NB + 4 * g + lq] : 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r0 = (rt0 + h * NW) * 16;
+      if (r0 >= L) break;
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int g = 0; g < NB / 4; ++g)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][g], Zs[4 * g + lq][lr], acc, 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = r0 + lq + 4 * e;
+        if (jok && r < L) Cb[r * crs + j * ccs] = -acc[e] + c[h][e];
+      }
     }
   }
 }
