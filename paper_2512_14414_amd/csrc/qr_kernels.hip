@@ -427,7 +427,9 @@ hipError_t launch_panel_update_mfma(double* C, int64_t crs, int64_t ccs, int64_t
                                     int nb, const double* V, const double* Y, int batch, int64_t kchunk, int ksplit,
                                     hipStream_t s) {
   if (L <= 0 || ncols <= 0 || batch <= 0) return hipSuccess;
-  if (batch > 65535 || (nb != 16 && nb != 8) || ksplit > PU_MAX_SPLIT || (ksplit > 1 && kchunk % 4 != 0))
+  // a split must cover the L rows in chunks of whole MFMA groups
+  if (batch > 65535 || (nb != 16 && nb != 8) || ksplit > PU_MAX_SPLIT ||
+      (ksplit > 1 && (kchunk <= 0 || kchunk % 4 != 0 || kchunk * ksplit < L)))
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)batch);
   if (nb == 16) panel_update_mfma_kernel<16><<<grid, 512, 0, s>>>(C, crs, ccs, cstride, L, ncols, V, Y, kchunk, ksplit);
