@@ -14,6 +14,11 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # MFMA accumulators in ordinary VGPRs: the FP64 product kernel then needs
+           # 212 registers instead of 200 + 128 accumulation registers (two waves per
+           # SIMD instead of one) and no longer copies its accumulators out and back
+           # in every K step; the arithmetic does not depend on the register file
+           "-mllvm", "-amdgpu-mfma-vgpr-form",
            "-I", os.path.join(ROOT, "include"),
            *[os.path.join(HERE, s) for s in SOURCES],
            "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib",
