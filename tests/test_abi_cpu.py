@@ -43,3 +43,16 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu():
     pat2 = (ctypes.c_int * 1)(3)
     rc = lib.ctm_init(ctypes.byref(h), ctypes.c_void_p(8), 2, 2, 8, 1, 1, pat2, 1, 0, None)
     assert rc == -1 and b"pattern" in lib.ctm_last_error(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark has no multi-GPU path: asked for two GPUs it prints one
+    JSON line naming the reason and exits with status 2, before any device work."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
