@@ -661,19 +661,25 @@ hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Strided copy with optional type conversion: out (contiguous, shape dims) is
-// filled from in at offset sum_i idx_i * in_stride_i.
-template <typename TI, typename TO>
-__global__ void permute_kernel(PermArgs p, const TI* __restrict__ in, TO* __restrict__ out, int64_t total) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t r = e, off_in = 0, off_out = 0;
+// filled from in at offset sum_i idx_i * in_stride_i.  The flat index is split
+// into per-axis indices by division, so the launcher first merges axes that
+// are contiguous in both tensors (fewer divisions) and, when every index and
+// offset fits in 31 bits, runs the 32-bit form: the device has no integer
+// divide, and a 64-bit one costs several times the 32-bit sequence.
+template <typename TI, typename TO, typename IT>
+__global__ __launch_bounds__(256) void permute_kernel(PermArgs p, const TI* __restrict__ in, TO* __restrict__ out,
+                                                      IT total) {
+  for (IT e = (IT)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (IT)gridDim.x * blockDim.x) {
+    IT r = e, off_in = 0, off_out = 0;
 #pragma unroll
     for (int i = PERM_MAX_DIMS - 1; i >= 0; --i) {
       if (i >= p.ndim) continue;
-      int64_t q = r / p.dims[i];
-      int64_t idx = r - q * p.dims[i];
+      const IT d = (IT)p.dims[i];
+      const IT q = r / d;
+      const IT idx = r - q * d;
       r = q;
-      off_in += idx * p.in_strides[i];
-      off_out += idx * p.out_strides[i];
+      off_in += idx * (IT)p.in_strides[i];
+      off_out += idx * (IT)p.out_strides[i];
     }
     TO v = (TO)in[off_in];
     if (p.accumulate) out[off_out] += v; else out[off_out] = v;
@@ -687,15 +693,50 @@ static unsigned grid_for(int64_t total) {
   return (unsigned)b;
 }
 
-hipError_t launch_permute(const PermArgs& p, int in_type, const void* in, int out_type, void* out, hipStream_t s) {
+template <typename TI, typename TO>
+static void permute_launch(const PermArgs& p, const void* in, void* out, int64_t total, bool narrow, hipStream_t s) {
+  const unsigned gb = grid_for(total);
+  if (narrow)
+    permute_kernel<TI, TO, uint32_t><<<gb, 256, 0, s>>>(p, (const TI*)in, (TO*)out, (uint32_t)total);
+  else
+    permute_kernel<TI, TO, int64_t><<<gb, 256, 0, s>>>(p, (const TI*)in, (TO*)out, total);
+}
+
+hipError_t launch_permute(const PermArgs& p0, int in_type, const void* in, int out_type, void* out, hipStream_t s) {
   int64_t total = 1;
-  for (int i = 0; i < p.ndim; ++i) total *= p.dims[i];
+  for (int i = 0; i < p0.ndim; ++i) total *= p0.dims[i];
   if (total <= 0) return hipSuccess;
-  unsigned gb = grid_for(total);
-  if (in_type == 0 && out_type == 0) permute_kernel<double, double><<<gb, 256, 0, s>>>(p, (const double*)in, (double*)out, total);
-  else if (in_type == 1 && out_type == 1) permute_kernel<float, float><<<gb, 256, 0, s>>>(p, (const float*)in, (float*)out, total);
-  else if (in_type == 0 && out_type == 1) permute_kernel<double, float><<<gb, 256, 0, s>>>(p, (const double*)in, (float*)out, total);
-  else permute_kernel<float, double><<<gb, 256, 0, s>>>(p, (const float*)in, (double*)out, total);
+  // merge axis i+1 into axis i where both tensors step over the pair as one axis
+  PermArgs p = p0;
+  int nd = 0;
+  for (int i = 0; i < p0.ndim; ++i) {
+    if (nd > 0 && p.out_strides[nd - 1] == p0.out_strides[i] * p0.dims[i] &&
+        p.in_strides[nd - 1] == p0.in_strides[i] * p0.dims[i]) {
+      p.dims[nd - 1] *= p0.dims[i];
+      p.out_strides[nd - 1] = p0.out_strides[i];
+      p.in_strides[nd - 1] = p0.in_strides[i];
+      continue;
+    }
+    p.dims[nd] = p0.dims[i];
+    p.in_strides[nd] = p0.in_strides[i];
+    p.out_strides[nd] = p0.out_strides[i];
+    ++nd;
+  }
+  p.ndim = nd;
+  // 32-bit form: flat index (plus one grid stride) and both largest offsets below 2^31
+  const int64_t lim = (int64_t)1 << 31;
+  bool narrow = total + (int64_t)grid_for(total) * 256 < lim;
+  int64_t max_in = 0, max_out = 0;
+  for (int i = 0; i < nd; ++i) {
+    if (p.in_strides[i] < 0 || p.out_strides[i] < 0 || p.dims[i] >= lim) narrow = false;
+    max_in += (p.dims[i] - 1) * p.in_strides[i];
+    max_out += (p.dims[i] - 1) * p.out_strides[i];
+  }
+  narrow = narrow && max_in < lim && max_out < lim;
+  if (in_type == 0 && out_type == 0) permute_launch<double, double>(p, in, out, total, narrow, s);
+  else if (in_type == 1 && out_type == 1) permute_launch<float, float>(p, in, out, total, narrow, s);
+  else if (in_type == 0 && out_type == 1) permute_launch<double, float>(p, in, out, total, narrow, s);
+  else permute_launch<float, double>(p, in, out, total, narrow, s);
   return hipGetLastError();
 }
 
