@@ -139,6 +139,22 @@ int ctm_energy_grad(ctm_ctx* ctx, const double* A, int n_sweeps, const double* H
  * plaquettes in the term list; n (host) receives the count. */
 int ctm_last_rdms(ctm_ctx* ctx, double* rho, int capacity, int* n);
 
+/* Order parameters of spin-1/2 sites (d = 2) from the plaquette density
+ * matrices of the last ctm_energy call (Eq. Mag1: site moments m_i, whose mean
+ * length over the inequivalent sites is the magnetisation M; Eq. Mag2: bond
+ * correlations, whose edge sums on two empty plaquettes give M_p).  out (host)
+ * receives CTM_N_OBS float64 values per plaquette, for the first
+ * min(capacity, n) plaquettes in the order of ctm_last_rdms: the moments
+ * (<S^x>, <S^y>, <S^z>) of the sites TL, TR, BL, BR, each <O> = Tr(O rho_s) /
+ * Tr rho_s over the one-site matrix (basis up, down; the tensors are real, so
+ * <S^y> is the real part of an imaginary trace, 0), then <S_a . S_b> =
+ * Tr((S_a . S_b) rho_ab) / Tr rho_ab for the pairs (TL,TR) (BL,BR) (TL,BL)
+ * (TR,BR) (TL,BR) (TR,BL).  n (host) receives the plaquette count (0 before any
+ * ctm_energy).  CTM_EINVAL for d != 2 or a NULL pointer.  Synchronises the
+ * context's stream. */
+#define CTM_N_OBS 18
+int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
+
 /* Options (key, value):
  *   "svd_cutoff"  relative cutoff below which s^(-1/2) is set to zero (default 1e-10)
  *   "lorentz_eta" relative Lorentzian width of the SVD derivative (default 1e-12)

@@ -45,6 +45,7 @@ def _load():
         "ctm_energy": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D)]),
         "ctm_energy_grad": (I, [P, P, I, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D), P]),
         "ctm_last_rdms": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
+        "ctm_observables": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
         "ctm_set_option": (I, [P, ctypes.c_char_p, D]),
         "ctm_profile_begin": (I, [P]),
         "ctm_profile_end": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I64)]),
@@ -59,7 +60,7 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("ctm_init", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
-            "ctm_sweep", "ctm_energy", "ctm_energy_grad", "ctm_last_rdms", "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
+            "ctm_sweep", "ctm_energy", "ctm_energy_grad", "ctm_last_rdms", "ctm_observables", "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
             "ctm_last_error", "ctm_free")
 
 
@@ -172,6 +173,17 @@ class CTM:
         k = min(n.value, capacity)
         d4 = self.d ** 4
         return torch.tensor(list(buf[: k * d8]), dtype=torch.float64).reshape(k, d4, d4)
+
+    N_OBS = 18   # CTM_N_OBS of include/ctm.h
+
+    def observables(self, capacity=16):
+        """Per plaquette of the last energy call: the (x, y, z) moments of TL, TR, BL, BR, then the six
+        bond correlations (ctm_observables)."""
+        buf = (ctypes.c_double * (capacity * self.N_OBS))()
+        n = ctypes.c_int()
+        self._check(LIB.ctm_observables(self._h, buf, capacity, ctypes.byref(n)))
+        k = min(n.value, capacity)
+        return torch.tensor(list(buf[: k * self.N_OBS]), dtype=torch.float64).reshape(k, self.N_OBS)
 
     def profile_begin(self):
         self._check(LIB.ctm_profile_begin(self._h))

@@ -1482,6 +1482,23 @@ int ctm_last_rdms(ctm_ctx* c, double* rho, int capacity, int* n) {
   } catch (const Error& e) { return fail(c, e); }
 }
 
+int ctm_observables(ctm_ctx* c, double* out, int capacity, int* n) {
+  if (!c || !out || !n || capacity < 0) return CTM_EINVAL;
+  try {
+    if (c->d != 2) throw Error(CTM_EINVAL, "ctm_observables: spin-1/2 sites (d = 2) only");
+    const int k = std::min(capacity, c->n_rdm);
+    DBuf o;
+    if (k > 0) {
+      o = DBuf(&c->dev, (size_t)k * CTM_N_OBS * 8);
+      HIP_CHECK(ctmk::launch_observables((const double*)c->rdm_buf.p, 256, k, (double*)o.p, c->dev.stream));
+      HIP_CHECK(hipMemcpyAsync(out, o.p, (size_t)k * CTM_N_OBS * 8, hipMemcpyDeviceToHost, c->dev.stream));
+    }
+    HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+    *n = c->n_rdm;
+    return CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
 int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   if (!c || !key) return CTM_EINVAL;
   std::string k(key);

@@ -69,6 +69,7 @@ hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, doub
                               int batch, hipStream_t st);
 hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,
                                 int64_t stride_l, int batch, hipStream_t s);
+hipError_t launch_observables(const double* rho, int64_t rho_stride, int n, double* out, hipStream_t s);
 hipError_t launch_energy(const double* rho, int64_t rho_stride, const double* h, const EnergyTerm* terms, int n_terms,
                          int d, double inv_sites, double* E_out, double* bond_out, hipStream_t s);
 hipError_t launch_nonfinite(int type, const void* x, int64_t n, int* flag, hipStream_t s);

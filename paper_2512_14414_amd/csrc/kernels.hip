@@ -891,6 +891,59 @@ hipError_t launch_energy(const double* rho, int64_t rho_stride, const double* h,
   return hipGetLastError();
 }
 
+// Order parameters of spin-1/2 plaquettes (Eqs. Mag1, Mag2) from the density
+// matrices of the energy, rho[(k1 k2 k3 k4), (b1 b2 b3 b4)] (16 x 16, FP64, site
+// q at digit weight 2^(3-q); sites TL, TR, BL, BR; basis up, down).  One
+// workgroup per plaquette, one thread per output: slots 0..11 the moments
+// (<S^x>, <S^y>, <S^z>) of the four sites, <O> = Tr(O rho_s) / Tr rho_s over the
+// one-site matrix; slots 12..17 <S_a . S_b> over the two-site matrix of the
+// pairs (TL,TR) (BL,BR) (TL,BL) (TR,BR) (TL,BR) (TR,BL).  Real rho: <S^y> is the
+// real part of an imaginary trace, zero.
+__global__ __launch_bounds__(64) void observables_kernel(const double* __restrict__ rho, int64_t rho_stride,
+                                                         double* __restrict__ out) {
+  constexpr int NOBS = 18;
+  const int slot = threadIdx.x;
+  if (slot >= NOBS) return;
+  const double* r = rho + (int64_t)blockIdx.x * rho_stride;
+  double v = 0.0;
+  if (slot < 12) {
+    const int s = slot / 3, comp = slot % 3, w = 8 >> s;
+    double rs[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int o = 0; o < 16; ++o) {
+      if (o & w) continue;   // o runs over the configurations of the three other sites
+      for (int k = 0; k < 2; ++k)
+        for (int b = 0; b < 2; ++b) rs[k][b] += r[(int64_t)(o | (k * w)) * 16 + (o | (b * w))];
+    }
+    const double tr = rs[0][0] + rs[1][1];
+    if (comp == 0) v = 0.5 * (rs[0][1] + rs[1][0]) / tr;
+    else if (comp == 2) v = 0.5 * (rs[0][0] - rs[1][1]) / tr;
+  } else {
+    const int pa[6] = {0, 2, 0, 1, 0, 1}, pb[6] = {1, 3, 2, 3, 3, 2};
+    const int wa = 8 >> pa[slot - 12], wb = 8 >> pb[slot - 12];
+    double r2[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) r2[i][j] = 0.0;
+    for (int o = 0; o < 16; ++o) {
+      if (o & (wa | wb)) continue;
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          const int ki = o | ((i >> 1) * wa) | ((i & 1) * wb), bj = o | ((j >> 1) * wa) | ((j & 1) * wb);
+          r2[i][j] += r[(int64_t)ki * 16 + bj];
+        }
+    }
+    // S_a . S_b = S^z S^z + (S^+ S^- + S^- S^+) / 2 in the basis (uu, ud, du, dd)
+    const double tr = r2[0][0] + r2[1][1] + r2[2][2] + r2[3][3];
+    v = (0.25 * (r2[0][0] + r2[3][3] - r2[1][1] - r2[2][2]) + 0.5 * (r2[1][2] + r2[2][1])) / tr;
+  }
+  out[(int64_t)blockIdx.x * NOBS + slot] = v;
+}
+
+hipError_t launch_observables(const double* rho, int64_t rho_stride, int n, double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  observables_kernel<<<n, 64, 0, s>>>(rho, rho_stride, out);
+  return hipGetLastError();
+}
+
 // Non-finite detector: sets *flag = 1 if any entry of x is NaN or Inf.
 template <typename T>
 __global__ void nonfinite_kernel(const T* x, int64_t n, int* flag) {
