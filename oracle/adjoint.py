@@ -31,7 +31,7 @@ from __future__ import annotations
 import torch
 from torch.utils.checkpoint import checkpoint
 
-from .ctmrg import corner_spectra, sweep, truncated_inverse_sqrt
+from .ctmrg import check_cut, corner_spectra, sweep, truncated_inverse_sqrt
 from .network import nested_cell, site_frames
 from .rdm import energy_from_rdms, plaquette_rdm
 
@@ -70,6 +70,7 @@ class Projectors(torch.autograd.Function):
         Qs, Rs = torch.linalg.qr(S, mode="reduced")
         M = Rn @ Rs.T
         U, s, Vh = torch.linalg.svd(M, full_matrices=False)
+        check_cut(s, N, S)
         V = Vh.T
         k, w = truncated_inverse_sqrt(s, chi, cutoff)
         P = (Rs.T @ V[:, :k]) * w

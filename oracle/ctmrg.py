@@ -31,7 +31,11 @@ Readings of points the paper leaves open (all stated in the design doc as well):
 * a sweep is the left, right, up and down moves in that order; the column
   steps of a move go in increasing order in the move's own frame;
 * convergence: delta = max over all corners of the L1 distance between the
-  normalised (sum 1) singular-value spectra of consecutive sweeps.
+  normalised (sum 1) singular-value spectra of consecutive sweeps;
+* a cut whose bond density matrix rho = N S^T vanishes to working precision
+  (largest singular value of M at most 1e-12 |N|_F |S|_F, where rounding
+  alone leaves about 1e-16) carries no environment: Lambda~^(-1/2) of Eq. PQ
+  is undefined there and the step raises ``DegenerateCut``.
 """
 from __future__ import annotations
 
@@ -68,6 +72,21 @@ def init_env(sites):
     return env
 
 
+# relative size of the largest singular value of M below which a cut is empty
+DEGENERATE_CUT = 1e-12
+
+
+class DegenerateCut(ArithmeticError):
+    """The bond density matrix of a cut is zero to working precision (no projector exists)."""
+
+
+def check_cut(s, N, S):
+    """Raise ``DegenerateCut`` if s_1 <= DEGENERATE_CUT * |N|_F |S|_F."""
+    scale = (torch.linalg.norm(N.detach()) * torch.linalg.norm(S.detach())).item()
+    if not s[0].item() > DEGENERATE_CUT * scale:
+        raise DegenerateCut(f"cut carries no weight: s_1 = {s[0].item():.3e}, |N||S| = {scale:.3e}")
+
+
 def truncated_inverse_sqrt(s, chi, cutoff):
     """Lambda~^(-1/2) of the chi' = min(chi, len(s)) largest singular values (pseudo-inverse)."""
     k = min(chi, s.shape[0])
@@ -89,6 +108,7 @@ def bond_projectors(N, S, chi, cutoff):
     Rs = torch.linalg.qr(S, mode="reduced")[1]
     M = Rn @ Rs.T
     U, s, Vh = torch.linalg.svd(M, full_matrices=False)
+    check_cut(s, N, S)
     k, w = truncated_inverse_sqrt(s, chi, cutoff)
     P = (Rs.T @ Vh[:k].T) * w
     Q = (Rn.T @ U[:, :k]) * w
@@ -179,6 +199,11 @@ def sweep(frames, env, chi, cutoff, proj=None):
     return env
 
 
+def spectra_delta(new, old):
+    """delta = max over corners of the L1 distance of two stacks of normalised spectra (rows = corners)."""
+    return (new - old).abs().sum(dim=1).max().item()
+
+
 def corner_spectra(env, chi):
     """Normalised singular values (sum 1, zero-padded to chi) of every corner, in a fixed order."""
     out = []
@@ -213,7 +238,7 @@ class CTM:
         for n in range(1, max_sweeps + 1):
             self.env = sweep(self.frames, self.env, self.chi, self.cutoff, proj=proj)
             sp = corner_spectra(self.env, self.chi)
-            delta = (sp - self.spectra).abs().sum(dim=1).max().item()
+            delta = spectra_delta(sp, self.spectra)
             self.spectra = sp
             if delta < tol:
                 break

@@ -237,6 +237,17 @@ def random_env_flat(chi: int, D: int, d: int, Lx: int, Ly: int, seed: int) -> np
     return np.random.default_rng(seed).uniform(0.0, 1.0, size=n)
 
 
+def random_double_env_flat(chi: int, D: int, Lx: int, Ly: int, seed: int) -> np.ndarray:
+    """A seeded uniform [0, 1) starting environment of the double-layer network (Eq. Tred).
+
+    Layout as ``random_env_flat`` but over the Ly x Lx PEPS positions (y, x)
+    in row-major order, every edge tensor being chi x D^2 x chi (the fused
+    ket/bra leg of the reduced tensor).
+    """
+    n = Lx * Ly * (4 * chi * chi + 4 * chi * D * D * chi)
+    return np.random.default_rng(seed).uniform(0.0, 1.0, size=n)
+
+
 def near_product_tensors(n_tensors: int, d: int, D: int, seed: int, eps: float = 0.2) -> np.ndarray:
     """Random site tensors close to a product state (short correlation length).
 

@@ -86,7 +86,9 @@ def test_random_product_states_bond_by_bond():
 def test_columnar_dimers_exact_plaquette():
     A0 = synth.columnar_dimer_tensors()
     A = synth.gauge_transform(A0, [[0, 1]], 1)
-    c = CTM(A, [[0, 1]], chi=8)
+    # from the sites-derived start some cut of an exact singlet product is
+    # empty (test_oracle_convergence_pins); a generic start avoids it
+    c = CTM(A, [[0, 1]], chi=8, env0=synth.random_env_flat(8, 2, 2, 2, 1, seed=0))
     c.run(8)
     assert abs(energy(c, H, synth.heisenberg_terms(2, 1)).item() + 0.375) < 1e-13
     pat4 = [[[0, 1][x % 2] for x in range(4)] for _ in range(4)]
@@ -106,7 +108,7 @@ def test_orthogonal_dimers_energy():
     assert abs(bond_expectation(brute_rdm(A0, pat4, [(2, 1), (1, 2)]).reshape(2, 2, 2, 2), H) + 0.75) < 1e-14
     A = synth.gauge_transform(A0, pattern, 2)
     for J_nn in (0.7, 0.8):
-        c = CTM(A, pattern, chi=8)
+        c = CTM(A, pattern, chi=8, env0=synth.random_env_flat(8, 2, 2, 2, 2, seed=1))
         c.run(10)
         E = energy(c, H, synth.shastry_sutherland_terms(J_nn, 1.0)).item()
         assert abs(E + 0.375) < 1e-12            # -3/8 J_dimer: an exact eigenstate of Eq. SSM
