@@ -61,11 +61,14 @@ enum {
   CTM_EINVAL = -1,       /* invalid argument */
   CTM_ENOMEM = -2,       /* device allocation failed */
   CTM_EHIP = -3,         /* HIP runtime or kernel launch error */
-  CTM_ESOLVER = -4,      /* the projector SVD did not converge, or a grid barrier wait of its sweep ran out */
+  CTM_ESOLVER = -4,      /* a projector or corner SVD did not converge (or a bounded wait of the one-launch
+                            Jacobi iteration ran out), a cut carries no weight (its bond density matrix
+                            N S^T vanishes to working precision: s_1 <= 1e-12 |N|_F |S|_F, so the
+                            projectors of Eq. PQ do not exist), or an updated environment tensor is zero */
   CTM_ENONFINITE = -5    /* NaN or Inf found in the environment or the result */
 };
 
-enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16 = 2 };
+enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16 = 2, CTM_MIXED = 3 };
 
 typedef struct {
   int px, py;    /* plaquette: top-left PEPS site, 0 <= px < Lx, 0 <= py < Ly */
@@ -74,13 +77,21 @@ typedef struct {
 } ctm_term;
 
 /* Create a context for site tensors A (device, n_tensors*d*D^4 float64, copied)
- * and set the sites-derived starting environment: every C and T is the
- * neighbouring nested site with its outward legs summed over all indices.
+ * of the iPEPS of Eq. PEPS on an Lx x Ly unit cell, build the nested cell of
+ * Sec. II B-C (Eq. XY: ket K and bra B sites with the crossing tensors X, Y on
+ * 2Lx x 2Ly nested positions), and set the sites-derived starting environment
+ * (the paper leaves the start open): every C and T is the neighbouring nested
+ * site with its outward legs summed over all indices.  The context owns all
+ * device memory it allocates; *out receives it (free with ctm_free).
  * precision: CTM_FP64 (all contractions FP64), CTM_FP32 (environment and
- * contractions FP32) or CTM_BF16 (environment FP32, contraction operands
- * rounded to bfloat16, FP32 accumulation).  In every mode the projector QR and
- * SVD (Eq. QRSVD), the projector weights, the norms and the energy sum are
- * FP64.  Requires d >= 1, D >= 1, chi >= D*d, Lx, Ly >= 1, pattern ids in
+ * contractions FP32), CTM_BF16 (environment FP32, contraction operands
+ * rounded to bfloat16, FP32 accumulation) or CTM_MIXED (environment and the
+ * sweep's contractions FP64, the energy's density-matrix contractions and
+ * their adjoints FP32 on the matrix cores: the sweep feeds the SVD
+ * derivative, whose 1/(s_i^2 - s_j^2) terms amplify rounding, while the
+ * energy holds most of the contraction flops and enters the gradient
+ * linearly).  In every mode the projector QR and SVD (Eq. QRSVD), the
+ * projector weights, the norms and the energy sum are FP64.  Requires d >= 1, D >= 1, chi >= D*d, Lx, Ly >= 1, pattern ids in
  * [0, n_tensors).  On error *out is NULL. */
 int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
              int n_tensors, int precision, void* stream);
@@ -103,11 +114,24 @@ int ctm_get_env(ctm_ctx* ctx, double* env);
  * computes the projectors of all rows (Eqs. PQ, QRSVD) and then updates
  * C1, T4, C4 of the next column (Fig. CTMRG b) with Frobenius normalisation.
  * If tol > 0, after each sweep delta = max over corners of the L1 distance of
- * the normalised singular-value spectra to the previous sweep, and the loop
+ * the normalised singular-value spectra to the previous sweep (for the first
+ * sweep after ctm_init, ctm_reset_env or ctm_set_env: to the environment the
+ * sweep started from; the spectra are those of ctm_corner_spectra), and the loop
  * stops once delta < tol; returns CTM_ENOTCONV if max_sweeps is reached
  * first.  sweeps_done and delta (host, may be NULL) receive the count and the
  * last delta (delta is -1 when tol <= 0). */
 int ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done, double* delta);
+
+/* Corner spectra of the current environment (the quantity whose convergence
+ * ends the iteration, Sec. II C): for every nested position (I, J) in row-major
+ * order and each corner C1..C4, the singular values of the chi x chi corner in
+ * descending order, divided by their sum and zero-padded to chi.  out (host)
+ * receives 4 * (2Lx) * (2Ly) * chi float64 values, capacity is its length in
+ * values; with out == NULL only *n_written (host, may be NULL otherwise) is
+ * set to the required length.  CTM_EINVAL if capacity is too small;
+ * CTM_ESOLVER if a corner SVD fails.  The sweep's own convergence state is not
+ * changed.  Synchronises the context's stream. */
+int ctm_corner_spectra(ctm_ctx* ctx, double* out, int64_t capacity, int64_t* n_written);
 
 /* Energy per site (Eq. ExpH) from the current environment: for every plaquette
  * named by a term, the 2x2 reduced density matrix rho (d^4 x d^4, ket indices
@@ -177,6 +201,14 @@ int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
  *                 test on the host.  Both give identical results.  No
  *                 convergence, or a wait between rounds that runs out (waits
  *                 are bounded), fails the call with CTM_ESOLVER when it returns.
+ *   "energy_precision" CTM_FP64, CTM_FP32 or CTM_BF16: the precision of the
+ *                 energy's density-matrix contractions (and their adjoints) alone,
+ *                 whatever the sweep's (default: that of the context's precision).
+ *   "jacobi_cooperative" 1 (default) to make that one launch a cooperative
+ *                 launch, whose workgroups the runtime guarantees to be resident
+ *                 together (a grid the device cannot hold is refused and the
+ *                 call falls back to one launch per round); 0 for a plain launch
+ *                 taken only when the occupancy API says the grid fits.
  *   "jacobi_max_sweeps" the most Jacobi sweeps of one projector SVD (1..1000,
  *                 default 40); an SVD that needs more fails the call with
  *                 CTM_ESOLVER.

@@ -119,9 +119,10 @@ def energy_after_sweeps(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-10,
                         use_checkpoint=True):
     """E(A) after ``n_sweeps`` sweeps from the constant environment ``env0``; differentiable in A.
 
-    Returns (E, env_final).  With ``use_checkpoint`` each sweep is recomputed
-    during the backward pass instead of stored (torch.utils.checkpoint), which
-    bounds memory to one sweep's intermediates.
+    Returns (E, env_final).  With ``use_checkpoint`` each sweep and each
+    plaquette density matrix is recomputed during the backward pass instead of
+    stored (torch.utils.checkpoint), which bounds memory to one sweep's or one
+    plaquette's intermediates.
     """
     sites, _ = nested_cell(A, pattern)
     frames = site_frames(sites)
@@ -145,8 +146,19 @@ def energy_after_sweeps(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-10,
         env = [[{k: out[(I * NX + J) * 8 + n] for n, k in enumerate(keys)} for J in range(NX)] for I in range(NY)]
     Ly, Lx = len(pattern), len(pattern[0])
     needed = sorted({(t[0], t[1]) for t in terms})
-    sites, _ = nested_cell(A, pattern)
-    rdms = {p: plaquette_rdm(sites, env, p[0], p[1]) for p in needed}
+    flat = tuple(env[I][J][k] for I in range(NY) for J in range(NX) for k in keys)
+
+    def rdm(px, py, A_, *flat_):
+        e = [[{k: flat_[(I * NX + J) * 8 + n] for n, k in enumerate(keys)} for J in range(NX)] for I in range(NY)]
+        return plaquette_rdm(nested_cell(A_, pattern)[0], e, px, py)
+
+    rdms = {}
+    for p in needed:
+        if use_checkpoint and A.requires_grad:
+            # recomputed in the backward pass: one plaquette's intermediates alive at a time
+            rdms[p] = checkpoint(rdm, p[0], p[1], A, *flat, use_reentrant=False)
+        else:
+            rdms[p] = rdm(p[0], p[1], A, *flat)
     return energy_from_rdms(rdms, H, terms, Lx * Ly), env
 
 

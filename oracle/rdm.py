@@ -14,9 +14,11 @@ ket index k on the K side and the bra index b on the B side.
 The raw rho is used, not a symmetrised one: the nested environment treats bra
 and ket separately and need not be Hermitian (Sec. IV).
 
-Contraction order: the left half (boundary column, nested columns 0 and 1)
-and the right half (boundary column, nested columns 3 and 2) are built column
-by column and then joined.
+Contraction order (the network and its sum are fixed; only the order of the
+pairwise contractions is chosen, for memory): each corner quadrant -- one
+corner, its two pairs of edges and its 2x2 block of nested sites -- is
+contracted first, then the upper two and the lower two quadrants, then the
+two halves.  The largest intermediate is a half of chi^2 D^4 d^4 entries.
 """
 from __future__ import annotations
 
@@ -89,20 +91,16 @@ def _block_tensors(sites, env, x, y):
 def plaquette_rdm(sites, env, x, y):
     """rho as a (d^4 x d^4) matrix [(k_TL k_TR k_BL k_BR), (b_TL b_TR b_BL b_BR)], not normalised."""
     et, st = _block_tensors(sites, env, x, y)
-    # left half: boundary column, then nested columns 0 and 1 (top edge, sites, bottom edge)
-    L = contract_all([et["C1"], et["T40"], et["T41"], et["T42"], et["T43"], et["C4"]])
-    for c in (0, 1):
-        L = contract(L, et[f"T1{c}"])
-        for r in range(4):
-            L = contract(L, st[(r, c)])
-        L = contract(L, et[f"T3{c}"])
-    R = contract_all([et["C2"], et["T20"], et["T21"], et["T22"], et["T23"], et["C3"]])
-    for c in (3, 2):
-        R = contract(R, et[f"T1{c}"])
-        for r in range(4):
-            R = contract(R, st[(r, c)])
-        R = contract(R, et[f"T3{c}"])
-    rho = contract(L, R)
+    # each list starts at the corner and takes one edge and the site it touches at a time
+    tl = contract_all([et["C1"], et["T10"], et["T40"], st[(0, 0)], et["T11"], st[(0, 1)], et["T41"], st[(1, 0)],
+                       st[(1, 1)]])
+    tr = contract_all([et["C2"], et["T13"], et["T20"], st[(0, 3)], et["T12"], st[(0, 2)], et["T21"], st[(1, 3)],
+                       st[(1, 2)]])
+    bl = contract_all([et["C4"], et["T43"], et["T30"], st[(3, 0)], et["T42"], st[(2, 0)], et["T31"], st[(3, 1)],
+                       st[(2, 1)]])
+    br = contract_all([et["C3"], et["T33"], et["T23"], st[(3, 3)], et["T32"], st[(3, 2)], et["T22"], st[(2, 3)],
+                       st[(2, 2)]])
+    rho = contract(contract(tl, tr), contract(bl, br))
     t = rho.order([f"k{n}" for n in ORDER] + [f"b{n}" for n in ORDER])
     d = t.shape[0]
     return t.reshape(d ** 4, d ** 4)

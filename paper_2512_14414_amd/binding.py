@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libctm.so")
 
 CTM_OK, CTM_ENOTCONV = 0, 1
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "mixed": 3}
 
 
 class CTMError(RuntimeError):
@@ -46,6 +46,7 @@ def _load():
         "ctm_energy_grad": (I, [P, P, I, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D), P]),
         "ctm_last_rdms": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
         "ctm_observables": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
+        "ctm_corner_spectra": (I, [P, ctypes.POINTER(D), I64, ctypes.POINTER(I64)]),
         "ctm_set_option": (I, [P, ctypes.c_char_p, D]),
         "ctm_profile_begin": (I, [P]),
         "ctm_profile_end": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I64)]),
@@ -60,7 +61,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("ctm_init", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
-            "ctm_sweep", "ctm_energy", "ctm_energy_grad", "ctm_last_rdms", "ctm_observables", "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
+            "ctm_sweep", "ctm_corner_spectra", "ctm_energy", "ctm_energy_grad", "ctm_last_rdms", "ctm_observables",
+            "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
             "ctm_last_error", "ctm_free")
 
 
@@ -173,6 +175,14 @@ class CTM:
         k = min(n.value, capacity)
         d4 = self.d ** 4
         return torch.tensor(list(buf[: k * d8]), dtype=torch.float64).reshape(k, d4, d4)
+
+    def corner_spectra(self):
+        """Normalised corner spectra (ctm_corner_spectra): rows = nested positions row-major x (C1..C4), chi each."""
+        n = ctypes.c_int64()
+        self._check(LIB.ctm_corner_spectra(self._h, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_double * n.value)()
+        self._check(LIB.ctm_corner_spectra(self._h, buf, n.value, ctypes.byref(n)))
+        return torch.tensor(list(buf), dtype=torch.float64).reshape(-1, self.chi)
 
     N_OBS = 18   # CTM_N_OBS of include/ctm.h
 

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
@@ -68,7 +69,9 @@ struct ctm_ctx {
   int d = 0, D = 0, chi = 0, Lx = 0, Ly = 0, nt = 0, prec = 0, NY = 0, NX = 0;
   std::vector<int> pattern;
   int st = T_F64;                 // storage type of sites and environment
-  int mode = ctmk::MODE_F64;      // matrix-core path for float contractions
+  int mode = ctmk::MODE_F64;      // matrix-core path of the sweep's contractions
+  int est = T_F64;                // storage type of the energy's intermediates
+  int emode = ctmk::MODE_F64;     // matrix-core path of the energy's contractions (and their adjoints)
   DBuf A64;                       // float64 copy of the site tensors
   DBuf site_buf;
   std::vector<SiteRef> frames[4];
@@ -79,12 +82,13 @@ struct ctm_ctx {
   int check_finite = 1;
   int jacobi_max_sweeps = 40;
   bool jacobi_one_launch = true;   // all rounds of a Jacobi sweep in one launch (when the grid fits the device)
+  bool jacobi_coop = true;         // launch that kernel cooperatively (co-residency guaranteed by the runtime)
   int64_t sweep_capacity = -1;     // workgroups of that launch the device holds at once (-1: not yet asked)
   DBuf spec_prev, spec_cur, dscal;   // spectra and a few device scalars
   bool have_prev = false;
   DBuf rdm_buf;
   int n_rdm = 0;
-  DBuf flag;                      // int flags: [0] non-finite, [1..] solver info
+  DBuf flag;                      // int flags: [0] non-finite, [1] failed solves, [2] empty cuts, [3] zero tensors
   std::string err;
   // Current storage of every environment tensor (position-major, 8 slots):
   // normally views of ``env``; while a tape records, every update goes to a
@@ -558,7 +562,9 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   const int maxsw = c->jacobi_max_sweeps;
   // the whole iteration in one launch when the device holds all its workgroups at once
   if (c->sweep_capacity < 0) c->sweep_capacity = ctmk::bjac_sweep_capacity();
-  const bool one_launch = c->jacobi_one_launch && ctmk::bjac_grid(r, batch) <= c->sweep_capacity;
+  // a cooperative launch is refused by the runtime when the device cannot hold
+  // the grid; the plain launch is only taken when the occupancy says it can
+  bool one_launch = c->jacobi_one_launch && (c->jacobi_coop || ctmk::bjac_grid(r, batch) <= c->sweep_capacity);
   // per-sweep rotation counts and largest rotated |cos| (one slot per sweep in
   // one launch, one reused slot otherwise), then the sweep count; the
   // synchronisation words of the one-launch iteration
@@ -594,9 +600,21 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
     HIP_CHECK(ctmk::launch_fill_int(rot_p, 0, slots + 1 + nsync, dev.stream));
     fill(dev, view(ovl.p, T_F64, {slots}, "b"), 0.0);
     if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
-    HIP_CHECK(ctmk::launch_bjac_svd((double*)X.p, (double*)W.p, r, stride, batch, maxsw, tol, stop,
-                                    (const double*)tiny2.p, rot_p, (double*)ovl.p, (unsigned*)(rot_p + slots + 1),
-                                    (int*)c->flag.p + 1, rot_p + slots, dev.stream));
+    hipError_t e = ctmk::launch_bjac_svd((double*)X.p, (double*)W.p, r, stride, batch, maxsw, tol, stop,
+                                         (const double*)tiny2.p, rot_p, (double*)ovl.p, (unsigned*)(rot_p + slots + 1),
+                                         (int*)c->flag.p + 1, rot_p + slots, c->jacobi_coop, dev.stream);
+    if (e != hipSuccess && c->jacobi_coop) {
+      // refused (the grid does not fit the device at once): nothing was queued;
+      // clear the error, close the timed interval (empty) and take one launch
+      // per round below
+      (void)hipGetLastError();
+      if (g_counters.timing) g_counters.record(dev.stream, FAM_JACOBI);
+      one_launch = false;
+    } else {
+      HIP_CHECK(e);
+    }
+  }
+  if (one_launch) {
     if (g_counters.timing) {
       g_counters.record(dev.stream, FAM_JACOBI);
       // profiling only: the flop count needs the number of sweeps run
@@ -656,6 +674,10 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
 // singular vectors of rho = N S^T (U_rho = Q_n [U; 0], V_rho = Q_s [V; 0])
 // and the derivative of the block (N, S) -> (P, Q) is recorded (see
 // proj_backward).
+// Largest singular value of M, relative to |N|_F |S|_F, at or below which a
+// cut carries no weight (rounding alone leaves about 1e-16).
+constexpr double kEmptyCut = 1e-12;
+
 struct ProjRow {
   int64_t kd = 0, mn = 0;
   std::shared_ptr<DBuf> N, S, Ur, Vr, s, w;   // N, S row-major mn x kd; Ur, Vr column-major mn x r
@@ -761,6 +783,22 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
   side_scope.join();
   // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
   jacobi_svd(c, (double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
+  {
+    // a cut whose bond density matrix vanishes to working precision has no
+    // projector (Lambda~^(-1/2) of Eq. PQ is undefined): counted in the flags
+    // and reported as CTM_ESOLVER when the call returns
+    ctmk::CutList cl;
+    std::memset(&cl, 0, sizeof(cl));
+    for (int I = 0; I < a; ++I) {
+      int p = I & 1, b = I >> 1;
+      const size_t lfs = (size_t)kd[p] * r;
+      cl.Ln[I] = (const double*)L[p].p + (size_t)b * lfs;
+      cl.Ls[I] = (const double*)L[p].p + (size_t)(cnt[p] + b) * lfs;
+      cl.s1[I] = (const double*)sv.p + (size_t)I * r;
+      cl.n[I] = (int64_t)lfs;
+    }
+    HIP_CHECK(ctmk::launch_cut_check(cl, a, kEmptyCut, (int*)c->flag.p + 2, dev.stream));
+  }
   HIP_CHECK(ctmk::launch_svd_weights((const double*)sv.p, r, r, (double*)w.p, chi, c->cutoff, a, dev.stream));
   for (int I = 0; I < a; ++I) {
     int p = I & 1, b = I >> 1;
@@ -899,6 +937,7 @@ void normalize_all(ctm_ctx* c, const std::vector<TRef>& ts) {
       L.n[cnt] = ts[i].numel();
     }
     if (rec) L.norm_out = (double*)norms->p + s0;
+    L.zero_flag = (int*)c->flag.p + 3;
     HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, dev.stream));
   }
   if (!rec) return;
@@ -991,13 +1030,18 @@ void left_move(ctm_ctx* c, int f) {
 
 const int MOVE_FRAMES[4] = {0, 2, 1, 3};   // left, right, up, down
 
-// Normalised corner spectra of the environment and their L1 change.
-double spectra_delta(ctm_ctx* c) {
+int corner_count(const ctm_ctx* c) { return c->NY * c->NX * 4; }
+
+// Singular values (descending, chi per corner) of every corner of the current
+// environment, in the order positions (I, J) row-major, then C1..C4.  A failed
+// rocSOLVER solve is counted in the context's solver flag.
+void corner_svals(ctm_ctx* c, DBuf& sv) {
   Dev& dev = c->dev;
   const int64_t chi = c->chi;
-  const int count = c->NY * c->NX * 4;
-  DBuf Cs(&dev, (size_t)count * chi * chi * 8), sv(&dev, (size_t)count * chi * 8), E(&dev, (size_t)count * chi * 8);
+  const int count = corner_count(c);
+  DBuf Cs(&dev, (size_t)count * chi * chi * 8), E(&dev, (size_t)count * chi * 8);
   DBuf infos(&dev, (size_t)count * sizeof(int));
+  sv = DBuf(&dev, (size_t)count * chi * 8);
   for (int p = 0; p < c->NY * c->NX; ++p)
     for (int k = 0; k < 4; ++k) {
       TRef src = view((char*)c->env.p + c->slot_off[(size_t)p * 8 + k] * type_size(c->st), c->st, {chi, chi}, "ab");
@@ -1007,6 +1051,17 @@ double spectra_delta(ctm_ctx* c) {
                                             (rocblas_int)chi, (double*)Cs.p, (rocblas_int)chi, chi * chi,
                                             (double*)sv.p, chi, nullptr, 1, 0, nullptr, 1, 0, (double*)E.p, chi,
                                             rocblas_outofplace, (int*)infos.p, count));
+  // info != 0: the bidiagonal iteration did not converge for that corner
+  HIP_CHECK(ctmk::launch_flag_or((const int*)infos.p, count, (int*)c->flag.p + 1, dev.stream));
+}
+
+// Normalised corner spectra of the environment and their L1 change.
+double spectra_delta(ctm_ctx* c) {
+  Dev& dev = c->dev;
+  const int64_t chi = c->chi;
+  const int count = corner_count(c);
+  DBuf sv;
+  corner_svals(c, sv);
   if (!c->spec_cur.p) {
     c->spec_cur = DBuf(&dev, (size_t)count * chi * 8);
     c->spec_prev = DBuf(&dev, (size_t)count * chi * 8);
@@ -1024,12 +1079,17 @@ double spectra_delta(ctm_ctx* c) {
 }
 
 void check_flags(ctm_ctx* c) {
-  int h[2] = {0, 0};
+  int h[4] = {0, 0, 0, 0};
   HIP_CHECK(hipMemcpyAsync(h, c->flag.p, sizeof(h), hipMemcpyDeviceToHost, c->dev.stream));
   HIP_CHECK(hipStreamSynchronize(c->dev.stream));
-  HIP_CHECK(hipMemsetAsync(c->flag.p, 0, 2 * sizeof(int), c->dev.stream));
-  // a failed solve first: it is the cause of whatever else went wrong after it
+  HIP_CHECK(hipMemsetAsync(c->flag.p, 0, sizeof(h), c->dev.stream));
+  // a failed solve or an empty cut first: either is the cause of whatever
+  // else went wrong after it
   if (h[1]) throw Error(CTM_ESOLVER, "SVD did not converge (" + std::to_string(h[1]) + " failed solves)");
+  if (h[2])
+    throw Error(CTM_ESOLVER, "empty cut: the bond density matrix of " + std::to_string(h[2]) +
+                                 " cut(s) vanished to working precision (s_1 <= 1e-12 |N||S|), no projector exists");
+  if (h[3]) throw Error(CTM_ESOLVER, "an updated environment tensor is zero (" + std::to_string(h[3]) + " tensors)");
   if (h[0]) throw Error(CTM_ENONFINITE, "non-finite value in the environment");
 }
 
@@ -1052,7 +1112,17 @@ void check_flags(ctm_ctx* c) {
 // rho[(k_TL k_TR k_BL k_BR), (b_TL b_TR b_BL b_BR)].
 void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
   Dev& dev = c->dev;
-  const int m = c->mode;
+  // the energy's own precision: its environment and site tensors are copied
+  // to the energy's storage type first when that differs from the sweep's
+  const int m = c->emode;
+  const int est = c->est;
+  std::deque<Tmp> conv;
+  auto in_est = [&](const TRef& t) -> TRef {
+    if (t.type == est) return t;
+    conv.emplace_back(&dev, est, t.dim, t.lab);
+    copy_into(dev, conv.back().t, t);
+    return conv.back().t;
+  };
   const int64_t D = c->D, d = c->d;
   const int r0 = 2 * py, c0 = 2 * px;
   Labels Lb;
@@ -1068,8 +1138,8 @@ void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
   auto bO = [&](int s) { return Lb(std::string("b") + names[s]); };
   auto str = [](std::initializer_list<char> l) { return std::string(l); };
 
-  auto env = [&](int r, int cc, int k, const std::string& lab) { return c->slot(0, r0 + r, c0 + cc, k, lab); };
-  auto site = [&](int r, int cc, const std::string& lab) { return c->site_t(0, r0 + r, c0 + cc, lab); };
+  auto env = [&](int r, int cc, int k, const std::string& lab) { return in_est(c->slot(0, r0 + r, c0 + cc, k, lab)); };
+  auto site = [&](int r, int cc, const std::string& lab) { return in_est(c->site_t(0, r0 + r, c0 + cc, lab)); };
 
   auto absorb = [&](Tmp& S, const TRef& X) {
     std::string out;
@@ -1078,7 +1148,7 @@ void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
     for (char ch : out) dims.push_back(S.t.dim[S.t.lab.find(ch)]);
     for (size_t q = 0; q < X.lab.size(); ++q)
       if (S.t.lab.find(X.lab[q]) == std::string::npos) { out += X.lab[q]; dims.push_back(X.dim[q]); }
-    Tmp R(&dev, c->st, dims, out);
+    Tmp R(&dev, est, dims, out);
     contract(dev, m, R.t, S.t, X);
     S = std::move(R);
   };
@@ -1088,7 +1158,7 @@ void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
     S.t.lab[i] = to;
   };
   auto start = [&](const TRef& corner) {
-    Tmp S(&dev, c->st, corner.dim, corner.lab);
+    Tmp S(&dev, est, corner.dim, corner.lab);
     copy_into(dev, S.t, corner);
     return S;
   };
@@ -1158,10 +1228,10 @@ void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
   absorb(BL, BR.t);   // over cB2, H(2,1), H(3,1)
   std::string ol = str({kO(0), kO(1), kO(2), kO(3), bO(0), bO(1), bO(2), bO(3)});
   std::vector<int64_t> od(8, d);
-  if (c->st == T_F64) {
+  if (est == T_F64) {
     contract(dev, m, view(rho_out, T_F64, od, ol), TL.t, BL.t);
   } else {
-    Tmp r32(&dev, c->st, od, ol);
+    Tmp r32(&dev, est, od, ol);
     contract(dev, m, r32.t, TL.t, BL.t);
     copy_into(dev, view(rho_out, T_F64, od, ol), r32.t);
   }
@@ -1342,7 +1412,7 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int 
     if (!A || !pattern || d < 1 || D < 1 || Lx < 1 || Ly < 1 || n_tensors < 1)
       throw Error(CTM_EINVAL, "invalid dimensions or NULL pointer");
     if ((int64_t)chi < (int64_t)D * d) throw Error(CTM_EINVAL, "chi must be at least D*d");
-    if (precision < CTM_FP64 || precision > CTM_BF16) throw Error(CTM_EINVAL, "unknown precision");
+    if (precision < CTM_FP64 || precision > CTM_MIXED) throw Error(CTM_EINVAL, "unknown precision");
     for (int i = 0; i < Lx * Ly; ++i)
       if (pattern[i] < 0 || pattern[i] >= n_tensors) throw Error(CTM_EINVAL, "pattern id out of range");
     c = new ctm_ctx();
@@ -1350,8 +1420,12 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int 
     c->d = d; c->D = D; c->chi = chi; c->Lx = Lx; c->Ly = Ly; c->nt = n_tensors; c->prec = precision;
     c->NY = 2 * Ly; c->NX = 2 * Lx;
     c->pattern.assign(pattern, pattern + Lx * Ly);
-    c->st = precision == CTM_FP64 ? T_F64 : T_F32;
+    c->st = (precision == CTM_FP64 || precision == CTM_MIXED) ? T_F64 : T_F32;
     c->mode = precision == CTM_BF16 ? ctmk::MODE_BF16 : (precision == CTM_FP32 ? ctmk::MODE_F32 : ctmk::MODE_F64);
+    // CTM_MIXED: the sweep in FP64, the energy's contractions (and their
+    // adjoints) in FP32 on the matrix cores
+    c->est = precision == CTM_MIXED ? T_F32 : c->st;
+    c->emode = precision == CTM_MIXED ? ctmk::MODE_F32 : c->mode;
     if (rocblas_create_handle(&c->blas) != rocblas_status_success) throw Error(CTM_EHIP, "rocblas_create_handle failed");
     RB_CHECK(rocblas_set_stream(c->blas, c->dev.stream));
     hipStream_t side = nullptr;
@@ -1424,6 +1498,8 @@ int ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, double* 
   try {
     double dl = -1.0;
     int n = 0;
+    // the first delta compares with the spectra of the environment the call starts from
+    if (tol > 0 && !c->have_prev) (void)spectra_delta(c);
     for (n = 1; n <= max_sweeps; ++n) {
       for (int f : MOVE_FRAMES) left_move(c, f);
       if (c->check_finite)
@@ -1439,6 +1515,27 @@ int ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, double* 
     if (sweeps_done) *sweeps_done = n;
     if (delta) *delta = dl;
     return (tol > 0 && !(dl < tol)) ? CTM_ENOTCONV : CTM_OK;
+  } catch (const Error& e) { return fail(c, e); }
+}
+
+int ctm_corner_spectra(ctm_ctx* c, double* out, int64_t capacity, int64_t* n_written) {
+  if (!c) return CTM_EINVAL;
+  const int64_t total = (int64_t)corner_count(c) * c->chi;
+  if (n_written) *n_written = 0;
+  if (!out) {
+    if (n_written) *n_written = total;
+    return CTM_OK;
+  }
+  if (capacity < total) return fail(c, Error(CTM_EINVAL, "capacity below 4 * (2Lx) * (2Ly) * chi values"));
+  try {
+    DBuf sv, norm(&c->dev, (size_t)total * 8);
+    corner_svals(c, sv);
+    HIP_CHECK(ctmk::launch_spectra_delta((const double*)sv.p, c->chi, c->chi, (double*)norm.p, nullptr,
+                                         corner_count(c), (double*)c->dscal.p, c->dev.stream));
+    HIP_CHECK(hipMemcpyAsync(out, norm.p, (size_t)total * 8, hipMemcpyDeviceToHost, c->dev.stream));
+    check_flags(c);
+    if (n_written) *n_written = total;
+    return CTM_OK;
   } catch (const Error& e) { return fail(c, e); }
 }
 
@@ -1510,6 +1607,11 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "rowmajor_f64") ctmk::g_rowmajor_f64 = value != 0;
   else if (k == "rowmajor_f32") ctmk::g_rowmajor_f32 = value != 0;
   else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
+  else if (k == "jacobi_cooperative") c->jacobi_coop = value != 0;
+  else if (k == "energy_precision" && (value == CTM_FP64 || value == CTM_FP32 || value == CTM_BF16)) {
+    c->est = value == CTM_FP64 ? T_F64 : T_F32;
+    c->emode = value == CTM_BF16 ? ctmk::MODE_BF16 : (value == CTM_FP32 ? ctmk::MODE_F32 : ctmk::MODE_F64);
+  }
   else if (k == "jacobi_max_sweeps" && value >= 1 && value <= 1000) c->jacobi_max_sweeps = (int)value;
   else if (k == "qr_fused_vy") g_qr_fused_vy = value != 0;
   else if (k == "qr_one_update") g_qr_one_update = value != 0;

@@ -382,6 +382,18 @@ Plan make_plan(const TRef& C, const TRef& A, const TRef& B) {
   return P;
 }
 
+// Whether a product with M x N outputs (per batch) and a sum of length K is
+// split over K (few output tiles and a long sum), and into which chunks.
+bool split_k(int64_t M, int64_t N, int64_t K, int64_t batch, int64_t& kchunk, int64_t& ksplit) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * batch;
+  if (tiles >= 128 || K < 256) return false;
+  const int64_t want = std::min<int64_t>((512 + tiles - 1) / tiles, K / 128);
+  if (want <= 1) return false;
+  kchunk = ((K + want - 1) / want + 31) / 32 * 32;
+  ksplit = (K + kchunk - 1) / kchunk;
+  return true;
+}
+
 void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A, const TRef& B, double alpha,
                  int beta, const double* colscale) {
   ctmk::GemmArgs g;
@@ -412,16 +424,10 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
   const double fl = 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
   // few output tiles and a long sum: split K over more workgroups (partials in a workspace)
   DBuf work;
-  const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
-  if (tiles < 128 && g.K >= 256) {
-    int64_t want = std::min<int64_t>((512 + tiles - 1) / tiles, g.K / 128);
-    if (want > 1) {
-      g.kchunk = ((g.K + want - 1) / want + 31) / 32 * 32;
-      g.ksplit = (g.K + g.kchunk - 1) / g.kchunk;
-      if (g.ksplit > 65535) throw Error(-1, "contract: K too long to split");
-      work = DBuf(&dev, (size_t)g.ksplit * g.batch * g.M * g.N * type_size(C.type));
-      g.work = work.p;
-    }
+  if (split_k(g.M, g.N, g.K, g.batch, g.kchunk, g.ksplit)) {
+    if (g.ksplit > 65535) throw Error(-1, "contract: K too long to split");
+    work = DBuf(&dev, (size_t)g.ksplit * g.batch * g.M * g.N * type_size(C.type));
+    g.work = work.p;
   }
   g_counters.launches++;
   g_counters.flops += fl;

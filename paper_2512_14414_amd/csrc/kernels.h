@@ -45,6 +45,16 @@ struct NormList {
   void* ptr[NORM_MAX];
   int64_t n[NORM_MAX];
   double* norm_out;         // optional, one value per tensor
+  int* zero_flag;           // optional: incremented for every tensor whose norm is 0
+};
+
+// Rows of a column step checked for an empty cut (launch_cut_check).
+constexpr int CUT_MAX = 64;
+struct CutList {
+  const double* Ln[CUT_MAX];   // R_n^T of the row (any layout, n entries)
+  const double* Ls[CUT_MAX];   // R_s^T of the row
+  const double* s1[CUT_MAX];   // largest singular value of M
+  int64_t n[CUT_MAX];
 };
 
 struct EnergyTerm {
@@ -67,6 +77,8 @@ hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_normalize(int type, const NormList& L, int count, hipStream_t s);
 hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, double* w, int64_t chi, double cutoff,
                               int batch, hipStream_t st);
+// Adds one to *flag for every row whose s_1 <= tau |N|_F |S|_F.
+hipError_t launch_cut_check(const CutList& L, int count, double tau, int* flag, hipStream_t s);
 hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,
                                 int64_t stride_l, int batch, hipStream_t s);
 hipError_t launch_observables(const double* rho, int64_t rho_stride, int n, double* out, hipStream_t s);
@@ -95,11 +107,14 @@ hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, in
 // device after each sweep.  rot: max_sweeps * batch ints, ovl: max_sweeps *
 // batch doubles, sync: bjac_sync_words(n, batch, max_sweeps) unsigned ints, all
 // zero before the launch.  *sweeps (device) receives the sweeps run; no
-// convergence, or a wait that ran out, adds one to *fail (device).  Only for
-// grids of at most bjac_sweep_capacity() workgroups (bjac_grid(n, batch)).
+// convergence, or a wait that ran out, adds one to *fail (device).  With
+// ``cooperative`` the launch is a cooperative one, which the runtime refuses
+// (an error return, nothing queued) when the device cannot hold the grid at
+// once; otherwise only for grids of at most bjac_sweep_capacity() workgroups
+// (bjac_grid(n, batch)).
 hipError_t launch_bjac_svd(double* A, double* V, int64_t n, int64_t stride, int batch, int max_sweeps, double tol,
                            double stop, const double* tiny2, int* rot, double* ovl, unsigned* sync, int* fail,
-                           int* sweeps, hipStream_t s);
+                           int* sweeps, bool cooperative, hipStream_t s);
 int64_t bjac_sync_words(int64_t n, int batch, int max_sweeps);
 int64_t bjac_sweep_capacity();
 int64_t bjac_grid(int64_t n, int batch);

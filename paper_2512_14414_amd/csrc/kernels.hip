@@ -781,6 +781,8 @@ __global__ __launch_bounds__(256) void normalize_kernel(NormList L) {
   }
   double nrm = sqrt(red[0]);
   if (threadIdx.x == 0 && L.norm_out) L.norm_out[t] = nrm;
+  // an updated environment tensor that is zero has lost the whole environment
+  if (threadIdx.x == 0 && L.zero_flag && !(nrm > 0.0)) atomicAdd(L.zero_flag, 1);
   double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) x[i] = (T)((double)x[i] * inv);
 }
@@ -810,6 +812,40 @@ hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, doub
                               int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
   svd_weights_kernel<<<batch, 128, 0, st>>>(s, r, stride_s, w, chi, cutoff, batch);
+  return hipGetLastError();
+}
+
+// Empty cuts: for row t, with R_n^T and R_s^T of its half systems (Frobenius
+// norms those of N and S) and the largest singular value s_1 of M = R_n R_s^T,
+// count the row in *flag when s_1 <= tau |N|_F |S|_F (the bond density matrix
+// N S^T vanishes to working precision and Lambda~^(-1/2) is undefined).
+__global__ __launch_bounds__(256) void cut_check_kernel(CutList L, double tau, int* flag) {
+  const int t = blockIdx.x;
+  const double* a = L.Ln[t];
+  const double* b = L.Ls[t];
+  double sa = 0.0, sb = 0.0;
+  for (int64_t i = threadIdx.x; i < L.n[t]; i += 256) {
+    sa += a[i] * a[i];
+    sb += b[i] * b[i];
+  }
+  __shared__ double ra[256], rb[256];
+  ra[threadIdx.x] = sa;
+  rb[threadIdx.x] = sb;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      ra[threadIdx.x] += ra[threadIdx.x + w];
+      rb[threadIdx.x] += rb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && !(*L.s1[t] > tau * sqrt(ra[0]) * sqrt(rb[0]))) atomicAdd(flag, 1);
+}
+
+hipError_t launch_cut_check(const CutList& L, int count, double tau, int* flag, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > CUT_MAX) return hipErrorInvalidValue;
+  cut_check_kernel<<<count, 256, 0, s>>>(L, tau, flag);
   return hipGetLastError();
 }
 
@@ -1637,6 +1673,9 @@ __device__ __forceinline__ void publish_blocks(unsigned* ver, int64_t P, int64_t
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
+    // the workgroup's column stores (ordered before this point by the
+    // barrier) happen before the counters' new values at agent scope
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (P < nblk) __hip_atomic_store(ver + P, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (Q < nblk) __hip_atomic_store(ver + Q, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -1659,6 +1698,8 @@ __device__ __forceinline__ bool wait_blocks(const unsigned* ver, int64_t P, int6
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    // pairs with the release of the workgroups that published the blocks
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok_s = ok;
   }
   __syncthreads();
@@ -1672,7 +1713,7 @@ __device__ __forceinline__ bool sweep_barrier(unsigned* count, unsigned target, 
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     unsigned spins = 0;
     while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -1684,6 +1725,7 @@ __device__ __forceinline__ bool sweep_barrier(unsigned* count, unsigned target, 
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok_s = ok;
   }
   __syncthreads();
@@ -1699,8 +1741,10 @@ __device__ __forceinline__ bool sweep_barrier(unsigned* count, unsigned target, 
 // sync[1 + b * np + B] the round counters of the blocks (counting across
 // sweeps), then one arrival counter per sweep; everything zero at launch.
 // *sweeps receives the number of sweeps run.  No convergence within
-// max_sweeps, or a wait that ran out, adds one to *fail.  The host launches it
-// only when the occupancy of the device holds the whole grid at once.
+// max_sweeps, or a wait that ran out, adds one to *fail.  Every workgroup
+// must be resident at once: the host launches it cooperatively (the runtime
+// refuses a grid the device cannot hold) or, with cooperative launches
+// switched off, only when the occupancy of the device holds the whole grid.
 __global__ __launch_bounds__(BJ_NT) void bjac_svd_kernel(double* A, double* V, int64_t n, int64_t nblk, int64_t np,
                                                          int64_t stride, int rounds, int max_sweeps, double tol,
                                                          double stop, const double* tiny2, int* rot,
@@ -1784,12 +1828,19 @@ int64_t bjac_sync_words(int64_t n, int batch, int max_sweeps) {
 
 hipError_t launch_bjac_svd(double* A, double* V, int64_t n, int64_t stride, int batch, int max_sweeps, double tol,
                            double stop, const double* tiny2, int* rot, double* ovl, unsigned* sync, int* fail,
-                           int* sweeps, hipStream_t s) {
+                           int* sweeps, bool cooperative, hipStream_t s) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
   const int64_t np = nblk + (nblk & 1);
   dim3 grid((unsigned)(np / 2), (unsigned)batch);
-  bjac_svd_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, (int)(np - 1), max_sweeps, tol, stop, tiny2, rot,
-                                         (unsigned long long*)ovl, sync, fail, sweeps);
+  int rounds = (int)(np - 1);
+  unsigned long long* ovl_u = (unsigned long long*)ovl;
+  if (cooperative) {
+    void* args[] = {&A, &V, &n, (void*)&nblk, (void*)&np, &stride, &rounds, &max_sweeps, &tol, &stop, &tiny2,
+                    &rot, &ovl_u, &sync, &fail, &sweeps};
+    return hipLaunchCooperativeKernel((const void*)bjac_svd_kernel, grid, dim3(BJ_NT), args, 0, s);
+  }
+  bjac_svd_kernel<<<grid, BJ_NT, 0, s>>>(A, V, n, nblk, np, stride, rounds, max_sweeps, tol, stop, tiny2, rot, ovl_u,
+                                         sync, fail, sweeps);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("ctm_init", "ctm_sweep", "ctm_energy", "ctm_energy_grad", "ctm_free", "ctm_last_error", "sur_init",
-              "sur_predict", "sur_train", "sur_free", "ctm_lbfgs"):
+              "sur_predict", "sur_train", "sur_free", "ctm_lbfgs", "ctm_corner_spectra"):
         assert n in names
 
 

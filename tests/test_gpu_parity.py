@@ -122,7 +122,7 @@ def test_rdm_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dist, see
     assert abs(E - Eo) < 1e-11 * max(1.0, abs(Eo))
 
 
-@pytest.mark.parametrize("name,nt,D,chi,pattern,dist,seed", CASES[:2])
+@pytest.mark.parametrize("name,nt,D,chi,pattern,dist,seed", CASES)
 def test_one_sweep_from_same_environment(ctm_mod, name, nt, D, chi, pattern, dist, seed):
     """One sweep of a random state from a random shared start.
 
@@ -224,16 +224,32 @@ def test_full_size_heis_d9_chi100_weakly_entangled(ctm_mod):
     assert err_s <= 30 * cond_s + 1e-8
 
 
-def test_two_sweeps_from_sites_start(ctm_mod):
+def test_heis_d2_chi8_run_to_convergence(ctm_mod):
+    """The D=2, chi=8 Heisenberg workload (seed 0) from the sites-derived start.
+    Its first sweeps are chaotic (energies far outside the physical range) and
+    the sweep at which the iteration settles depends on rounding: 60 in the
+    oracle, 100 with LAPACK's other SVD driver or A perturbed by 1e-15, 180
+    with 1e-13, and again another sweep here.  The 100-sweep budget therefore
+    ends with CTM_ENOTCONV; run on to delta < 1e-10, the iteration reaches the
+    fixed point of the oracle's own run (tests/golden/heis_d2_chi8_convergence.json)
+    to 1e-8 in the energy."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "heis_d2_chi8_convergence.json")) as f:
+        gold = json.load(f)
     cfg = synth.CONFIGS["heis_d2_chi8"]
     A = synth.config_tensors(cfg, 0)
-    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
-    g.sweep(2)
-    o = OCTM(A, cfg["pattern"], cfg["chi"])
-    o.run(2)
     terms = synth.config_terms(cfg)
-    E, Eo = g.energy(H, terms), oenergy(o, H, terms).item()
-    assert abs(E - Eo) < 1e-8 * max(1.0, abs(Eo))
+    g = ctm_mod.CTM(A, cfg["pattern"], cfg["chi"])
+    n, delta, ok = g.sweep(cfg["sweeps"], tol=cfg["tol"])
+    E100 = g.energy(H, terms)
+    assert not ok and n == cfg["sweeps"] and delta > cfg["tol"]
+    n2, delta, ok = g.sweep(6000, tol=cfg["tol"])
+    E = g.energy(H, terms)
+    print(f"heis_d2_chi8: E(100) {E100:.12f}; converged after {n + n2} sweeps (oracle {gold['nested_sweeps_to_tol']}),"
+          f" E {E:.12f}, oracle {gold['nested_E_converged']:.12f}")
+    assert ok and delta < cfg["tol"]
+    assert abs(E - gold["nested_E_converged"]) < 1e-8
 
 
 @pytest.mark.parametrize("name,sweeps", [("ssm_d6_chi72", 1), ("heis_d4_chi32", 3)])
@@ -429,12 +445,11 @@ def test_neel_and_uniform_product_states(ctm_mod):
 def test_dimer_states(ctm_mod):
     """Columnar dimers (Heisenberg, 2x1 cell) and the orthogonal dimers of the
     Shastry-Sutherland model (2x2 cell), gauge-transformed and perturbed by
-    1e-6 relative noise.  The exact states make the cut matrix M vanish on some
-    bonds, so that their projectors come from rounding noise, the oracle's as
-    much as these kernels' (whose result then depends on the order of every
-    rounding); the perturbation gives every bond weight.  GPU against the oracle
-    on the same perturbed state to 1e-10; against -3/8 per site to 1e-6 (the
-    perturbation itself moves the energy by about 1e-7)."""
+    1e-6 relative noise, from the sites-derived start.  Unperturbed, some cut
+    of these states is empty from that start (test_gpu_boundary); the
+    perturbation gives every bond weight.  GPU against the oracle on the same
+    perturbed state to 1e-10; against -3/8 per site to 1e-6 (the perturbation
+    itself moves the energy by about 1e-7)."""
     rng = np.random.default_rng(4)
     cases = [(synth.gauge_transform(synth.columnar_dimer_tensors(), [[0, 1]], 1), [[0, 1]], 8,
               synth.heisenberg_terms(2, 1), 1e-6),
