@@ -158,6 +158,26 @@ int ctm_energy(ctm_ctx* ctx, const double* H_bond, int n_terms, const ctm_term* 
 int ctm_energy_grad(ctm_ctx* ctx, const double* A, int n_sweeps, const double* H_bond, int n_terms,
                     const ctm_term* terms, double* E, double* dEdA);
 
+/* Gradient of the converged energy E(A) = E(env*(A), A), where env* is the
+ * fixed point of one sweep, env* = f(env*, A) (the fixed-point form of the
+ * derivative of Eq. AD, Sec. IV): by implicit differentiation dE/dA =
+ * dE/dA|_env + lam df/dA with lam = dE/denv + lam df/denv, summed as the
+ * series lam = mu_0 + mu_1 + ..., mu_{k+1} = mu_k df/denv, each term one
+ * reverse pass over a single recorded sweep.  The context's current
+ * environment must be converged (ctm_sweep to a small delta): the gauge rules
+ * (projector column signs, tensor signs) make a converged environment a fixed
+ * point of the sweep entry by entry, and *gap (host, may be NULL) receives
+ * max|f(env) - env| / max|env| of the recorded sweep to check it.  The series
+ * stops once max|mu_k| <= tol * max|mu_1| or after max_iter terms (then
+ * CTM_ENOTCONV, results still written); *iters (host, may be NULL) receives
+ * the number of terms beyond the first.  A (device, optional) replaces the
+ * site tensors first; E (host) receives the energy after the recorded sweep,
+ * dEdA (device, layout of A) the gradient.  The environment is left at the
+ * result of the recorded sweep.  Derivatives of the projectors as in
+ * ctm_energy_grad. */
+int ctm_energy_grad_fp(ctm_ctx* ctx, const double* A, double tol, int max_iter, const double* H_bond, int n_terms,
+                       const ctm_term* terms, double* E, double* dEdA, int* iters, double* gap);
+
 /* Plaquette density matrices of the last ctm_energy call, copied to a host
  * buffer of n * d^8 float64 values in the order of first appearance of the
  * plaquettes in the term list; n (host) receives the count. */

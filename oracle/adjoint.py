@@ -31,7 +31,7 @@ from __future__ import annotations
 import torch
 from torch.utils.checkpoint import checkpoint
 
-from .ctmrg import check_cut, corner_spectra, sweep, truncated_inverse_sqrt
+from .ctmrg import check_cut, corner_spectra, projector_signs, sweep, truncated_inverse_sqrt
 from .network import nested_cell, site_frames
 from .rdm import energy_from_rdms, plaquette_rdm
 
@@ -74,6 +74,12 @@ class Projectors(torch.autograd.Function):
         V = Vh.T
         k, w = truncated_inverse_sqrt(s, chi, cutoff)
         P = (Rs.T @ V[:, :k]) * w
+        # gauge: the signs of the kept pairs (u_k, v_k) (another valid SVD)
+        sg = projector_signs(P)
+        U, V = U.clone(), V.clone()
+        U[:, :k] *= sg
+        V[:, :k] *= sg
+        P = P * sg
         Q = (Rn.T @ U[:, :k]) * w
         ctx.save_for_backward(N, S, Qn @ U, Qs @ V, s, w)
         ctx.k, ctx.eta = k, eta
@@ -168,3 +174,50 @@ def energy_and_grad(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-10, eta
     E, env = energy_after_sweeps(A, pattern, chi, detach_env(env0), n_sweeps, H, terms, cutoff, eta, use_checkpoint)
     (g,) = torch.autograd.grad(E, A)
     return E.item(), g, detach_env(env)
+
+
+def fixed_point_grad(A, pattern, chi, env_star, H, terms, cutoff=1e-10, eta=1e-12, tol=1e-12, max_iter=500):
+    """dE/dA of the converged energy E(A) = E(env*(A), A), where env* = f(env*, A) is the
+    fixed point of the sweep map f (Eq. AD taken at the fixed point; Sec. IV).
+
+    Implicit differentiation of env* = f(env*, A) gives
+        dE/dA = dE/dA|_env + lam df/dA,   lam = dE/denv + lam df/denv,
+    and lam = sum_k mu_k with mu_0 = dE/denv and mu_{k+1} = mu_k df/denv.  Each
+    term is a vector-Jacobian product of one recorded sweep at (env*, A); the
+    series stops once |mu_k| <= tol |mu_0| (it converges where the iteration
+    itself is contracting).  The result is the limit n -> infinity of the
+    gradient of ``energy_after_sweeps`` from env*.  env* must be a fixed point
+    entry by entry (the gauge reading of ``ctmrg``).
+
+    Returns (E, dE/dA, iterations, |f(env*) - env*|_max / |env*|_max).
+    """
+    A = torch.as_tensor(A, dtype=torch.float64).clone().requires_grad_(True)
+    keys = ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4")
+    NY, NX = len(env_star), len(env_star[0])
+    leaves = [env_star[I][J][k].detach().clone().requires_grad_(True)
+              for I in range(NY) for J in range(NX) for k in keys]
+    env = [[{k: leaves[(I * NX + J) * 8 + n] for n, k in enumerate(keys)} for J in range(NX)] for I in range(NY)]
+    frames = site_frames(nested_cell(A, pattern)[0])
+    out = sweep(frames, env, chi, cutoff, proj=projector_fn(eta))
+    outs = [out[I][J][k] for I in range(NY) for J in range(NX) for k in keys]
+    gap = max((o.detach() - l.detach()).abs().max().item() for o, l in zip(outs, leaves)) / \
+        max(l.detach().abs().max().item() for l in leaves)
+    Ly, Lx = len(pattern), len(pattern[0])
+    sites = nested_cell(A, pattern)[0]
+    needed = sorted({(t[0], t[1]) for t in terms})
+    rdms = {p: plaquette_rdm(sites, out, p[0], p[1]) for p in needed}
+    E = energy_from_rdms(rdms, H, terms, Lx * Ly)
+    # first term: dE/dA|_env + mu_0 df/dA (mu_0 = dE/d out) and mu_1 = mu_0 df/denv
+    gs = torch.autograd.grad(E, [A] + leaves, retain_graph=True, allow_unused=True)
+    grad = gs[0].clone()
+    mu = [g if g is not None else torch.zeros_like(l) for g, l in zip(gs[1:], leaves)]
+    norm0 = max(m.abs().max().item() for m in mu)
+    it = 0
+    while it < max_iter and norm0 > 0:
+        it += 1
+        gs = torch.autograd.grad(outs, [A] + leaves, grad_outputs=mu, retain_graph=True, allow_unused=True)
+        grad += gs[0]
+        mu = [g if g is not None else torch.zeros_like(l) for g, l in zip(gs[1:], leaves)]
+        if max(m.abs().max().item() for m in mu) <= tol * norm0:
+            break
+    return E.item(), grad.detach(), it, gap

@@ -27,11 +27,19 @@ Readings of points the paper leaves open (all stated in the design doc as well):
   values below ``cutoff * s_1`` (default 1e-10) get a zero in place of
   s^(-1/2): smaller ones carry directions fixed only by rounding and, with
   weights s^(-1/2), make even weakly entangled states iterate chaotically;
-* every updated tensor is divided by its Frobenius norm;
+* every updated tensor is divided by its Frobenius norm, and its sign is
+  chosen so that its entry of largest magnitude is positive (the first such
+  entry on ties);
 * a sweep is the left, right, up and down moves in that order; the column
   steps of a move go in increasing order in the move's own frame;
 * convergence: delta = max over all corners of the L1 distance between the
   normalised (sum 1) singular-value spectra of consecutive sweeps;
+* gauge: the sign of every kept singular pair (u_k, v_k) of M, which flips
+  column k of both P and Q, is chosen so that the entry of largest magnitude
+  of P's column k is positive (the first such entry on ties): P does not
+  depend on the sign conventions of the QR, so every implementation makes the
+  same choice, and a converged environment is then a fixed point of the
+  sweep entry by entry (which the fixed-point derivative needs);
 * a cut whose bond density matrix rho = N S^T vanishes to working precision
   (largest singular value of M at most 1e-12 |N|_F |S|_F, where rounding
   alone leaves about 1e-16) carries no environment: Lambda~^(-1/2) of Eq. PQ
@@ -96,13 +104,21 @@ def truncated_inverse_sqrt(s, chi, cutoff):
     return k, torch.where(keep, safe.rsqrt(), torch.zeros_like(sk))
 
 
+def projector_signs(P):
+    """+1/-1 per column: the sign of the column's entry of largest magnitude (first on ties; +1 for a zero column)."""
+    idx = P.detach().abs().argmax(dim=0)
+    v = P.detach()[idx, torch.arange(P.shape[1])]
+    return torch.where(v < 0, -torch.ones_like(v), torch.ones_like(v))
+
+
 def bond_projectors(N, S, chi, cutoff):
     """P, Q of Eq. PQ from the half systems N and S of Eq. QRSVD.
 
     N is [a1a2, a5a6] and S is [a3a4, a5a6].  N = Q_n R_n and S = Q_s R_s
     (reduced QR), R_n R_s^T = U Lambda V^T, and with Lambda~ the chi largest
     singular values P = R_s^T V Lambda~^(-1/2), Q = R_n^T U Lambda~^(-1/2);
-    N P Q^T S^T is then the rank-chi truncated SVD of rho = N S^T.
+    N P Q^T S^T is then the rank-chi truncated SVD of rho = N S^T.  Column
+    signs as in ``projector_signs`` (the gauge reading of the module).
     """
     Rn = torch.linalg.qr(N, mode="reduced")[1]
     Rs = torch.linalg.qr(S, mode="reduced")[1]
@@ -112,7 +128,8 @@ def bond_projectors(N, S, chi, cutoff):
     k, w = truncated_inverse_sqrt(s, chi, cutoff)
     P = (Rs.T @ Vh[:k].T) * w
     Q = (Rn.T @ U[:, :k]) * w
-    return P, Q, s
+    sg = projector_signs(P)
+    return P * sg, Q * sg, s
 
 
 def half_systems(sites, env, I, J):
@@ -141,7 +158,10 @@ def half_systems(sites, env, I, J):
 
 
 def normalized(t):
-    return t / torch.linalg.norm(t)
+    """t / |t|_F with the sign that makes its entry of largest magnitude positive (first on ties)."""
+    flat = t.detach().reshape(-1)
+    sg = -1.0 if flat[flat.abs().argmax()] < 0 else 1.0
+    return t * (sg / torch.linalg.norm(t))
 
 
 def left_move(sites, env, chi, cutoff, proj=None, record=None):

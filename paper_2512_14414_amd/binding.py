@@ -44,6 +44,8 @@ def _load():
         "ctm_sweep": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
         "ctm_energy": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D)]),
         "ctm_energy_grad": (I, [P, P, I, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D), P]),
+        "ctm_energy_grad_fp": (I, [P, P, D, I, ctypes.POINTER(D), I, ctypes.POINTER(Term), ctypes.POINTER(D), P,
+                                   ctypes.POINTER(I), ctypes.POINTER(D)]),
         "ctm_last_rdms": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
         "ctm_observables": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
         "ctm_corner_spectra": (I, [P, ctypes.POINTER(D), I64, ctypes.POINTER(I64)]),
@@ -61,7 +63,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("ctm_init", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
-            "ctm_sweep", "ctm_corner_spectra", "ctm_energy", "ctm_energy_grad", "ctm_last_rdms", "ctm_observables",
+            "ctm_sweep", "ctm_corner_spectra", "ctm_energy", "ctm_energy_grad", "ctm_energy_grad_fp", "ctm_last_rdms",
+            "ctm_observables",
             "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
             "ctm_last_error", "ctm_free")
 
@@ -166,6 +169,20 @@ class CTM:
         self._check(LIB.ctm_energy_grad(self._h, aptr, int(n_sweeps), _hbond(H), len(terms), _terms(terms),
                                         ctypes.byref(E), _dptr(g)))
         return E.value, g
+
+    def energy_grad_fp(self, H, terms, tol=1e-12, max_iter=500, A=None):
+        """(E, dE/dA, terms of the series, fixed-point gap, converged) of the converged energy
+        (ctm_energy_grad_fp); the current environment must be converged."""
+        aptr = None
+        if A is not None:
+            self.A = torch.as_tensor(A, dtype=torch.float64).to(self.A.device).contiguous()
+            aptr = _dptr(self.A)
+        g = torch.empty_like(self.A)
+        E, it, gap = ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+        rc = self._check(LIB.ctm_energy_grad_fp(self._h, aptr, tol, max_iter, _hbond(H), len(terms), _terms(terms),
+                                                ctypes.byref(E), _dptr(g), ctypes.byref(it), ctypes.byref(gap)),
+                         allow=(CTM_OK, CTM_ENOTCONV))
+        return E.value, g, it.value, gap.value, rc == CTM_OK
 
     def last_rdms(self, capacity=16):
         d8 = self.d ** 8

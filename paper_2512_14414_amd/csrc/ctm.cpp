@@ -27,6 +27,7 @@
 #include "../../include/ctm.h"
 #include "engine.h"
 #include "kernels.h"
+#include "opt_kernels.h"
 #include "qr_kernels.h"
 
 using namespace ctm;
@@ -83,6 +84,9 @@ struct ctm_ctx {
   int jacobi_max_sweeps = 40;
   bool jacobi_one_launch = true;   // all rounds of a Jacobi sweep in one launch (when the grid fits the device)
   bool jacobi_coop = true;         // launch that kernel cooperatively (co-residency guaranteed by the runtime)
+  int svd_method = 0;              // projector SVD of sweeps that are not differentiated: 0 exact, 1 randomized
+  int rsvd_oversample = 8, rsvd_power = 2;
+  uint64_t rsvd_seed = 0;
   int64_t sweep_capacity = -1;     // workgroups of that launch the device holds at once (-1: not yet asked)
   DBuf spec_prev, spec_cur, dscal;   // spectra and a few device scalars
   bool have_prev = false;
@@ -655,6 +659,69 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   return sweep;
 }
 
+// Leading singular triplets of the r x r column-major matrices M[b] (stride
+// r*r) from a randomized range finder (Halko, Martinsson and Tropp, SIAM Rev.
+// 53 (2011), Algorithms 4.4 and 5.1), the cheaper projectors of the paper's
+// outlook: k = min(chi + oversample, r) columns, the test matrix Omega[i][j] =
+// 2u - 1 with u = (splitmix64(seed, i k + j) >> 11) 2^-53, Y = M Omega and
+// ``power`` passes of Z = M^T Q, Y = M Q(Z), every product orthonormalised by
+// the blocked Householder QR; then B^T = M^T Q = Q_b R_b, the SVD R_b^T =
+// U_r diag(s) V_r^T of the k x k factor by the block Jacobi, and M ~ (Q U_r)
+// diag(s) (Q_b V_r)^T.  Outputs as jacobi_svd: s (k values, then zeros, to the
+// r slots of sv[b]), the kmax leading left and right vectors to U[b], Vk[b]
+// (column-major r x kmax, columns beyond k zero).  M is left unchanged.
+void randomized_svd(ctm_ctx* c, const double* M, int64_t r, int batch, int64_t kmax, double* sv, double* U, double* Vk) {
+  Dev& dev = c->dev;
+  const int m = ctmk::MODE_F64;
+  const int64_t k = std::min<int64_t>(c->chi + c->rsvd_oversample, r);
+  const int64_t rk = r * k;
+  DBuf Om(&dev, (size_t)rk * 8), Q(&dev, (size_t)batch * rk * 8), Z(&dev, (size_t)batch * rk * 8),
+      ones(&dev, (size_t)batch * k * 8);
+  HIP_CHECK(optk::launch_uniform_init_f64((double*)Om.p, rk, c->rsvd_seed, 0, 1.0, dev.stream));
+  fill(dev, view(ones.p, T_F64, {batch * k}, "q"), 1.0);
+  TRef Mv{(void*)M, T_F64, {batch, r, r}, {r * r, 1, r}, "bij"};
+  auto colmaj = [&](void* p, const std::string& lab) { return TRef{p, T_F64, {batch, r, k}, {rk, 1, r}, lab}; };
+  // Y (in place) -> the explicit thin Q factor of its Householder QR, written to ``out``
+  auto orth = [&](DBuf& Y, DBuf& out) {
+    HQR q;
+    q.A = (double*)Y.p; q.m = r; q.n = k; q.rs = 1; q.cs = r; q.stride = rk; q.batch = batch;
+    hqr_factor(dev, q);
+    fill(dev, view(out.p, T_F64, {batch * rk}, "q"), 0.0);
+    copy_into(dev, TRef{out.p, T_F64, {batch, k}, {rk, r + 1}, "bd"}, view(ones.p, T_F64, {batch, k}, "bd"));
+    hqr_apply(dev, q, (double*)out.p, 1, r, rk, k, false);
+  };
+  DBuf Y(&dev, (size_t)batch * rk * 8);
+  contract(dev, m, colmaj(Y.p, "bil"), Mv, view(Om.p, T_F64, {r, k}, "jl"));
+  orth(Y, Q);
+  for (int p = 0; p < c->rsvd_power; ++p) {
+    contract(dev, m, colmaj(Z.p, "bjl"), Mv, colmaj(Q.p, "bil"));
+    orth(Z, Y);   // Y holds Q(Z)
+    contract(dev, m, colmaj(Z.p, "bil"), Mv, colmaj(Y.p, "bjl"));
+    orth(Z, Q);
+  }
+  // B^T = M^T Q = Q_b R_b; the Jacobi SVD of the k x k factor R_b^T
+  contract(dev, m, colmaj(Z.p, "bjl"), Mv, colmaj(Q.p, "bil"));
+  HQR qb;
+  qb.A = (double*)Z.p; qb.m = r; qb.n = k; qb.rs = 1; qb.cs = r; qb.stride = rk; qb.batch = batch;
+  hqr_factor(dev, qb);
+  const int64_t km = std::min(kmax, k);
+  DBuf L(&dev, (size_t)batch * k * k * 8), ss(&dev, (size_t)batch * k * 8), Ur(&dev, (size_t)batch * k * km * 8),
+      Vr(&dev, (size_t)batch * k * km * 8);
+  HIP_CHECK(qrk::launch_extract_rt((const double*)Z.p, 1, r, rk, k, k, (double*)L.p, k * k, batch, dev.stream));
+  jacobi_svd(c, (double*)L.p, k, batch, km, (double*)ss.p, (double*)Ur.p, (double*)Vr.p);
+  // singular values into the r slots of every matrix (zeros beyond k)
+  fill(dev, view(sv, T_F64, {batch * r}, "q"), 0.0);
+  copy_into(dev, TRef{sv, T_F64, {batch, k}, {r, 1}, "bq"}, view(ss.p, T_F64, {batch, k}, "bq"));
+  // U = Q U_r, V = Q_b [V_r; 0]
+  fill(dev, view(U, T_F64, {batch * r * kmax}, "q"), 0.0);
+  fill(dev, view(Vk, T_F64, {batch * r * kmax}, "q"), 0.0);
+  contract(dev, m, TRef{U, T_F64, {batch, r, km}, {r * kmax, 1, r}, "bia"}, colmaj(Q.p, "bil"),
+           TRef{Ur.p, T_F64, {batch, k, km}, {k * km, 1, k}, "bla"});
+  copy_into(dev, TRef{Vk, T_F64, {batch, k, km}, {r * kmax, 1, r}, "bla"},
+            TRef{Vr.p, T_F64, {batch, k, km}, {k * km, 1, k}, "bla"});
+  hqr_apply(dev, qb, Vk, 1, r, r * kmax, km, false);
+}
+
 // Projectors of every row of column step J of frame f (Eqs. PQ, QRSVD), in
 // float64, written to P64/Q64 + I*maxkd*chi as [(chi-leg, site-leg), chi]
 // matrices (the site leg is the down leg of (I, J)).
@@ -782,7 +849,9 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
   }
   side_scope.join();
   // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
-  jacobi_svd(c, (double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
+  if (!rec && c->svd_method == 1) randomized_svd(c, (const double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p,
+                                                 (double*)Vk.p);
+  else jacobi_svd(c, (double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
   {
     // a cut whose bond density matrix vanishes to working precision has no
     // projector (Lambda~^(-1/2) of Eq. PQ is undefined): counted in the flags
@@ -810,6 +879,22 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     const double* wI = (const double*)w.p + (size_t)I * chi;
     contract(dev, m, view(P64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Rv, Vv, 1.0, 0, wI);
     contract(dev, m, view(Q64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Lv, Uv, 1.0, 0, wI);
+  }
+  {
+    // gauge: each kept pair (u_k, v_k) takes the sign that makes the entry of
+    // largest magnitude of P[:, k] positive; P does not depend on the QR's
+    // sign conventions, so the converged environment is a fixed point of the
+    // sweep entry by entry
+    ctmk::SignList sl;
+    std::memset(&sl, 0, sizeof(sl));
+    for (int I = 0; I < a; ++I) {
+      sl.P[I] = P64 + (size_t)I * maxkd * chi;
+      sl.Q[I] = Q64 + (size_t)I * maxkd * chi;
+      sl.U[I] = (double*)Uk.p + (size_t)I * r * kk;
+      sl.V[I] = (double*)Vk.p + (size_t)I * r * kk;
+      sl.kd[I] = kd[I & 1];
+    }
+    HIP_CHECK(ctmk::launch_proj_signs(sl, a, std::min<int64_t>(chi, r), r, dev.stream));
   }
   if (!rec) return;
   // singular vectors of rho = N S^T: U_rho = Q_n [U; 0], V_rho = Q_s [V; 0]
@@ -1392,6 +1477,84 @@ double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, co
   return E;
 }
 
+double device_max_abs(ctm_ctx* c, int type, const void* a, const void* b, int64_t n) {
+  HIP_CHECK(ctmk::launch_max_abs(type, a, b, n, (double*)c->dscal.p + 1, c->dev.stream));
+  double v = 0.0;
+  HIP_CHECK(hipMemcpyAsync(&v, (double*)c->dscal.p + 1, 8, hipMemcpyDeviceToHost, c->dev.stream));
+  HIP_CHECK(hipStreamSynchronize(c->dev.stream));
+  return v;
+}
+
+// dE/dA of the converged energy E(A) = E(env*(A), A), env* = f(env*, A) the
+// fixed point of the sweep map f (Eq. AD taken at the fixed point, Sec. IV).
+// Implicit differentiation gives dE/dA = dE/dA|_env + lam df/dA with
+// lam = dE/denv + lam df/denv, summed as lam = mu_0 + mu_1 + ... (mu_{k+1} =
+// mu_k df/denv).  One sweep from the current environment (which must be the
+// fixed point entry by entry, as the gauge rules of the projectors and the
+// normalisation make a converged one) and the energy after it are recorded
+// once; the first reverse pass gives dE/dA|_env + mu_0 df/dA and mu_1, every
+// further pass over the sweep's operations alone, seeded with mu_k, adds
+// mu_k df/dA and gives mu_{k+1}, until max|mu_k| <= tol max|mu_1|.  The
+// environment is left at the result of the recorded sweep.
+double energy_grad_fp_impl(ctm_ctx* c, const double* H_bond, int n_terms, const ctm_term* terms, double* grad,
+                           double tol, int max_iter, int* iters, double* gap, bool* converged) {
+  Dev& dev = c->dev;
+  const size_t eb = (size_t)c->env_elems * type_size(c->st);
+  const size_t es = type_size(c->st);
+  DBuf final_env(&dev, eb), mu(&dev, eb);
+  DBuf site_adj(&dev, c->site_buf.bytes), env_adj(&dev, eb);
+  HIP_CHECK(hipMemsetAsync(site_adj.p, 0, site_adj.bytes, dev.stream));
+  HIP_CHECK(hipMemsetAsync(env_adj.p, 0, eb, dev.stream));
+  c->tape.begin(&dev);
+  c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
+  c->tape.reg(c->env.p, eb, env_adj.p);
+  for (int f : MOVE_FRAMES) left_move(c, f);
+  const size_t n_sweep_ops = c->tape.ops.size();
+  double E = energy_impl(c, H_bond, n_terms, terms);
+  {
+    TapePause pause(dev);
+    for (size_t idx = 0; idx < c->slot_ptr.size(); ++idx) {
+      const int64_t ne = c->slot_elems(idx);
+      copy_into(dev, view((char*)final_env.p + c->slot_off[idx] * es, c->st, {ne}, "q"),
+                view(c->slot_ptr[idx], c->st, {ne}, "q"));
+    }
+    HIP_CHECK(ctmk::launch_nonfinite(c->st, final_env.p, c->env_elems, (int*)c->flag.p, dev.stream));
+  }
+  const double env_max = device_max_abs(c, c->st, c->env.p, nullptr, c->env_elems);
+  *gap = env_max > 0 ? device_max_abs(c, c->st, final_env.p, c->env.p, c->env_elems) / env_max : 0.0;
+  c->tape.backward();   // dE/dA|_env + mu_0 df/dA into site_adj; mu_1 into env_adj
+  const double norm0 = device_max_abs(c, c->st, env_adj.p, nullptr, c->env_elems);
+  int k = 0;
+  double mk = norm0;
+  while (k < max_iter && mk > tol * norm0) {
+    HIP_CHECK(hipMemcpyAsync(mu.p, env_adj.p, eb, hipMemcpyDeviceToDevice, dev.stream));
+    c->tape.zero_own_adjoints();
+    HIP_CHECK(hipMemsetAsync(env_adj.p, 0, eb, dev.stream));
+    {
+      TapePause pause(dev);
+      for (size_t idx = 0; idx < c->slot_ptr.size(); ++idx) {
+        const int64_t ne = c->slot_elems(idx);
+        copy_into(dev, view(c->tape.adj_ptr(c->slot_ptr[idx]), c->st, {ne}, "q"),
+                  view((char*)mu.p + c->slot_off[idx] * es, c->st, {ne}, "q"));
+      }
+    }
+    c->tape.backward_range(0, n_sweep_ops);   // += mu_k df/dA into site_adj; mu_{k+1} into env_adj
+    ++k;
+    mk = device_max_abs(c, c->st, env_adj.p, nullptr, c->env_elems);
+  }
+  *iters = k;
+  c->tape.clear();
+  HIP_CHECK(hipMemcpyAsync(c->env.p, final_env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
+  c->reset_slot_ptrs();
+  c->have_prev = false;
+  sites_adjoint_to_A(c, site_adj.p, grad);
+  HIP_CHECK(ctmk::launch_nonfinite(T_F64, grad, (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D, (int*)c->flag.p,
+                                   dev.stream));
+  HIP_CHECK(hipStreamSynchronize(dev.stream));
+  *converged = mk <= tol * norm0;
+  return E;
+}
+
 int fail(ctm_ctx* c, const Error& e) {
   if (c) c->err = e.what();
   else g_init_error = e.what();
@@ -1567,6 +1730,30 @@ int ctm_energy_grad(ctm_ctx* c, const double* A, int n_sweeps, const double* H_b
   }
 }
 
+int ctm_energy_grad_fp(ctm_ctx* c, const double* A, double tol, int max_iter, const double* H_bond, int n_terms,
+                       const ctm_term* terms, double* E, double* dEdA, int* iters, double* gap) {
+  if (!c || !H_bond || (n_terms > 0 && !terms) || !E || !dEdA || !(tol >= 0) || max_iter < 0) return CTM_EINVAL;
+  try {
+    if (A) {
+      int64_t nA = (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D;
+      HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
+      build_sites(c);
+    }
+    int k = 0;
+    double g = 0.0;
+    bool conv = false;
+    *E = energy_grad_fp_impl(c, H_bond, n_terms, terms, dEdA, tol, max_iter, &k, &g, &conv);
+    if (iters) *iters = k;
+    if (gap) *gap = g;
+    check_flags(c);
+    return conv ? CTM_OK : CTM_ENOTCONV;
+  } catch (const Error& e) {
+    c->tape.clear();
+    c->reset_slot_ptrs();
+    return fail(c, e);
+  }
+}
+
 int ctm_last_rdms(ctm_ctx* c, double* rho, int capacity, int* n) {
   if (!c || !rho || !n) return CTM_EINVAL;
   try {
@@ -1608,6 +1795,10 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "rowmajor_f32") ctmk::g_rowmajor_f32 = value != 0;
   else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
   else if (k == "jacobi_cooperative") c->jacobi_coop = value != 0;
+  else if (k == "svd_method" && (value == 0 || value == 1)) c->svd_method = (int)value;
+  else if (k == "svd_oversample" && value >= 0 && value <= 4096) c->rsvd_oversample = (int)value;
+  else if (k == "svd_power" && value >= 0 && value <= 16) c->rsvd_power = (int)value;
+  else if (k == "svd_seed" && value >= 0 && value < 9007199254740992.0) c->rsvd_seed = (uint64_t)value;
   else if (k == "energy_precision" && (value == CTM_FP64 || value == CTM_FP32 || value == CTM_BF16)) {
     c->est = value == CTM_FP64 ? T_F64 : T_F32;
     c->emode = value == CTM_BF16 ? ctmk::MODE_BF16 : (value == CTM_FP32 ? ctmk::MODE_F32 : ctmk::MODE_F64);

@@ -247,10 +247,18 @@ void Tape::custom(std::function<void()> f) {
   ops.push_back(std::move(o));
 }
 
-void Tape::backward() {
+void Tape::backward() { backward_range(0, ops.size()); }
+
+void Tape::zero_own_adjoints() {
+  for (auto& kv : bufs)
+    if (kv.second.own && kv.second.adj) HIP_CHECK(hipMemsetAsync(kv.second.adj, 0, kv.second.bytes, dev->stream));
+}
+
+void Tape::backward_range(size_t lo, size_t hi) {
   bool was = on;
   on = false;
-  for (size_t i = ops.size(); i-- > 0;) {
+  if (hi > ops.size()) hi = ops.size();
+  for (size_t i = hi; i-- > lo;) {
     Op& o = ops[i];
     if (o.kind == 0) {
       if (!has(o.c.p)) continue;

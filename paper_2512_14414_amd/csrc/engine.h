@@ -169,6 +169,12 @@ struct Tape {
   void* adj_ptr(const void* p);
   void custom(std::function<void()> f);
   void backward();
+  // Reverse pass over the recorded operations [lo, hi) only; the tape stays
+  // as recorded, so that the range can be run again with other seeds.
+  void backward_range(size_t lo, size_t hi);
+  // Zero every adjoint buffer the tape allocated itself (registered external
+  // adjoints are left to their owner).
+  void zero_own_adjoints();
   void clear();          // frees retained forward buffers and owned adjoints
 };
 

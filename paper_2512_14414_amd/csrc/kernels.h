@@ -77,6 +77,17 @@ hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_normalize(int type, const NormList& L, int count, hipStream_t s);
 hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, double* w, int64_t chi, double cutoff,
                               int batch, hipStream_t st);
+// Rows of a column step whose projector signs are fixed (launch_proj_signs).
+struct SignList {
+  double* P[CUT_MAX];   // kd x chi row-major
+  double* Q[CUT_MAX];
+  double* U[CUT_MAX];   // column-major, r rows, at least chi columns
+  double* V[CUT_MAX];
+  int64_t kd[CUT_MAX];
+};
+// Negates column k < chi of P, Q, U, V of a row when the entry of largest
+// magnitude of P[:, k] (the first on ties) is negative.
+hipError_t launch_proj_signs(const SignList& L, int count, int64_t chi, int64_t r, hipStream_t s);
 // Adds one to *flag for every row whose s_1 <= tau |N|_F |S|_F.
 hipError_t launch_cut_check(const CutList& L, int count, double tau, int* flag, hipStream_t s);
 hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,
@@ -89,6 +100,8 @@ hipError_t launch_spectra_delta(const double* sv, int64_t r, int64_t chi, double
                                 double* delta_out, hipStream_t s);
 
 hipError_t launch_flag_or(const int* src, int n, int* flag, hipStream_t s);
+// *out (device double) = max_i |a_i - b_i| (b == nullptr: max_i |a_i|), a and b of type T_F64 (0) or T_F32.
+hipError_t launch_max_abs(int type, const void* a, const void* b, int64_t n, double* out, hipStream_t s);
 
 hipError_t launch_jacobi_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
                                const double* tiny2, int* rot, hipStream_t s);

@@ -10,6 +10,8 @@
 // or v_mfma_f32_16x16x16bf16_1k (BF16 mode: FP32 data rounded to bfloat16 while
 // staged in LDS, FP32 accumulation).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "kernels.h"
@@ -763,8 +765,42 @@ hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Entry of largest magnitude of x[0..n) in one workgroup of 256 threads, the
+// first one on ties: every thread keeps its first maximum over its strided
+// entries, and the reduction prefers the larger magnitude, then the smaller
+// index.  All threads receive the index.
+template <typename T>
+__device__ int64_t argmax_abs_256(const T* x, int64_t n, double* sv, int64_t* si) {
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double a = fabs((double)x[i]);
+    if (a > best) { best = a; bi = i; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double a = sv[threadIdx.x + w];
+      const int64_t j = si[threadIdx.x + w];
+      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && j < si[threadIdx.x])) {
+        sv[threadIdx.x] = a;
+        si[threadIdx.x] = j;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t r = si[0];
+  __syncthreads();
+  return r;
+}
+
 // Frobenius normalisation of a list of tensors, one workgroup per tensor,
-// sums of squares accumulated in FP64.  Optionally stores the norm.
+// sums of squares accumulated in FP64, and the sign that makes the entry of
+// largest magnitude positive (the first on ties): x <- sign * x / |x|.
+// Optionally stores the signed norm sign * |x| (its reciprocal is the factor
+// the adjoint needs).
 template <typename T>
 __global__ __launch_bounds__(256) void normalize_kernel(NormList L) {
   int t = blockIdx.x;
@@ -773,17 +809,21 @@ __global__ __launch_bounds__(256) void normalize_kernel(NormList L) {
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) { double v = (double)x[i]; s += v * v; }
   __shared__ double red[256];
+  __shared__ int64_t idx[256];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  double nrm = sqrt(red[0]);
-  if (threadIdx.x == 0 && L.norm_out) L.norm_out[t] = nrm;
+  const double nrm = sqrt(red[0]);
+  __syncthreads();
+  const int64_t im = argmax_abs_256(x, n, red, idx);
+  const double sg = (n > 0 && (double)x[im] < 0.0) ? -1.0 : 1.0;
+  if (threadIdx.x == 0 && L.norm_out) L.norm_out[t] = sg * nrm;
   // an updated environment tensor that is zero has lost the whole environment
   if (threadIdx.x == 0 && L.zero_flag && !(nrm > 0.0)) atomicAdd(L.zero_flag, 1);
-  double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  double inv = nrm > 0.0 ? sg / nrm : 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) x[i] = (T)((double)x[i] * inv);
 }
 
@@ -812,6 +852,58 @@ hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, doub
                               int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
   svd_weights_kernel<<<batch, 128, 0, st>>>(s, r, stride_s, w, chi, cutoff, batch);
+  return hipGetLastError();
+}
+
+// Gauge of the projectors: for row t and kept column k, the sign of the entry
+// of largest magnitude of P[:, k] (the first on ties); if negative, column k of
+// P, Q (kd x chi, row-major) and of the singular vectors U, V (column-major,
+// r rows, column stride r) is negated (another valid SVD of M).
+__global__ __launch_bounds__(256) void proj_signs_kernel(SignList L, int64_t chi, int64_t r) {
+  const int k = blockIdx.x, t = blockIdx.y;
+  double* P = L.P[t];
+  const int64_t kd = L.kd[t];
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  // column k of P as a strided sequence: the argmax over a runs on P[a * chi + k]
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t a = threadIdx.x; a < kd; a += 256) {
+    const double v = fabs(P[a * chi + k]);
+    if (v > best) { best = v; bi = a; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double v = sv[threadIdx.x + w];
+      const int64_t j = si[threadIdx.x + w];
+      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x])) {
+        sv[threadIdx.x] = v;
+        si[threadIdx.x] = j;
+      }
+    }
+    __syncthreads();
+  }
+  if (!(P[si[0] * chi + k] < 0.0)) return;   // uniform across the workgroup
+  double* Q = L.Q[t];
+  for (int64_t a = threadIdx.x; a < kd; a += 256) {
+    P[a * chi + k] = -P[a * chi + k];
+    Q[a * chi + k] = -Q[a * chi + k];
+  }
+  double* U = L.U[t] + (int64_t)k * r;
+  double* V = L.V[t] + (int64_t)k * r;
+  for (int64_t i = threadIdx.x; i < r; i += 256) {
+    U[i] = -U[i];
+    V[i] = -V[i];
+  }
+}
+
+hipError_t launch_proj_signs(const SignList& L, int count, int64_t chi, int64_t r, hipStream_t s) {
+  if (count <= 0 || chi <= 0) return hipSuccess;
+  if (count > CUT_MAX) return hipErrorInvalidValue;
+  proj_signs_kernel<<<dim3((unsigned)chi, (unsigned)count), 256, 0, s>>>(L, chi, r);
   return hipGetLastError();
 }
 
@@ -993,6 +1085,39 @@ hipError_t launch_nonfinite(int type, const void* x, int64_t n, int* flag, hipSt
   if (n <= 0) return hipSuccess;
   if (type == 0) nonfinite_kernel<double><<<grid_for(n), 256, 0, s>>>((const double*)x, n, flag);
   else nonfinite_kernel<float><<<grid_for(n), 256, 0, s>>>((const float*)x, n, flag);
+  return hipGetLastError();
+}
+
+// Largest |a_i - b_i| (b == nullptr: largest |a_i|) over n entries, into
+// *out (zero before the launch): per-workgroup maxima combined by an atomic
+// maximum on the bit pattern (non-negative doubles order as their bits).
+template <typename T>
+__global__ __launch_bounds__(256) void max_abs_kernel(const T* a, const T* b, int64_t n, unsigned long long* out) {
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = b ? (double)a[i] - (double)b[i] : (double)a[i];
+    m = fmax(m, fabs(v));
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+hipError_t launch_max_abs(int type, const void* a, const void* b, int64_t n, double* out, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(double), s);
+  if (e != hipSuccess || n <= 0) return e;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  if (type == 0)
+    max_abs_kernel<double><<<(unsigned)blocks, 256, 0, s>>>((const double*)a, (const double*)b, n,
+                                                           (unsigned long long*)out);
+  else
+    max_abs_kernel<float><<<(unsigned)blocks, 256, 0, s>>>((const float*)a, (const float*)b, n,
+                                                          (unsigned long long*)out);
   return hipGetLastError();
 }
 
@@ -1226,8 +1351,9 @@ __global__ __launch_bounds__(256) void normalize_backward_kernel(NormList Y, Nor
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
+  // norm_out holds the signed norm sign * |x| of the forward pass
   double dot = red[0], nrm = Y.norm_out[t];
-  double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  double inv = nrm != 0.0 ? 1.0 / nrm : 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) yb[i] = (T)(((double)yb[i] - (double)y[i] * dot) * inv);
 }
 

@@ -12,6 +12,8 @@ struct DotList {
 };
 
 hipError_t launch_uniform_init(float* p, int64_t n, uint64_t seed, int64_t offset, double bound, hipStream_t s);
+hipError_t launch_uniform_init_f64(double* p, int64_t n, uint64_t seed, int64_t offset, double bound,
+                                   hipStream_t s);
 hipError_t launch_bias_act(float* Z, const float* bias, float* A, int64_t rows, int64_t cols, hipStream_t s);
 hipError_t launch_gelu_backward(const float* Z, const float* dA, float* dZ, int64_t n, hipStream_t s);
 hipError_t launch_colsum(const float* X, int64_t rows, int64_t cols, float* out, hipStream_t s);

@@ -37,6 +37,21 @@ hipError_t launch_uniform_init(float* p, int64_t n, uint64_t seed, int64_t offse
   return hipGetLastError();
 }
 
+// The same draw in float64: p[i] = (2u - 1) * bound (test matrices of the randomized projector SVD).
+__global__ void uniform_init_f64_kernel(double* p, int64_t n, uint64_t seed, int64_t offset, double bound) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double u = (double)(splitmix64(seed, (uint64_t)(offset + i)) >> 11) * 0x1.0p-53;
+    p[i] = (2.0 * u - 1.0) * bound;
+  }
+}
+
+hipError_t launch_uniform_init_f64(double* p, int64_t n, uint64_t seed, int64_t offset, double bound,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  uniform_init_f64_kernel<<<grid_for(n), 256, 0, s>>>(p, n, seed, offset, bound);
+  return hipGetLastError();
+}
+
 // GELU with the exact error function: gelu(z) = z/2 (1 + erf(z / sqrt 2)).
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
