@@ -50,6 +50,19 @@ int sur_set_params(sur_net* net, const float* params);
  * last sur_train call). */
 int sur_predict(sur_net* net, const float* X, int batch, float* y);
 
+/* Allocation-free variant of sur_predict, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and the same result (the same
+ * kernels on the same data): every workspace of the forward pass (hidden
+ * activations, split-K partial sums) is cut from a fixed 16 MiB device array
+ * of the library, one per GPU, held until the process ends; the call makes no
+ * device allocation or free.  CTM_EINVAL (message with the sizes) if the
+ * batch needs more than 16 MiB of workspace (about 3000 inputs of a
+ * 5000 -> 256 -> 256 -> 1 network).  Every call on one GPU shares that array,
+ * and a call's array contents are only valid until the next call on that
+ * GPU: calls that overlap on one GPU (other streams or threads) race. */
+int sur_predict_noalloc(sur_net* net, const float* X, int batch, float* y);
+
 /* Mean squared error (1/n) sum (f(x_i) - t_i)^2 of the raw network output f
  * against targets t (device, n floats; no standardisation) and its gradient
  * (device, sur_param_count floats, flat layout); loss (host) may be NULL. */

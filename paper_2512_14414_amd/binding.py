@@ -264,6 +264,7 @@ def _load_opt():
         "sur_get_params": (I, [P, P]),
         "sur_set_params": (I, [P, P]),
         "sur_predict": (I, [P, P, I, P]),
+        "sur_predict_noalloc": (I, [P, P, I, P]),
         "sur_loss_grad": (I, [P, P, P, I, ctypes.POINTER(F), P]),
         "sur_train": (I, [P, P, P, I, I, F, ctypes.POINTER(F)]),
         "sur_last_error": (ctypes.c_char_p, [P]),
@@ -343,6 +344,14 @@ class Surrogate:
         X = torch.as_tensor(X, dtype=torch.float32).cuda().contiguous()
         y = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
         self._check(LIB.sur_predict(self._h, _fptr(X), X.shape[0], _fptr(y)))
+        torch.cuda.synchronize()
+        return y
+
+    def predict_noalloc(self, X):
+        """sur_predict_noalloc: the prediction with every workspace in the library's fixed scratch array."""
+        X = torch.as_tensor(X, dtype=torch.float32).cuda().contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        self._check(LIB.sur_predict_noalloc(self._h, _fptr(X), X.shape[0], _fptr(y)))
         torch.cuda.synchronize()
         return y
 

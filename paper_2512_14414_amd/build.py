@@ -5,8 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/kernels.hip", "csrc/qr_kernels.hip", "csrc/opt_kernels.hip", "csrc/engine.cpp", "csrc/ctm.cpp", "csrc/surrogate.cpp",
-           "csrc/lbfgs.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/qr_kernels.hip", "csrc/opt_kernels.hip", "csrc/sur_noalloc.hip", "csrc/engine.cpp",
+           "csrc/ctm.cpp", "csrc/surrogate.cpp", "csrc/lbfgs.cpp"]
 OUT = os.path.join(HERE, "libctm.so")
 
 

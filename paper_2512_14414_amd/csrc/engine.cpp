@@ -138,6 +138,15 @@ static void release_all_caches() {
 }
 
 void* Dev::take(size_t bytes) {
+  if (arena) {
+    const size_t off = (arena_used + 255) & ~(size_t)255;
+    const size_t sz = bytes == 0 ? 8 : bytes;
+    if (off > arena_bytes || sz > arena_bytes - off)
+      throw Error(-2, "scratch arena exhausted: " + std::to_string(off + sz) + " bytes needed, " +
+                          std::to_string(arena_bytes) + " available");
+    arena_used = off + sz;
+    return arena + off;
+  }
   if (!pool_ready) {
     retain_pool_memory();
     pool_ready = true;
@@ -163,6 +172,7 @@ void* Dev::take(size_t bytes) {
 }
 
 void Dev::give(void* p) {
+  if (arena && (char*)p >= arena && (char*)p < arena + arena_bytes) return;   // arena blocks are not freed
   auto it = live.find(p);
   if (it == live.end()) {   // not from take(): straight back to the pool
     (void)hipFreeAsync(p, stream);
@@ -446,6 +456,12 @@ void launch_plan(Dev& dev, int mode, const Plan& P, const TRef& C, const TRef& A
 }
 
 }  // namespace
+
+int64_t split_workspace_bytes(int64_t M, int64_t N, int64_t K, int64_t batch, size_t elem) {
+  int64_t kchunk = 0, ksplit = 0;
+  if (M < 1 || N < 1 || K < 1 || batch < 1 || !split_k(M, N, K, batch, kchunk, ksplit)) return 0;
+  return ksplit * batch * M * N * (int64_t)elem;
+}
 
 void contract(Dev& dev, int mode, const TRef& C, const TRef& A, const TRef& B, double alpha, int beta,
               const double* colscale) {

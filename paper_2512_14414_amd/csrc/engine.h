@@ -68,6 +68,11 @@ struct Dev {
   hipStream_t stream = nullptr;
   Tape* tape = nullptr;
   bool pool_ready = false;
+  // Optional caller-provided arena: while set, every block is cut from it
+  // (256-byte aligned, in request order) and frees are ignored; a request
+  // beyond its end throws.  No device allocation is made meanwhile.
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
   std::unordered_map<void*, size_t> live;                    // block -> size class
   std::unordered_map<size_t, std::vector<void*>> cached;     // size class -> free blocks
   Dev();
@@ -80,6 +85,25 @@ struct Dev {
   void give(void* p);          // back to the cache
   void release();              // cached blocks back to the device pool
 };
+
+// Work of a Dev confined to an arena for the lifetime of the scope.
+struct ArenaScope {
+  Dev* d;
+  ArenaScope(Dev* dev, void* p, size_t bytes) : d(dev) {
+    d->arena = (char*)p;
+    d->arena_bytes = bytes;
+    d->arena_used = 0;
+  }
+  ~ArenaScope() {
+    d->arena = nullptr;
+    d->arena_bytes = d->arena_used = 0;
+  }
+};
+
+// Bytes of the split-K partial-sum workspace the contraction planner takes
+// for a product with M x N outputs, a sum of length K over ``batch``
+// matrices and elements of ``elem`` bytes (0 when it does not split K).
+int64_t split_workspace_bytes(int64_t M, int64_t N, int64_t K, int64_t batch, size_t elem);
 
 // Owning device buffer released on the stream.
 struct DBuf {

@@ -9,18 +9,9 @@
 #include "../../include/ctm_opt.h"
 #include "engine.h"
 #include "opt_kernels.h"
+#include "surrogate.h"
 
 using namespace ctm;
-
-struct sur_net {
-  Dev dev;
-  int n_in = 0, width = 0;
-  int64_t np = 0;
-  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
-  DBuf params, stats;
-  std::string err;
-  float* P(int64_t off) { return (float*)params.p + off; }
-};
 
 namespace {
 
@@ -67,6 +58,8 @@ void backward(sur_net* s, const float* X, int64_t B, const Acts& a, const float*
   HIP_CHECK(optk::launch_colsum((const float*)dZ.p, B, w, g + s->ob1, dev.stream));
 }
 
+int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+
 int sfail(sur_net* s, const Error& e) {
   if (s) s->err = e.what();
   else g_sur_error = e.what();
@@ -74,6 +67,26 @@ int sfail(sur_net* s, const Error& e) {
 }
 
 }  // namespace
+
+namespace ctm {
+
+void sur_predict_impl(sur_net* s, const float* X, int64_t batch, float* y) {
+  Acts a;
+  forward(s, X, batch, a);
+  HIP_CHECK(hipMemcpyAsync(y, a.y.p, (size_t)batch * 4, hipMemcpyDeviceToDevice, s->dev.stream));
+  HIP_CHECK(optk::launch_destandardize(y, (int)batch, (const float*)s->stats.p, s->dev.stream));
+}
+
+// The blocks forward() takes, in its order: Z1, A1, the partials of
+// X W1^T, Z2, A2, those of A1 W2^T, y, those of A2 W3.
+int64_t sur_predict_workspace_bytes(int64_t n_in, int64_t width, int64_t batch) {
+  const int64_t act = round256(batch * width * 4);
+  return 4 * act + round256(batch * 4) + round256(split_workspace_bytes(batch, width, n_in, 1, 4)) +
+         round256(split_workspace_bytes(batch, width, width, 1, 4)) +
+         round256(split_workspace_bytes(batch, 1, width, 1, 4));
+}
+
+}  // namespace ctm
 
 extern "C" {
 
@@ -105,6 +118,8 @@ int sur_init(sur_net** out, int n_in, int width, uint64_t seed, void* stream) {
     float st[2] = {0.0f, 1.0f};
     HIP_CHECK(hipMemcpyAsync(s->stats.p, st, 8, hipMemcpyHostToDevice, s->dev.stream));
     HIP_CHECK(hipStreamSynchronize(s->dev.stream));
+    // the scratch of sur_predict_noalloc on this device
+    HIP_CHECK((hipError_t)sur_scratch_setup());
     *out = s;
     return CTM_OK;
   } catch (const Error& e) {
@@ -136,10 +151,7 @@ int sur_set_params(sur_net* s, const float* params) {
 int sur_predict(sur_net* s, const float* X, int batch, float* y) {
   if (!s || !X || !y || batch < 1) return CTM_EINVAL;
   try {
-    Acts a;
-    forward(s, X, batch, a);
-    HIP_CHECK(hipMemcpyAsync(y, a.y.p, (size_t)batch * 4, hipMemcpyDeviceToDevice, s->dev.stream));
-    HIP_CHECK(optk::launch_destandardize(y, batch, (const float*)s->stats.p, s->dev.stream));
+    sur_predict_impl(s, X, batch, y);
     return CTM_OK;
   } catch (const Error& e) { return sfail(s, e); }
 }
