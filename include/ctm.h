@@ -221,6 +221,17 @@ int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
  *                 test on the host.  Both give identical results.  No
  *                 convergence, or a wait between rounds that runs out (waits
  *                 are bounded), fails the call with CTM_ESOLVER when it returns.
+ *   "conv_env"    1 to take the delta of ctm_sweep as max|env_new - env_old| /
+ *                 max|env_old| over all environment entries (meaningful because
+ *                 the gauge rules make a converged environment a fixed point
+ *                 entry by entry; the corner spectra alone stop too early when the
+ *                 corners are of rank one while the edges still move), 0
+ *                 (default) for the corner spectra.
+ *   "svd_method"  0 (default) exact projector SVD; 1 randomized partial SVD
+ *                 (range finder with "svd_oversample" extra columns, default 8,
+ *                 "svd_power" subspace passes, default 2, test matrix from
+ *                 SplitMix64 with "svd_seed", default 0) in sweeps that are not
+ *                 differentiated.
  *   "energy_precision" CTM_FP64, CTM_FP32 or CTM_BF16: the precision of the
  *                 energy's density-matrix contractions (and their adjoints) alone,
  *                 whatever the sweep's (default: that of the context's precision).

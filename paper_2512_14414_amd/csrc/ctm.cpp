@@ -85,6 +85,8 @@ struct ctm_ctx {
   bool jacobi_one_launch = true;   // all rounds of a Jacobi sweep in one launch (when the grid fits the device)
   bool jacobi_coop = true;         // launch that kernel cooperatively (co-residency guaranteed by the runtime)
   int svd_method = 0;              // projector SVD of sweeps that are not differentiated: 0 exact, 1 randomized
+  int conv_env = 0;                // delta of ctm_sweep: 0 corner spectra, 1 largest change of the (gauge-fixed) entries
+  DBuf env_prev;                   // environment before the sweep (conv_env)
   int rsvd_oversample = 8, rsvd_power = 2;
   uint64_t rsvd_seed = 0;
   int64_t sweep_capacity = -1;     // workgroups of that launch the device holds at once (-1: not yet asked)
@@ -1661,14 +1663,23 @@ int ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, double* 
   try {
     double dl = -1.0;
     int n = 0;
+    const size_t eb = (size_t)c->env_elems * type_size(c->st);
+    if (tol > 0 && c->conv_env && !c->env_prev.p) c->env_prev = DBuf(&c->dev, eb);
     // the first delta compares with the spectra of the environment the call starts from
-    if (tol > 0 && !c->have_prev) (void)spectra_delta(c);
+    if (tol > 0 && !c->conv_env && !c->have_prev) (void)spectra_delta(c);
     for (n = 1; n <= max_sweeps; ++n) {
+      if (tol > 0 && c->conv_env)
+        HIP_CHECK(hipMemcpyAsync(c->env_prev.p, c->env.p, eb, hipMemcpyDeviceToDevice, c->dev.stream));
       for (int f : MOVE_FRAMES) left_move(c, f);
       if (c->check_finite)
         HIP_CHECK(ctmk::launch_nonfinite(c->st, c->env.p, c->env_elems, (int*)c->flag.p, c->dev.stream));
       if (tol > 0) {
-        dl = spectra_delta(c);
+        if (c->conv_env) {
+          const double mx = device_max_abs(c, c->st, c->env_prev.p, nullptr, c->env_elems);
+          dl = mx > 0 ? device_max_abs(c, c->st, c->env.p, c->env_prev.p, c->env_elems) / mx : 1e300;
+        } else {
+          dl = spectra_delta(c);
+        }
         check_flags(c);
         if (dl < tol) break;
       }
@@ -1796,6 +1807,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "jacobi_one_launch") c->jacobi_one_launch = value != 0;
   else if (k == "jacobi_cooperative") c->jacobi_coop = value != 0;
   else if (k == "svd_method" && (value == 0 || value == 1)) c->svd_method = (int)value;
+  else if (k == "conv_env" && (value == 0 || value == 1)) c->conv_env = (int)value;
   else if (k == "svd_oversample" && value >= 0 && value <= 4096) c->rsvd_oversample = (int)value;
   else if (k == "svd_power" && value >= 0 && value <= 16) c->rsvd_power = (int)value;
   else if (k == "svd_seed" && value >= 0 && value < 9007199254740992.0) c->rsvd_seed = (uint64_t)value;
@@ -1844,7 +1856,7 @@ void ctm_free(ctm_ctx* c) {
   {
     ctm_ctx* t = c;
     t->A64.reset(); t->site_buf.reset(); t->env.reset(); t->spec_prev.reset(); t->spec_cur.reset();
-    t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset();
+    t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset(); t->env_prev.reset();
   }
   c->tape.clear();
   c->dev.release();

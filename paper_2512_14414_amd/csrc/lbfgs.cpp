@@ -67,7 +67,7 @@ struct Opt {
     int rc = fg(user, x, f, g);
     if (rc != 0) throw Error(rc < 0 ? rc : CTM_EINVAL, "objective returned " + std::to_string(rc));
     ++evals;
-    if (!sur) return;
+    if (!sur || !std::isfinite(*f)) return;
     if (count == cap) {
       int64_t nc = std::max<int64_t>(64, 2 * cap);
       DBuf nX(&dev, (size_t)nc * n * 4), nF(&dev, (size_t)nc * 4);

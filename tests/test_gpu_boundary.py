@@ -7,7 +7,9 @@
   density matrix vanishes (the oracle raises DegenerateCut, the library
   returns CTM_ESOLVER); from a generic start both reach -3/8 per site;
 * the one-launch Jacobi iteration launched cooperatively and plainly gives
-  the same environment bit for bit.
+  the same environment bit for bit;
+* the environment-entry delta (option conv_env) sweep by sweep against the
+  oracle's environments.
 """
 import numpy as np
 import pytest
@@ -119,3 +121,40 @@ def test_cooperative_and_plain_jacobi_launch_match(ctm_mod, name, sweeps):
         envs.append(g.get_env().cpu())
         del g
     assert torch.equal(envs[0], envs[1])
+
+
+def test_env_entry_delta_matches_oracle(ctm_mod):
+    """Option conv_env: the delta of a sweep is max |env_new - env_old| /
+    max |env_old| over every environment entry.  The gauge rules make the
+    oracle's environment equal the library's entry by entry, so the oracle's
+    delta of the same sweeps, computed from its flattened environments, is the
+    reference (bar 1e-8 + 1e-6 delta), on a two-tensor state whose
+    environment settles to 1e-11 in about 200 sweeps (the 2x2 D=3 states of
+    the spectra test converge with a factor ~0.99 per sweep); a call with
+    tol = 1e-9 stops at the first sweep whose own delta is below it."""
+    A = synth.near_product_tensors(2, 2, 2, 6, 0.3)
+    pattern, chi = [[0, 1]], 8
+    g = ctm_mod.CTM(A, pattern, chi)
+    g.set_option("conv_env", 1)
+    o = OCTM(A, pattern, chi)
+    prev = env_to_flat(o.env, o.sites, chi)
+    assert (g.get_env().cpu() - prev).abs().max().item() < 1e-14
+    dg, do = [], []
+    for _ in range(300):
+        _, dgi, _ = g.sweep(1, tol=1e-300)
+        o.run(1)
+        cur = env_to_flat(o.env, o.sites, chi)
+        dg.append(dgi)
+        do.append(((cur - prev).abs().max() / prev.abs().max()).item())
+        prev = cur
+        if do[-1] < 1e-11 and dgi < 1e-11:
+            break
+    err = max(abs(a - b) - 1e-6 * b for a, b in zip(dg, do))
+    print(f"env delta per sweep, {len(do)} sweeps: first {do[0]:.3e}, last gpu {dg[-1]:.3e} oracle {do[-1]:.3e}; "
+          f"max |d_gpu - d_oracle| - 1e-6 d_oracle = {err:.2e}")
+    assert err < 1e-8 and do[-1] < 1e-11
+    n_own = next(i for i, v in enumerate(dg) if v < 1e-9) + 1
+    g2 = ctm_mod.CTM(A, pattern, chi)
+    g2.set_option("conv_env", 1)
+    n, delta, ok = g2.sweep(len(dg), tol=1e-9)
+    assert ok and n == n_own and delta == dg[n - 1]
