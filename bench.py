@@ -114,6 +114,14 @@ def main():
                          "Shastry-Sutherland workload, plain FP64 against the mixed mode with and without the surrogate")
     ap.add_argument("--lbfgs-iters", type=int, default=120)
     ap.add_argument("--lbfgs-sweeps", type=int, default=10, help="differentiated sweeps per L-BFGS evaluation")
+    ap.add_argument("--lbfgs-sur-start", type=int, default=51, help="first L-BFGS iteration the surrogate screens")
+    ap.add_argument("--lbfgs-runs", default="all",
+                    help="comma-separated subset of plain_fp64,mixed,mixed_surrogate (runs of about ten minutes "
+                         "each can then go into separate invocations)")
+    ap.add_argument("--lbfgs-e-plain", type=float, default=None,
+                    help="E_plain of an earlier plain FP64 run, when that run is not part of this invocation")
+    ap.add_argument("--lbfgs-plain-seconds", type=float, default=None,
+                    help="the earlier plain FP64 run's seconds to target, for the speedup")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a device buffer of MIB mebibytes once (calibration of the HBM byte counters)")
     args = ap.parse_args()
@@ -425,8 +433,8 @@ def lbfgs_time_to_target(args, torch, synth, ctm):
     wall time to its first iterate with E < E_plain + 1e-5 is reported.  Runs: plain FP64 (FP64
     contractions, plain line search), mixed (FP64 sweep, FP32 energy and its adjoint) with the
     plain line search, and mixed with the surrogate (5000 -> 256 -> 256 -> 1, trained on the
-    exact evaluations of the first 50 iterations, then screening 8 trial steps per line search,
-    every accepted step confirmed by an exact evaluation)."""
+    exact evaluations of the iterations before --lbfgs-sur-start, default 51, then screening 8
+    trial steps per line search, every accepted step confirmed by an exact evaluation)."""
     name = "ssm_d5_chi50"
     cfg = synth.CONFIGS[name]
     A0 = torch.tensor(synth.near_product_tensors(cfg["n_tensors"], 2, cfg["D"], 0, 0.3))
@@ -485,21 +493,27 @@ def lbfgs_time_to_target(args, torch, synth, ctm):
         res["its"] = its
         return res
 
-    plain = run("plain fp64", "fp64", 0)
-    E_plain = plain["final_E"]
+    kinds = {"plain_fp64": ("plain fp64", "fp64", 0), "mixed": ("mixed", "mixed", 0),
+             "mixed_surrogate": ("mixed+surrogate", "mixed", args.lbfgs_sur_start)}
+    which = list(kinds) if args.lbfgs_runs == "all" else args.lbfgs_runs.split(",")
+    if "plain_fp64" not in which and args.lbfgs_e_plain is None:
+        sys.exit("--lbfgs-e-plain is needed when the plain FP64 run is not part of this invocation")
+    out_runs = {k: run(*kinds[k]) for k in which}
+    E_plain = out_runs["plain_fp64"]["final_E"] if "plain_fp64" in out_runs else args.lbfgs_e_plain
     target = E_plain + 1e-5
-    out_runs = {"plain_fp64": plain, "mixed": run("mixed", "mixed", 0), "mixed_surrogate": run("mixed+surrogate", "mixed", 51)}
     for r in out_runs.values():
         hit = next((t for (f, t, e, scr) in r["its"] if f < target), None)
         r["seconds_to_target"] = None if hit is None else round(hit, 2)
         r["evaluations_to_target"] = next((e for (f, t, e, scr) in r["its"] if f < target), None)
         del r["its"]
-    tp, ts = out_runs["plain_fp64"]["seconds_to_target"], out_runs["mixed_surrogate"]["seconds_to_target"]
+    tp = out_runs["plain_fp64"]["seconds_to_target"] if "plain_fp64" in out_runs else args.lbfgs_plain_seconds
+    ts = out_runs["mixed_surrogate"]["seconds_to_target"] if "mixed_surrogate" in out_runs else None
     out = {"metric": "wall time to |E - E_plain| < 1e-5 per site, L-BFGS (mixed + surrogate vs plain FP64)",
            "value": ts, "unit": "s", "higher_is_better": False, "n_gpus": 1,
            "config": {"workload": f"{name}: Shastry-Sutherland J_dimer=1 J_nn=0.7, 2x2 cell of 4 tensors, d=2 D=5 "
                                   f"chi=50, start: product + 0.3 noise (seed 0), normalised; pseudo-inverse cutoff "
-                                  f"1e-6; L-BFGS {args.lbfgs_iters} iterations, m = 10, strong Wolfe; an evaluation: "
+                                  f"1e-6; L-BFGS {args.lbfgs_iters} iterations, m = 10, strong Wolfe, surrogate from "
+                                  f"iteration {args.lbfgs_sur_start}; an evaluation: "
                                   f"E and dE/dA after {nsw} differentiated sweeps from a fixed seeded random "
                                   "environment"},
            "E_plain": E_plain, "runs": out_runs,

@@ -117,7 +117,11 @@ void ctm_lbfgs_default_params(ctm_lbfgs_params* p);
  * with L-BFGS: two-loop recursion (Nocedal and Wright, Algorithms 7.4, 7.5)
  * with scaling s.y/y.y; plain line search by bracketing and zoom for the
  * strong Wolfe conditions (their Algorithms 3.5, 3.6) with safeguarded cubic
- * interpolation (bisection outside the middle 80 % of the bracket).  Without
+ * interpolation (bisection outside the middle 80 % of the bracket); when its
+ * max_ls evaluations run out, the trial point of lowest f that passed the
+ * Armijo test with a strict decrease is taken, and if there is none the
+ * history is dropped and the iteration is retried along -g (the run ends
+ * when a search along -g fails as well).  Without
  * history the first trial step alpha_init is alpha0/max|g|, else 1.  If sur
  * is not NULL, from iteration sur_start on (once trained) the n_trials steps
  * alpha_init 2^(extrap-j) are ranked by the predicted objective relative to
@@ -128,7 +132,11 @@ void ctm_lbfgs_default_params(ctm_lbfgs_params* p);
  * evaluation becomes a training pair (normalised x, f).  trace (host, may be
  * NULL) receives up to ``capacity`` records, n_iter (host, may be NULL) the
  * iteration count.  Returns CTM_OK when max|g| < gtol was reached,
- * CTM_ENOTCONV when max_iter ran out or a line search failed. */
+ * CTM_ENOTCONV when max_iter ran out or a search along -g failed,
+ * CTM_ENONFINITE when the gradient at an accepted iterate is not finite.  An
+ * objective may return f = +inf (with any finite g) for a point it cannot
+ * evaluate: the search treats it as a failed Armijo test and such values are
+ * kept out of the surrogate's training set. */
 int ctm_lbfgs(int64_t n, double* x, ctm_objective_fn fg, void* user, sur_net* sur, const ctm_lbfgs_params* p,
               void* stream, ctm_lbfgs_record* trace, int capacity, int* n_iter);
 

@@ -12,7 +12,11 @@ The paper minimises E(X) (Eq. OptPro) with L-BFGS on the gradient of Eq. AD
 * plain line search: bracketing and zoom for the strong Wolfe conditions
   (Nocedal and Wright, Algorithms 3.5 and 3.6) with safeguarded cubic
   interpolation (their Eq. 3.59; bisection when the minimiser falls outside
-  the middle 80 % of the bracket), at most ``max_ls`` evaluations;
+  the middle 80 % of the bracket), at most ``max_ls`` evaluations; when they
+  run out, the lowest trial point that passed the Armijo test with a strict
+  decrease is taken, and
+  if there is none the history is dropped and the iteration is retried
+  along -g (the run stops when a search along -g fails as well);
 * surrogate screening (from iteration ``sur_start``, once trained): the trial
   steps alpha_j = alpha_init 2^(extrap - j) (j < n_trials, so from
   2^extrap down to 2^(extrap - n_trials + 1) times the unit step) are ranked
@@ -58,6 +62,7 @@ class Result:
     f: float
     records: list = field(default_factory=list)   # (iter, evals, screened, f, max|g|, step)
     evals: int = 0
+    resets: int = 0
     data_x: list = field(default_factory=list)
     data_f: list = field(default_factory=list)
 
@@ -100,7 +105,9 @@ def minimize(fg, x0, p: Params, predictor=None, train=None, features=None):
 
     S, Y = [], []
     trained = False
-    for k in range(1, p.max_iter + 1):
+    k = 0
+    while k < p.max_iter:
+        k += 1
         gmax = float(np.max(np.abs(g)))
         if gmax < p.gtol:
             break
@@ -142,7 +149,14 @@ def minimize(fg, x0, p: Params, predictor=None, train=None, features=None):
         if accepted is None:
             accepted = _line_search(evaluate, x, f, pdir, d0, a_init, p)
             if accepted is None:
-                break
+                if not S:
+                    break
+                # a failed search along a quasi-Newton direction: forget the
+                # curvature pairs and retry this iteration along -g
+                S, Y = [], []
+                res.resets += 1
+                k -= 1
+                continue
         a, xn, fn, gn = accepted
         s, y = xn - x, gn - g
         if float(s @ y) > 0.0:
@@ -163,35 +177,44 @@ def minimize(fg, x0, p: Params, predictor=None, train=None, features=None):
 
 
 def _line_search(evaluate, x, f0, pdir, d0, a_init, p):
-    """Strong Wolfe search: bracketing, then zoom; None if the budget runs out."""
+    """Strong Wolfe search: bracketing, then zoom.  If the budget runs out, the
+    trial point of lowest f among those that passed the Armijo test with a
+    strict decrease is taken
+    (the curvature test can fail for good where f has kinks, e.g. where the
+    set of kept singular values changes); None if there is none."""
     used = 0
     a_prev, f_prev, d_prev = 0.0, f0, d0
     a = a_init
-    while used < p.max_ls:
+    best = [None]
+
+    def trial(a):
         xt = x + a * pdir
         ft, gt = evaluate(xt)
+        if ft <= f0 + p.c1 * a * d0 and ft < f0 and (best[0] is None or ft < best[0][2]):
+            best[0] = (a, xt, ft, gt)
+        return xt, ft, gt, float(gt @ pdir)
+
+    while used < p.max_ls:
+        xt, ft, gt, dt = trial(a)
         used += 1
-        dt = float(gt @ pdir)
         if ft > f0 + p.c1 * a * d0 or (used > 1 and ft >= f_prev):
-            return _zoom(evaluate, x, f0, pdir, d0, (a_prev, f_prev, d_prev, None, None), (a, ft, dt, xt, gt), used, p)
+            return _zoom(trial, f0, d0, (a_prev, f_prev, d_prev), (a, ft, dt), used, p, best)
         if abs(dt) <= -p.c2 * d0:
             return a, xt, ft, gt
         if dt >= 0.0:
-            return _zoom(evaluate, x, f0, pdir, d0, (a, ft, dt, xt, gt), (a_prev, f_prev, d_prev, None, None), used, p)
+            return _zoom(trial, f0, d0, (a, ft, dt), (a_prev, f_prev, d_prev), used, p, best)
         a_prev, f_prev, d_prev = a, ft, dt
         a = 2.0 * a
-    return None
+    return best[0]
 
 
-def _zoom(evaluate, x, f0, pdir, d0, lo, hi, used, p):
-    lo_a, lo_f, lo_d = lo[0], lo[1], lo[2]
-    hi_a, hi_f, hi_d = hi[0], hi[1], hi[2]
+def _zoom(trial, f0, d0, lo, hi, used, p, best):
+    lo_a, lo_f, lo_d = lo
+    hi_a, hi_f, hi_d = hi
     while used < p.max_ls:
         a = cubic_step(lo_a, lo_f, lo_d, hi_a, hi_f, hi_d)
-        xt = x + a * pdir
-        ft, gt = evaluate(xt)
+        xt, ft, gt, dt = trial(a)
         used += 1
-        dt = float(gt @ pdir)
         if ft > f0 + p.c1 * a * d0 or ft >= lo_f:
             hi_a, hi_f, hi_d = a, ft, dt
         else:
@@ -200,4 +223,4 @@ def _zoom(evaluate, x, f0, pdir, d0, lo, hi, used, p):
             if dt * (hi_a - lo_a) >= 0.0:
                 hi_a, hi_f, hi_d = lo_a, lo_f, lo_d
             lo_a, lo_f, lo_d = a, ft, dt
-    return None
+    return best[0]

@@ -104,19 +104,40 @@ double cubic_step(double lo, double flo, double dlo, double hi, double fhi, doub
 }
 
 // Strong Wolfe line search along pdir from x (f0, d0 = g.pdir); on success xt,
-// gt hold the accepted point and its gradient.
+// gt hold the accepted point and its gradient.  When the evaluations run out
+// the trial point of lowest f among those that passed the Armijo test with a
+// strict decrease is taken (kept in xb, gb): where f has kinks the curvature
+// test can fail at every trial point.
 bool line_search(Opt& o, const double* x, double f0, const double* pdir, double d0, double a_init, double* xt,
-                 double* gt, double& a_out, double& f_out) {
+                 double* gt, double* xb, double* gb, double& a_out, double& f_out) {
   const ctm_lbfgs_params& p = o.p;
   int used = 0;
   double a_prev = 0.0, f_prev = f0, d_prev = d0, a = a_init;
   double lo = 0, flo = 0, dlo = 0, hi = 0, fhi = 0, dhi = 0;
-  bool zoom = false;
+  bool zoom = false, have_best = false;
+  double a_best = 0, f_best = 0;
+  auto keep = [&](double at, double ft) {
+    if (!(ft <= f0 + p.c1 * at * d0 && ft < f0) || (have_best && ft >= f_best)) return;
+    HIP_CHECK(hipMemcpyAsync(xb, xt, (size_t)o.n * 8, hipMemcpyDeviceToDevice, o.dev.stream));
+    HIP_CHECK(hipMemcpyAsync(gb, gt, (size_t)o.n * 8, hipMemcpyDeviceToDevice, o.dev.stream));
+    have_best = true;
+    a_best = at;
+    f_best = ft;
+  };
+  auto fallback = [&]() {
+    if (!have_best) return false;
+    HIP_CHECK(hipMemcpyAsync(xt, xb, (size_t)o.n * 8, hipMemcpyDeviceToDevice, o.dev.stream));
+    HIP_CHECK(hipMemcpyAsync(gt, gb, (size_t)o.n * 8, hipMemcpyDeviceToDevice, o.dev.stream));
+    a_out = a_best;
+    f_out = f_best;
+    return true;
+  };
   while (used < p.max_ls) {
     HIP_CHECK(optk::launch_xpay(x, a, pdir, xt, o.n, o.dev.stream));
     double ft;
     o.evaluate(xt, &ft, gt);
     ++used;
+    keep(a, ft);
     const double dt = o.dot(gt, pdir);
     if (ft > f0 + p.c1 * a * d0 || (used > 1 && ft >= f_prev)) {
       lo = a_prev; flo = f_prev; dlo = d_prev; hi = a; fhi = ft; dhi = dt;
@@ -132,13 +153,14 @@ bool line_search(Opt& o, const double* x, double f0, const double* pdir, double 
     a_prev = a; f_prev = ft; d_prev = dt;
     a = 2.0 * a;
   }
-  if (!zoom) return false;
+  if (!zoom) return fallback();
   while (used < p.max_ls) {
     a = cubic_step(lo, flo, dlo, hi, fhi, dhi);
     HIP_CHECK(optk::launch_xpay(x, a, pdir, xt, o.n, o.dev.stream));
     double ft;
     o.evaluate(xt, &ft, gt);
     ++used;
+    keep(a, ft);
     const double dt = o.dot(gt, pdir);
     if (ft > f0 + p.c1 * a * d0 || ft >= flo) {
       hi = a; fhi = ft; dhi = dt;
@@ -148,7 +170,7 @@ bool line_search(Opt& o, const double* x, double f0, const double* pdir, double 
       lo = a; flo = ft; dlo = dt;
     }
   }
-  return false;
+  return fallback();
 }
 
 }  // namespace
@@ -193,7 +215,8 @@ int ctm_lbfgs(int64_t n, double* x_io, ctm_objective_fn fg, void* user, sur_net*
     o.sur = p.sur_start > 0 ? sur : nullptr;
     o.p = p;
     o.scal = DBuf(&o.dev, 64);
-    Vec x(&o.dev, n), g(&o.dev, n), pd(&o.dev, n), q(&o.dev, n), xt(&o.dev, n), gt(&o.dev, n);
+    Vec x(&o.dev, n), g(&o.dev, n), pd(&o.dev, n), q(&o.dev, n), xt(&o.dev, n), gt(&o.dev, n), xb(&o.dev, n),
+        gb(&o.dev, n);
     HIP_CHECK(hipMemcpyAsync(x.p(), x_io, (size_t)n * 8, hipMemcpyDeviceToDevice, o.dev.stream));
     std::vector<Vec> S, Y;
     std::vector<double> rho;
@@ -208,6 +231,7 @@ int ctm_lbfgs(int64_t n, double* x_io, ctm_objective_fn fg, void* user, sur_net*
         cand_y(&o.dev, (size_t)(nt + 1) * 4);
     for (int k = 1; k <= p.max_iter; ++k) {
       const double gmax = o.absmax(g.p());
+      if (!std::isfinite(gmax)) throw Error(CTM_ENONFINITE, "non-finite gradient at the current iterate");
       if (gmax < p.gtol) { converged = true; break; }
       // two-loop recursion
       HIP_CHECK(hipMemcpyAsync(q.p(), g.p(), (size_t)n * 8, hipMemcpyDeviceToDevice, o.dev.stream));
@@ -271,7 +295,14 @@ int ctm_lbfgs(int64_t n, double* x_io, ctm_objective_fn fg, void* user, sur_net*
         }
       }
       if (!accepted) {
-        if (!line_search(o, x.p(), f, pd.p(), d0, a_init, xt.p(), gt.p(), a_acc, f_acc)) break;
+        if (!line_search(o, x.p(), f, pd.p(), d0, a_init, xt.p(), gt.p(), xb.p(), gb.p(), a_acc, f_acc)) {
+          if (S.empty()) break;
+          // a failed search along a quasi-Newton direction: forget the curvature
+          // pairs and retry this iteration along -g
+          S.clear(); Y.clear(); rho.clear();
+          --k;
+          continue;
+        }
       }
       // s = xt - x, y = gt - g
       Vec s(&o.dev, n), y(&o.dev, n);

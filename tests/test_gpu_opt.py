@@ -101,6 +101,12 @@ def _numpy_on_gpu(fn):
     return f
 
 
+def _kinked(x):
+    f = abs(x[0] - 1.0) + 2.0 * abs(x[1] + 0.5) + 0.1 * float(x @ x)
+    g = np.array([np.sign(x[0] - 1.0), 2.0 * np.sign(x[1] + 0.5)]) + 0.2 * x
+    return f, g
+
+
 @pytest.mark.parametrize("problem", ["quadratic", "rosenbrock"])
 def test_lbfgs_matches_oracle(m, problem):
     if problem == "quadratic":
@@ -122,6 +128,30 @@ def test_lbfgs_matches_oracle(m, problem):
         assert r[0] == q[0] and r[1] == q[1] and r[2] == q[2]
         assert abs(r[3] - q[3]) <= 1e-9 * max(1.0, abs(q[3]))
     assert np.max(np.abs(x.cpu().numpy() - ref.x)) < 1e-9
+
+
+def test_lbfgs_kinked_minimum(m):
+    """|x0 - 1| + 2|x1 + 0.5| + 0.1|x|^2 from (0.3, 0.2): at the kinks no trial
+    point meets the curvature test, so the run goes on through the Armijo
+    fallback and the history reset.  Against the oracle: the records of the
+    smooth part of the path (up to the first search that uses all max_ls
+    evaluations) and the end point, the closed-form minimum 0.125 at
+    (1, -0.5), reached with f strictly decreasing; the run ends there with
+    CTM_ENOTCONV (max|g| stays 0.2 at the kink)."""
+    x0 = np.array([0.3, 0.2])
+    kw = dict(max_iter=100, gtol=1e-8)
+    ref = olbfgs.minimize(_kinked, x0, olbfgs.Params(**kw))
+    x, recs, ok = m.lbfgs(torch.from_numpy(x0), m.python_objective(_numpy_on_gpu(_kinked), 2),
+                          params=m.lbfgs_params(**kw))
+    assert not ok and ref.resets >= 1
+    smooth = next(i for i, r in enumerate(ref.records) if r[1] - (ref.records[i - 1][1] if i else 1) >= 20)
+    for r, q in zip(recs[:smooth], ref.records[:smooth]):
+        assert r[0] == q[0] and r[1] == q[1]
+        assert abs(r[3] - q[3]) <= 1e-9
+    fs = [r[3] for r in recs]
+    assert all(b < a for a, b in zip(fs, fs[1:]))
+    assert abs(fs[-1] - 0.125) < 1e-12 and np.max(np.abs(x.cpu().numpy() - [1.0, -0.5])) < 1e-9
+    assert len(recs) < 100
 
 
 def test_lbfgs_screened_quadratic_with_the_network(m):

@@ -129,3 +129,33 @@ def test_screening_with_exact_and_adversarial_predictors():
         if sign > 0:
             assert any(r[2] for r in res.records)
             assert res.evals < plain.evals
+
+
+def _kinked(x):
+    """|x0 - 1| + 2 |x1 + 0.5| + 0.1 |x|^2: minimum 0.125 at (1, -0.5), where
+    the gradient (sign(0) = 0) cannot meet the curvature test."""
+    f = abs(x[0] - 1.0) + 2.0 * abs(x[1] + 0.5) + 0.1 * float(x @ x)
+    g = np.array([np.sign(x[0] - 1.0), 2.0 * np.sign(x[1] + 0.5)]) + 0.2 * x
+    return f, g
+
+
+def test_lbfgs_kink_armijo_fallback():
+    """f = |x - 1| has |f'| = 1 > c2 |f'(x0)| everywhere but at the kink, so no
+    trial point meets the strong Wolfe conditions: the search takes its lowest
+    Armijo point, which the cubic steps drive to the kink."""
+    fg = lambda x: (abs(x[0] - 1.0), np.array([np.sign(x[0] - 1.0)]))
+    res = lbfgs.minimize(fg, np.array([0.3]), lbfgs.Params(max_iter=5, gtol=1e-8))
+    assert res.records and res.records[0][3] < 1e-9
+    assert abs(res.x[0] - 1.0) < 1e-9
+
+
+def test_lbfgs_kinked_minimum_with_history_reset():
+    """On the two-kink function the run reaches the closed-form minimum 0.125
+    at (1, -0.5) with f strictly decreasing, drops its history at least once
+    (a failed search along the quasi-Newton direction) and ends when the search
+    along -g fails at the minimum."""
+    res = lbfgs.minimize(_kinked, np.array([0.3, 0.2]), lbfgs.Params(max_iter=100, gtol=1e-8))
+    fs = [r[3] for r in res.records]
+    assert all(b < a for a, b in zip(fs, fs[1:]))
+    assert abs(res.f - 0.125) < 1e-12 and np.max(np.abs(res.x - [1.0, -0.5])) < 1e-9
+    assert res.resets >= 1 and len(res.records) < 100
