@@ -96,6 +96,22 @@ typedef struct {
 int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
              int n_tensors, int precision, void* stream);
 
+/* The conventional double-layer method that the nested one is compared with
+ * (Eq. Tred; Appendix, Fig. SM-Compare): a context over the Lx x Ly lattice
+ * of reduced tensors a_t[(l l'), (u u'), (r r'), (d d')] = sum_s A_t[s,l,u,r,d]
+ * A_t[s,l',u',r',d'] (legs of dimension D^2, ket index major), formed on the
+ * device from A with the same arguments, ownership and errors as ctm_init.
+ * The sweep, its options, the projectors (now of (chi D^2) x chi; the
+ * randomized partial SVD of option "svd_method" suits these larger cuts), the
+ * convergence measures and the environment layout (Lx*Ly positions, T legs
+ * of dimension D^2) are those of the nested context; ctm_energy, ctm_last_rdms
+ * and ctm_observables contract each plaquette quadrant with the ket and then
+ * the bra tensor of its site, without forming the open reduced tensor.
+ * ctm_energy_grad and ctm_energy_grad_fp return CTM_EINVAL on such a context.
+ * Requires chi >= D*D. */
+int ctm_init_double_layer(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
+                          int n_tensors, int precision, void* stream);
+
 /* Replace the site tensors (device, same shape as in ctm_init); the environment is kept. */
 int ctm_set_tensors(ctm_ctx* ctx, const double* A);
 

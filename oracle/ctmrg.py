@@ -28,15 +28,17 @@ Readings of points the paper leaves open (all stated in the design doc as well):
   s^(-1/2): smaller ones carry directions fixed only by rounding and, with
   weights s^(-1/2), make even weakly entangled states iterate chaotically;
 * every updated tensor is divided by its Frobenius norm, and its sign is
-  chosen so that its entry of largest magnitude is positive (the first such
-  entry on ties);
+  chosen so that its first entry within a relative 1e-9 (GAUGE_TIE) of the
+  largest magnitude is positive;
 * a sweep is the left, right, up and down moves in that order; the column
   steps of a move go in increasing order in the move's own frame;
 * convergence: delta = max over all corners of the L1 distance between the
   normalised (sum 1) singular-value spectra of consecutive sweeps;
 * gauge: the sign of every kept singular pair (u_k, v_k) of M, which flips
-  column k of both P and Q, is chosen so that the entry of largest magnitude
-  of P's column k is positive (the first such entry on ties): P does not
+  column k of both P and Q, is chosen so that the first entry of P's column
+  k within GAUGE_TIE of its largest magnitude is positive (ties that hold in
+  exact arithmetic, as in every column of the double-layer network's
+  projectors, are then decided the same way whatever the rounding): P does not
   depend on the sign conventions of the QR, so every implementation makes the
   same choice, and a converged environment is then a fixed point of the
   sweep entry by entry (which the fixed-point derivative needs);
@@ -104,9 +106,25 @@ def truncated_inverse_sqrt(s, chi, cutoff):
     return k, torch.where(keep, safe.rsqrt(), torch.zeros_like(sk))
 
 
+# Relative width of a tie in the gauge rules: entries whose magnitudes are
+# equal in exact arithmetic (the ket-bra exchange symmetry of a reduced tensor
+# makes such pairs in every projector column of the double-layer network)
+# differ by rounding only, so the sign is taken from the first entry within
+# this width of the largest magnitude, which does not depend on where the
+# rounding falls.
+GAUGE_TIE = 1e-9
+
+
+def _sign_entry(a):
+    """Index (along dim 0) of the first entry of |a| within GAUGE_TIE of the column maximum."""
+    m = a.max(dim=0).values
+    return (a >= m * (1.0 - GAUGE_TIE)).to(torch.int8).argmax(dim=0)
+
+
 def projector_signs(P):
-    """+1/-1 per column: the sign of the column's entry of largest magnitude (first on ties; +1 for a zero column)."""
-    idx = P.detach().abs().argmax(dim=0)
+    """+1/-1 per column: the sign of the column's first entry within a relative
+    GAUGE_TIE of its largest magnitude (+1 for a zero column)."""
+    idx = _sign_entry(P.detach().abs())
     v = P.detach()[idx, torch.arange(P.shape[1])]
     return torch.where(v < 0, -torch.ones_like(v), torch.ones_like(v))
 
@@ -158,9 +176,10 @@ def half_systems(sites, env, I, J):
 
 
 def normalized(t):
-    """t / |t|_F with the sign that makes its entry of largest magnitude positive (first on ties)."""
+    """t / |t|_F with the sign that makes its first entry within a relative
+    GAUGE_TIE of the largest magnitude positive."""
     flat = t.detach().reshape(-1)
-    sg = -1.0 if flat[flat.abs().argmax()] < 0 else 1.0
+    sg = -1.0 if flat[_sign_entry(flat.abs())] < 0 else 1.0
     return t * (sg / torch.linalg.norm(t))
 
 

@@ -36,6 +36,7 @@ def _load():
     P, I, D, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
     sig = {
         "ctm_init": (I, [ctypes.POINTER(P), P, I, I, I, I, I, ctypes.POINTER(I), I, I, P]),
+        "ctm_init_double_layer": (I, [ctypes.POINTER(P), P, I, I, I, I, I, ctypes.POINTER(I), I, I, P]),
         "ctm_set_tensors": (I, [P, P]),
         "ctm_reset_env": (I, [P]),
         "ctm_env_size": (I64, [P]),
@@ -62,7 +63,7 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ("ctm_init", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
+EXPORTED = ("ctm_init", "ctm_init_double_layer", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
             "ctm_sweep", "ctm_corner_spectra", "ctm_energy", "ctm_energy_grad", "ctm_energy_grad_fp", "ctm_last_rdms",
             "ctm_observables",
             "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
@@ -88,9 +89,12 @@ def _dptr(t: torch.Tensor, dtype=torch.float64):
 
 
 class CTM:
-    """A CTMRG context on the current GPU (one per set of site tensors)."""
+    """A CTMRG context on the current GPU (one per set of site tensors).
 
-    def __init__(self, A, pattern, chi, precision="fp64", stream=None):
+    layout "nested" (ctm_init): the single-layer nested network; "double"
+    (ctm_init_double_layer): the double-layer network of reduced tensors."""
+
+    def __init__(self, A, pattern, chi, precision="fp64", stream=None, layout="nested"):
         A = torch.as_tensor(A, dtype=torch.float64)
         if not A.is_cuda:
             A = A.cuda()
@@ -102,8 +106,10 @@ class CTM:
         flat = (ctypes.c_int * (self.Lx * self.Ly))(*[pattern[y][x] for y in range(self.Ly) for x in range(self.Lx)])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._h = ctypes.c_void_p()
-        rc = LIB.ctm_init(ctypes.byref(self._h), _dptr(self.A), d, D, chi, self.Lx, self.Ly, flat, n_t,
-                          PRECISIONS[precision], ctypes.c_void_p(self.stream.cuda_stream))
+        init = {"nested": LIB.ctm_init, "double": LIB.ctm_init_double_layer}[layout]
+        self.layout = layout
+        rc = init(ctypes.byref(self._h), _dptr(self.A), d, D, chi, self.Lx, self.Ly, flat, n_t,
+                  PRECISIONS[precision], ctypes.c_void_p(self.stream.cuda_stream))
         if rc != CTM_OK:
             raise CTMError(rc, LIB.ctm_last_error(None).decode())
 

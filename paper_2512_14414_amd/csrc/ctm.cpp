@@ -14,6 +14,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -68,6 +69,10 @@ struct ctm_ctx {
   Dev dev;
   rocblas_handle blas = nullptr;
   int d = 0, D = 0, chi = 0, Lx = 0, Ly = 0, nt = 0, prec = 0, NY = 0, NX = 0;
+  // 0: the nested network of K, B, X, Y sites on a 2Ly x 2Lx cell (Sec. II B);
+  // 1: the double-layer network of reduced tensors a = sum_s A A* with legs of
+  //    dimension D^2 on the Ly x Lx cell (Eq. Tred)
+  int layout = 0;
   std::vector<int> pattern;
   int st = T_F64;                 // storage type of sites and environment
   int mode = ctmk::MODE_F64;      // matrix-core path of the sweep's contractions
@@ -118,10 +123,15 @@ struct ctm_ctx {
     HIP_CHECK(hipStreamWaitEvent(dev.stream, ev_join, 0));
   }
 
+  int64_t max_leg() const { return layout ? (int64_t)D * D : (int64_t)D * d; }
   int ny(int f) const { return (f & 1) ? NX : NY; }
   int nx(int f) const { return (f & 1) ? NY : NX; }
   int kind(int I, int J) const { return (I & 1) * 2 + (J & 1); }   // 0 K, 1 Y, 2 X, 3 B
   void leg_dims(int I, int J, int64_t* l) const {
+    if (layout) {
+      l[0] = l[1] = l[2] = l[3] = (int64_t)D * D;
+      return;
+    }
     int64_t Dd = (int64_t)D * d;
     switch (kind(I, J)) {
       case 0: l[0] = D; l[1] = D; l[2] = Dd; l[3] = D; break;
@@ -210,8 +220,49 @@ void build_layout(ctm_ctx* c) {
   c->env_elems = off;
 }
 
+// Reduced tensors a_t[(l l'), (u u'), (r r'), (d d')] = sum_s A_t[s,l,u,r,d] A_t[s,l',u',r',d']
+// (Eq. Tred; real tensors, fused legs ket index major) of every frame.
+void build_sites_double(ctm_ctx* c) {
+  Dev& dev = c->dev;
+  const int d = c->d, D = c->D;
+  const int64_t D2 = (int64_t)D * D, na = D2 * D2 * D2 * D2, nk = (int64_t)d * D * D * D * D;
+  const size_t es = type_size(c->st);
+  if (!c->site_buf.p) c->site_buf = DBuf(&dev, (size_t)(4 * c->nt * na) * es);
+  const std::string lurd = "lurd";
+  Tmp a8(&dev, T_F64, {D, D, D, D, D, D, D, D}, "lLuUrRdD");
+  for (int t = 0; t < c->nt; ++t) {
+    double* At = (double*)c->A64.p + t * nk;
+    contract(dev, ctmk::MODE_F64, a8.t, view(At, T_F64, {d, D, D, D, D}, "slurd"),
+             view(At, T_F64, {d, D, D, D, D}, "sLURD"));
+    for (int f = 0; f < 4; ++f) {
+      std::string rl;
+      for (int i = 0; i < 4; ++i) rl += lurd[(i + f) % 4];   // new axis i = old axis (i+f) mod 4
+      void* dst = (char*)c->site_buf.p + (size_t)(f * c->nt + t) * na * es;
+      copy_into(dev, view(dst, c->st, {D2, D2, D2, D2}, rl), view(a8.buf.p, T_F64, {D2, D2, D2, D2}, lurd));
+    }
+  }
+  for (int f = 0; f < 4; ++f) {
+    int a = c->ny(f), b = c->nx(f);
+    c->frames[f].assign((size_t)a * b, SiteRef());
+    for (int I = 0; I < a; ++I)
+      for (int J = 0; J < b; ++J) {
+        int oi, oj;
+        c->to_orig(f, I, J, oi, oj);
+        int t = c->pattern[(size_t)oi * c->Lx + oj];
+        SiteRef s;
+        s.p = (char*)c->site_buf.p + (size_t)(f * c->nt + t) * na * es;
+        for (int q = 0; q < 4; ++q) s.dim[q] = D2;
+        c->frames[f][(size_t)I * b + J] = s;
+      }
+  }
+}
+
 // Dense nested sites of every frame from the float64 site tensors.
 void build_sites(ctm_ctx* c) {
+  if (c->layout) {
+    build_sites_double(c);
+    return;
+  }
   Dev& dev = c->dev;
   const int d = c->d, D = c->D;
   const int64_t Dd = (int64_t)D * d, n4 = (int64_t)D * D * D * D;
@@ -302,7 +353,7 @@ void build_sites(ctm_ctx* c) {
 void init_env(ctm_ctx* c) {
   Dev& dev = c->dev;
   fill(dev, view(c->env.p, c->st, {c->env_elems}, "e"), 0.0);
-  int64_t mx = (int64_t)c->D * c->d;
+  int64_t mx = c->max_leg();
   Tmp ones(&dev, c->st, {mx, mx}, "pq");
   fill(dev, ones.t, 1.0);
   for (int I = 0; I < c->NY; ++I)
@@ -883,8 +934,9 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     contract(dev, m, view(Q64 + (size_t)I * maxkd * chi, T_F64, {kd[p], chi}, "ak"), Lv, Uv, 1.0, 0, wI);
   }
   {
-    // gauge: each kept pair (u_k, v_k) takes the sign that makes the entry of
-    // largest magnitude of P[:, k] positive; P does not depend on the QR's
+    // gauge: each kept pair (u_k, v_k) takes the sign that makes the first
+    // entry of P[:, k] within a relative 1e-9 of its largest magnitude
+    // positive; P does not depend on the QR's
     // sign conventions, so the converged environment is a fixed point of the
     // sweep entry by entry
     ctmk::SignList sl;
@@ -1053,7 +1105,7 @@ void normalize_all(ctm_ctx* c, const std::vector<TRef>& ts) {
 void left_move(ctm_ctx* c, int f) {
   Dev& dev = c->dev;
   const int a = c->ny(f), b = c->nx(f);
-  const int64_t chi = c->chi, maxkd = chi * c->D * c->d;
+  const int64_t chi = c->chi, maxkd = chi * c->max_leg();
   const int m = c->mode;
   for (int J = 0; J < b; ++J) {
     DBuf P64(&dev, (size_t)a * maxkd * chi * 8), Q64(&dev, (size_t)a * maxkd * chi * 8);
@@ -1197,7 +1249,107 @@ void check_flags(ctm_ctx* c) {
 // (chi D^2)^2 d^4 entries (the column-by-column order carries a strip of
 // chi^2 D^4 d^4 entries and more).  Result:
 // rho[(k_TL k_TR k_BL k_BR), (b_TL b_TR b_BL b_BR)].
+// Plaquette density matrix of the double-layer network (Eq. Tred with the
+// physical indices of the four sites open), with top-left site (px, py).
+// Each quadrant is one corner, its two edges and one site; the site's ket
+// tensor and then its bra tensor are contracted into it one layer at a time
+// (the D^2 legs of the edges split into ket and bra halves), so the open
+// reduced tensor itself (D^8 d^2 entries) is never formed.  Then the upper
+// and the lower pair of quadrants, then the two halves.
+void plaquette_rdm_double(ctm_ctx* c, int px, int py, double* rho_out) {
+  Dev& dev = c->dev;
+  const int m = c->emode;
+  const int est = c->est;
+  std::deque<Tmp> conv;
+  auto in_est = [&](const TRef& t) -> TRef {
+    if (t.type == est) return t;
+    conv.emplace_back(&dev, est, t.dim, t.lab);
+    copy_into(dev, conv.back().t, t);
+    return conv.back().t;
+  };
+  const int64_t D = c->D, d = c->d, nk = d * D * D * D * D;
+  Labels Lb;
+  auto L = [&](const std::string& n) { return Lb(n); };
+  auto str = [](std::initializer_list<char> l) { return std::string(l); };
+  auto env = [&](int r, int cc, int k, const std::string& lab) { return in_est(c->slot(0, py + r, px + cc, k, lab)); };
+  auto site = [&](int r, int cc, const std::string& lab) {
+    const int y = (py + r) % c->Ly, x = (px + cc) % c->Lx;
+    const int t = c->pattern[(size_t)y * c->Lx + x];
+    return in_est(view((double*)c->A64.p + (size_t)t * nk, T_F64, {d, D, D, D, D}, lab));
+  };
+  auto absorb = [&](Tmp& S, const TRef& X) {
+    std::string out;
+    for (char ch : S.t.lab) if (X.lab.find(ch) == std::string::npos) out += ch;
+    std::vector<int64_t> dims;
+    for (char ch : out) dims.push_back(S.t.dim[S.t.lab.find(ch)]);
+    for (size_t q = 0; q < X.lab.size(); ++q)
+      if (S.t.lab.find(X.lab[q]) == std::string::npos) { out += X.lab[q]; dims.push_back(X.dim[q]); }
+    Tmp R(&dev, est, dims, out);
+    contract(dev, m, R.t, S.t, X);
+    S = std::move(R);
+  };
+  auto start = [&](const TRef& corner) {
+    Tmp S(&dev, est, corner.dim, corner.lab);
+    copy_into(dev, S.t, corner);
+    return S;
+  };
+  // a D^2 leg of the running tensor split into its ket (major) and bra halves
+  auto split = [&](Tmp& S, const std::string& fused, const std::string& ket, const std::string& bra) {
+    S.t = split_axis(S.t, L(fused), D, D, L(ket), L(bra));
+  };
+  // one quadrant: corner slot kc with edge slots ke1 and ke2 at position
+  // (r, cc); the site legs (l, u, r, d) are named ``legs``, with suffix k on
+  // the ket tensor and b on the bra tensor; the two legs that meet the edges
+  // (leg1, leg2) are split into those halves first
+  auto quadrant = [&](int r, int cc, int kc, const std::string& cl, int ke1, const std::string& e1,
+                      int ke2, const std::string& e2, const std::string& leg1, const std::string& leg2,
+                      const std::array<std::string, 4>& legs, const std::string& open) {
+    Tmp Q = start(env(r, cc, kc, cl));
+    absorb(Q, env(r, cc, ke1, e1));
+    absorb(Q, env(r, cc, ke2, e2));
+    split(Q, leg1, leg1 + "k", leg1 + "b");
+    split(Q, leg2, leg2 + "k", leg2 + "b");
+    auto lab = [&](const std::string& suffix, const std::string& phys) {
+      std::string o = str({L(phys)});
+      for (const auto& n : legs) o += L(n + suffix);
+      return o;
+    };
+    absorb(Q, site(r, cc, lab("k", "k" + open)));
+    absorb(Q, site(r, cc, lab("b", "b" + open)));
+    return Q;
+  };
+  // chi legs: top t0 t1 t2, right R0 R1 R2, bottom b0 b1 b2, left L0 L1 L2;
+  // D^2 legs between the plaquette's sites: m0 (TL-TR), m1 (BL-BR), n0 (TL-BL), n1 (TR-BR);
+  // D^2 legs to the environment: v0 v1 (top), e0 e1 (right), w0 w1 (bottom), f0 f1 (left)
+  auto cl = [&](const char* a, const char* b) { return str({L(a), L(b)}); };
+  auto el = [&](const char* a, const char* b, const char* e) { return str({L(a), L(b), L(e)}); };
+  Tmp TL = quadrant(0, 0, 0, cl("L0", "t0"), 4, el("t0", "v0", "t1"), 7, el("L1", "f0", "L0"), "f0", "v0",
+                    {"f0", "v0", "m0", "n0"}, "TL");
+  Tmp TR = quadrant(0, 1, 1, cl("t2", "R0"), 4, el("t1", "v1", "t2"), 5, el("R0", "e0", "R1"), "v1", "e0",
+                    {"m0", "v1", "e0", "n1"}, "TR");
+  Tmp BL = quadrant(1, 0, 3, cl("b0", "L2"), 6, el("b1", "w0", "b0"), 7, el("L2", "f1", "L1"), "w0", "f1",
+                    {"f1", "n0", "m1", "w0"}, "BL");
+  Tmp BR = quadrant(1, 1, 2, cl("R2", "b2"), 5, el("R1", "e1", "R2"), 6, el("b2", "w1", "b1"), "e1", "w1",
+                    {"m1", "n1", "e1", "w1"}, "BR");
+  absorb(TL, TR.t);   // over t1 and the ket and bra halves of m0
+  absorb(BL, BR.t);   // over b1 and m1
+  std::string ol;
+  for (const char* n : {"kTL", "kTR", "kBL", "kBR", "bTL", "bTR", "bBL", "bBR"}) ol += L(n);
+  std::vector<int64_t> od(8, d);
+  if (est == T_F64) {
+    contract(dev, m, view(rho_out, T_F64, od, ol), TL.t, BL.t);
+  } else {
+    Tmp r32(&dev, est, od, ol);
+    contract(dev, m, r32.t, TL.t, BL.t);
+    copy_into(dev, view(rho_out, T_F64, od, ol), r32.t);
+  }
+}
+
 void plaquette_rdm(ctm_ctx* c, int px, int py, double* rho_out) {
+  if (c->layout) {
+    plaquette_rdm_double(c, px, py, rho_out);
+    return;
+  }
   Dev& dev = c->dev;
   // the energy's own precision: its environment and site tensors are copied
   // to the energy's storage type first when that differs from the sweep's
@@ -1568,22 +1720,28 @@ int fail(ctm_ctx* c, const Error& e) {
 // =============================================================================
 extern "C" {
 
-int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
-             int n_tensors, int precision, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int init_impl(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
+              int n_tensors, int precision, void* stream, int layout) {
   if (!out) { g_init_error = "out is NULL"; return CTM_EINVAL; }
   *out = nullptr;
   ctm_ctx* c = nullptr;
   try {
     if (!A || !pattern || d < 1 || D < 1 || Lx < 1 || Ly < 1 || n_tensors < 1)
       throw Error(CTM_EINVAL, "invalid dimensions or NULL pointer");
-    if ((int64_t)chi < (int64_t)D * d) throw Error(CTM_EINVAL, "chi must be at least D*d");
+    if (!layout && (int64_t)chi < (int64_t)D * d) throw Error(CTM_EINVAL, "chi must be at least D*d");
+    if (layout && (int64_t)chi < (int64_t)D * D) throw Error(CTM_EINVAL, "chi must be at least D*D");
     if (precision < CTM_FP64 || precision > CTM_MIXED) throw Error(CTM_EINVAL, "unknown precision");
     for (int i = 0; i < Lx * Ly; ++i)
       if (pattern[i] < 0 || pattern[i] >= n_tensors) throw Error(CTM_EINVAL, "pattern id out of range");
     c = new ctm_ctx();
     c->dev.stream = (hipStream_t)stream;
     c->d = d; c->D = D; c->chi = chi; c->Lx = Lx; c->Ly = Ly; c->nt = n_tensors; c->prec = precision;
-    c->NY = 2 * Ly; c->NX = 2 * Lx;
+    c->layout = layout;
+    c->NY = layout ? Ly : 2 * Ly; c->NX = layout ? Lx : 2 * Lx;
     c->pattern.assign(pattern, pattern + Lx * Ly);
     c->st = (precision == CTM_FP64 || precision == CTM_MIXED) ? T_F64 : T_F32;
     c->mode = precision == CTM_BF16 ? ctmk::MODE_BF16 : (precision == CTM_FP32 ? ctmk::MODE_F32 : ctmk::MODE_F64);
@@ -1621,6 +1779,20 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int 
     if (c) ctm_free(c);
     return CTM_EHIP;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
+             int n_tensors, int precision, void* stream) {
+  return init_impl(out, A, d, D, chi, Lx, Ly, pattern, n_tensors, precision, stream, 0);
+}
+
+int ctm_init_double_layer(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
+                          int n_tensors, int precision, void* stream) {
+  return init_impl(out, A, d, D, chi, Lx, Ly, pattern, n_tensors, precision, stream, 1);
 }
 
 int ctm_set_tensors(ctm_ctx* c, const double* A) {
@@ -1726,6 +1898,7 @@ int ctm_energy_grad(ctm_ctx* c, const double* A, int n_sweeps, const double* H_b
                     const ctm_term* terms, double* E, double* dEdA) {
   if (!c || !H_bond || (n_terms > 0 && !terms) || !E || !dEdA || n_sweeps < 0) return CTM_EINVAL;
   try {
+    if (c->layout) throw Error(CTM_EINVAL, "gradients are implemented for the nested network only");
     if (A) {
       int64_t nA = (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D;
       HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
@@ -1745,6 +1918,7 @@ int ctm_energy_grad_fp(ctm_ctx* c, const double* A, double tol, int max_iter, co
                        const ctm_term* terms, double* E, double* dEdA, int* iters, double* gap) {
   if (!c || !H_bond || (n_terms > 0 && !terms) || !E || !dEdA || !(tol >= 0) || max_iter < 0) return CTM_EINVAL;
   try {
+    if (c->layout) throw Error(CTM_EINVAL, "gradients are implemented for the nested network only");
     if (A) {
       int64_t nA = (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D;
       HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));

@@ -85,8 +85,8 @@ struct SignList {
   double* V[CUT_MAX];
   int64_t kd[CUT_MAX];
 };
-// Negates column k < chi of P, Q, U, V of a row when the entry of largest
-// magnitude of P[:, k] (the first on ties) is negative.
+// Negates column k < chi of P, Q, U, V of a row when the first entry of
+// P[:, k] within a relative 1e-9 of the column's largest magnitude is negative.
 hipError_t launch_proj_signs(const SignList& L, int count, int64_t chi, int64_t r, hipStream_t s);
 // Adds one to *flag for every row whose s_1 <= tau |N|_F |S|_F.
 hipError_t launch_cut_check(const CutList& L, int count, double tau, int* flag, hipStream_t s);

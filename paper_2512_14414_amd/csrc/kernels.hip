@@ -765,40 +765,46 @@ hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Entry of largest magnitude of x[0..n) in one workgroup of 256 threads, the
-// first one on ties: every thread keeps its first maximum over its strided
-// entries, and the reduction prefers the larger magnitude, then the smaller
-// index.  All threads receive the index.
+// Relative width of a tie in the gauge rules.  Entries whose magnitudes are
+// equal in exact arithmetic (the ket-bra exchange symmetry of a reduced tensor
+// makes such pairs in every projector column of the double-layer network)
+// differ by rounding only; the sign is taken from the first entry within this
+// width of the largest magnitude, which does not depend on where the rounding
+// falls.
+constexpr double kGaugeTie = 1e-9;
+
+// Index of the sign-deciding entry of x[0], x[stride], ..., x[(n-1) stride] in
+// one workgroup of 256 threads: the largest magnitude m (a max reduction),
+// then the smallest index with |x| >= (1 - kGaugeTie) m (a min reduction);
+// 0 when n = 0.  All threads receive the index.
 template <typename T>
-__device__ int64_t argmax_abs_256(const T* x, int64_t n, double* sv, int64_t* si) {
-  double best = -1.0;
-  int64_t bi = 0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double a = fabs((double)x[i]);
-    if (a > best) { best = a; bi = i; }
-  }
+__device__ int64_t sign_entry_256(const T* x, int64_t n, int64_t stride, double* sv, int64_t* si) {
+  double best = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) best = fmax(best, fabs((double)x[i * stride]));
   sv[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double thr = sv[0] * (1.0 - kGaugeTie);
+  int64_t bi = n;
+  for (int64_t i = threadIdx.x; i < n; i += 256)
+    if (fabs((double)x[i * stride]) >= thr) { bi = i; break; }
   si[threadIdx.x] = bi;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      const double a = sv[threadIdx.x + w];
-      const int64_t j = si[threadIdx.x + w];
-      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && j < si[threadIdx.x])) {
-        sv[threadIdx.x] = a;
-        si[threadIdx.x] = j;
-      }
-    }
+    if (threadIdx.x < w && si[threadIdx.x + w] < si[threadIdx.x]) si[threadIdx.x] = si[threadIdx.x + w];
     __syncthreads();
   }
-  const int64_t r = si[0];
+  const int64_t r = si[0] < n ? si[0] : 0;
   __syncthreads();
   return r;
 }
 
 // Frobenius normalisation of a list of tensors, one workgroup per tensor,
-// sums of squares accumulated in FP64, and the sign that makes the entry of
-// largest magnitude positive (the first on ties): x <- sign * x / |x|.
+// sums of squares accumulated in FP64, and the sign that makes the entry
+// chosen by sign_entry_256 positive: x <- sign * x / |x|.
 // Optionally stores the signed norm sign * |x| (its reciprocal is the factor
 // the adjoint needs).
 template <typename T>
@@ -818,7 +824,7 @@ __global__ __launch_bounds__(256) void normalize_kernel(NormList L) {
   }
   const double nrm = sqrt(red[0]);
   __syncthreads();
-  const int64_t im = argmax_abs_256(x, n, red, idx);
+  const int64_t im = sign_entry_256(x, n, 1, red, idx);
   const double sg = (n > 0 && (double)x[im] < 0.0) ? -1.0 : 1.0;
   if (threadIdx.x == 0 && L.norm_out) L.norm_out[t] = sg * nrm;
   // an updated environment tensor that is zero has lost the whole environment
@@ -856,7 +862,7 @@ hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, doub
 }
 
 // Gauge of the projectors: for row t and kept column k, the sign of the entry
-// of largest magnitude of P[:, k] (the first on ties); if negative, column k of
+// of P[:, k] chosen by sign_entry_256; if negative, column k of
 // P, Q (kd x chi, row-major) and of the singular vectors U, V (column-major,
 // r rows, column stride r) is negated (another valid SVD of M).
 __global__ __launch_bounds__(256) void proj_signs_kernel(SignList L, int64_t chi, int64_t r) {
@@ -865,28 +871,9 @@ __global__ __launch_bounds__(256) void proj_signs_kernel(SignList L, int64_t chi
   const int64_t kd = L.kd[t];
   __shared__ double sv[256];
   __shared__ int64_t si[256];
-  // column k of P as a strided sequence: the argmax over a runs on P[a * chi + k]
-  double best = -1.0;
-  int64_t bi = 0;
-  for (int64_t a = threadIdx.x; a < kd; a += 256) {
-    const double v = fabs(P[a * chi + k]);
-    if (v > best) { best = v; bi = a; }
-  }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      const double v = sv[threadIdx.x + w];
-      const int64_t j = si[threadIdx.x + w];
-      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x])) {
-        sv[threadIdx.x] = v;
-        si[threadIdx.x] = j;
-      }
-    }
-    __syncthreads();
-  }
-  if (!(P[si[0] * chi + k] < 0.0)) return;   // uniform across the workgroup
+  // column k of P is the strided sequence P[a * chi + k], a < kd
+  const int64_t im = sign_entry_256(P + k, kd, chi, sv, si);
+  if (!(P[im * chi + k] < 0.0)) return;   // uniform across the workgroup
   double* Q = L.Q[t];
   for (int64_t a = threadIdx.x; a < kd; a += 256) {
     P[a * chi + k] = -P[a * chi + k];

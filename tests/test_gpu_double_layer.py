@@ -1,0 +1,159 @@
+"""Double-layer CTMRG (Eq. Tred) on the GPU against the oracle's.
+
+ctm_init_double_layer forms the reduced tensors on the device and runs the
+library's sweep on the Lx x Ly lattice of them; its plaquette density
+matrices contract the ket and then the bra tensor into each quadrant.  The
+oracle (oracle/double_layer.py) forms the reduced tensors with einsum and
+runs its generic multi-site sweep on them.  With the gauge rules both
+environments agree entry by entry; compared are the environment after a
+fixed number of sweeps, the delta of every sweep, the energy and the four
+plaquette density matrices, on weakly entangled and uniform random states.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.ctmrg import env_to_flat
+from oracle.double_layer import DoubleLayerCTM, energy as dl_energy, plaquette_rdm as dl_rdm
+
+pytestmark = pytest.mark.gpu
+
+H = synth.heisenberg_bond()
+
+
+@pytest.fixture(scope="module")
+def ctm_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_14414_amd as m
+    return m
+
+
+def _terms(pattern):
+    Ly, Lx = len(pattern), len(pattern[0])
+    if (Lx, Ly) == (2, 2):
+        return synth.shastry_sutherland_terms(0.7, 1.0)
+    return synth.heisenberg_terms(Lx, Ly)
+
+
+CASES = [
+    # name, tensors, D, chi, pattern, sweeps
+    ("np_1x1_D2_chi8", synth.near_product_tensors(1, 2, 2, 5, 0.3), 8, [[0]], 12),
+    ("np_2x2_D3_chi12", synth.near_product_tensors(4, 2, 3, 5, 0.3), 12, [[0, 1], [2, 3]], 12),
+    ("uniform_2x1_D2_chi6", synth.site_tensors(2, 2, 2, 3, "uniform"), 6, [[0, 1]], 6),
+]
+
+
+@pytest.mark.parametrize("name,A,chi,pattern,sweeps", CASES, ids=[c[0] for c in CASES])
+def test_double_layer_sweeps_and_energy_match_oracle(ctm_mod, name, A, chi, pattern, sweeps):
+    """Start environment, delta of every sweep (bar 1e-10 + 1e-6 delta), the
+    environment after the sweeps (1e-10 of its largest entry), the energy
+    (1e-12) and the plaquette density matrices (1e-12 of their largest entry)."""
+    terms = _terms(pattern)
+    g = ctm_mod.CTM(A, pattern, chi, layout="double")
+    o = DoubleLayerCTM(A, pattern, chi)
+    ref0 = env_to_flat(o.env, o.sites, chi)
+    assert g.get_env().cpu().shape == ref0.shape
+    assert (g.get_env().cpu() - ref0).abs().max().item() < 1e-12
+    dg, do = [], []
+    for _ in range(sweeps):
+        _, dgi, _ = g.sweep(1, tol=1e-300)
+        _, doi = o.run(1)
+        dg.append(dgi)
+        do.append(doi)
+    ref = env_to_flat(o.env, o.sites, chi)
+    env_err = (g.get_env().cpu() - ref).abs().max().item() / ref.abs().max().item()
+    E = g.energy(H, terms)
+    Eo = dl_energy(o, H, terms).item()
+    derr = max(abs(a - b) - 1e-6 * b for a, b in zip(dg, do))
+    print(f"{name}: deltas gpu {dg[-1]:.2e} oracle {do[-1]:.2e} (max excess {derr:.1e}); env {env_err:.1e}; "
+          f"E {E:.15f} oracle {Eo:.15f}")
+    assert derr < 1e-10
+    assert env_err < 1e-10
+    assert abs(E - Eo) < 1e-12
+    rhos = g.last_rdms()
+    order = []
+    for t in terms:
+        if (t[0], t[1]) not in order:
+            order.append((t[0], t[1]))
+    for q, (px, py) in enumerate(order):
+        r = dl_rdm(o, px, py)
+        err = (rhos[q] - r).abs().max().item() / r.abs().max().item()
+        assert err < 1e-12, (px, py, err)
+
+
+@pytest.mark.parametrize("precision,bar", [("mixed", 1e-6), ("fp32", 1e-5)])
+def test_double_layer_reduced_precision(ctm_mod, precision, bar):
+    """FP32 storage, or the FP32 density matrices of the mixed mode, against the
+    FP64 oracle after 10 sweeps on the 2x2 D=3 state."""
+    _, A, chi, pattern, _ = CASES[1]
+    terms = _terms(pattern)
+    g = ctm_mod.CTM(A, pattern, chi, precision=precision, layout="double")
+    g.sweep(10)
+    o = DoubleLayerCTM(A, pattern, chi)
+    o.run(10)
+    E, Eo = g.energy(H, terms), dl_energy(o, H, terms).item()
+    print(f"{precision}: E {E:.12f} oracle {Eo:.12f} |dE| {abs(E - Eo):.1e}")
+    assert abs(E - Eo) < bar
+
+
+def test_double_layer_randomized_projectors(ctm_mod):
+    """Randomized partial SVD for the (chi D^2)-sized cuts: converged energy of
+    the 2x2 D=3 state at chi = 18 within 1e-9 of the exact-SVD run, which
+    itself equals the oracle's to 1e-12."""
+    A = synth.near_product_tensors(4, 2, 3, 5, 0.3)
+    pattern, chi = [[0, 1], [2, 3]], 18
+    terms = _terms(pattern)
+    Es = []
+    for method in (0, 1):
+        g = ctm_mod.CTM(A, pattern, chi, layout="double")
+        g.set_option("svd_method", method)
+        n, delta, ok = g.sweep(200, tol=1e-12)
+        assert ok
+        Es.append(g.energy(H, terms))
+        g.close()
+    o = DoubleLayerCTM(A, pattern, chi)
+    o.run(200, tol=1e-12)
+    Eo = dl_energy(o, H, terms).item()
+    print(f"E exact {Es[0]:.14f} randomized {Es[1]:.14f} oracle {Eo:.14f}")
+    assert abs(Es[0] - Eo) < 1e-12
+    assert abs(Es[1] - Es[0]) < 1e-9
+
+
+def test_nested_and_double_layer_energies_approach_each_other(ctm_mod):
+    """Appendix comparison on the correlated seeded one-tensor D=2 state of the
+    oracle's chi-limit pin (product + noise 1.0, seed 2): the library's nested
+    and double-layer energies, each converged to delta < 1e-11, differ by more
+    than 10x less per chi step (4, 8, 16) and by < 5e-9 at chi = 16; the
+    double-layer energy equals the oracle's at every chi."""
+    A = synth.near_product_tensors(1, 2, 2, 2, eps=1.0)
+    pattern = [[0]]
+    terms = synth.heisenberg_terms(1, 1)
+    gaps = []
+    for chi in (4, 8, 16):
+        gd = ctm_mod.CTM(A, pattern, chi, layout="double")
+        assert gd.sweep(400, tol=1e-11)[2]
+        Ed = gd.energy(H, terms)
+        o = DoubleLayerCTM(A, pattern, chi)
+        o.run(400, tol=1e-11)
+        assert abs(Ed - dl_energy(o, H, terms).item()) < 1e-10
+        gn = ctm_mod.CTM(A, pattern, chi)
+        assert gn.sweep(400, tol=1e-11)[2]
+        En = gn.energy(H, terms)
+        gaps.append(abs(En - Ed))
+        print(f"chi {chi}: nested {En:.12f} double {Ed:.12f} |diff| {gaps[-1]:.2e}")
+    for a, b in zip(gaps, gaps[1:]):
+        assert b < a / 10, gaps
+    assert gaps[-1] < 5e-9
+
+
+def test_double_layer_rejects_gradients_and_small_chi(ctm_mod):
+    A = synth.near_product_tensors(1, 2, 3, 0, 0.3)
+    with pytest.raises(ctm_mod.CTMError) as err:
+        ctm_mod.CTM(A, [[0]], 8, layout="double")
+    assert err.value.code == -1 and "D*D" in str(err.value)
+    g = ctm_mod.CTM(A, [[0]], 9, layout="double")
+    with pytest.raises(ctm_mod.CTMError) as err:
+        g.energy_grad(1, H, synth.heisenberg_terms(1, 1))
+    assert err.value.code == -1 and "nested" in str(err.value)
