@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--egrad-sweeps", type=int, default=2)
     ap.add_argument("--no-d9", action="store_true", help="skip the D=9, chi=100 sub-record")
     ap.add_argument("--no-randomized", action="store_true", help="skip the sweeps with randomized projectors")
+    ap.add_argument("--no-double-layer", action="store_true",
+                    help="skip the nested against double-layer sweeps at D=5, chi=50")
     ap.add_argument("--plain-jacobi-launch", action="store_true",
                     help="launch the one-launch Jacobi kernel plainly instead of cooperatively (same results); "
                          "rocprofv3's counter collection does not survive cooperative launches")
@@ -316,6 +318,35 @@ def main():
             h.close()
         log(f"[bench] D=9: {d9}")
 
+    # ---- nested against double-layer CTMRG (Eq. Tred; Appendix) at the D = 5, chi = 50 Shastry-Sutherland
+    # shape: FP64 sweeps from the sites-derived start of the seeded tensors, each network with its own
+    # environment; the double-layer cuts are (chi D^2) = 1250 wide, so both solvers are timed there
+    dl = None
+    if not args.no_double_layer and args.config == "ssm_d6_chi72":
+        c5 = synth.CONFIGS["ssm_d5_chi50"]
+        A5 = synth.config_tensors(c5, 0)
+        t5 = synth.config_terms(c5)
+        dl = {"workload": "ssm_d5_chi50: Shastry-Sutherland J_nn=0.7, 2x2 cell, d=2 D=5 chi=50, seeded "
+                          "uniform[-1,1] tensors, FP64, sites-derived start; 2 untimed + 3 timed sweeps"}
+        E5 = {}
+        for layout, method in (("nested", 0), ("double", 0), ("double", 1)):
+            key = f"{layout}_{'randomized' if method else 'exact'}_svd"
+            h = ctm.CTM(A5, c5["pattern"], c5["chi"], precision="fp64", layout=layout)
+            h.set_option("svd_method", method)
+            h.sweep(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.sweep(3)
+            torch.cuda.synchronize()
+            dl[f"sweeps_per_s_{key}"] = round(3 / (time.perf_counter() - t0), 4)
+            if layout == "double":
+                E5[method] = h.energy(H, t5)
+            h.close()
+        # the two double-layer runs follow the same iteration (the randomized SVD keeps the chi + 8 leading
+        # triplets to its own accuracy); the nested one from this start is still in its chaotic phase
+        dl["dE_double_randomized_vs_exact_after_5_sweeps"] = abs(E5[1] - E5[0])
+        log(f"[bench] nested vs double layer: {dl}")
+
     # ---- roofline of the kernel family with the largest share of the profiled sweep
     fam = max(prof, key=lambda k: prof[k][0])
     ms, impl_flops, launches = prof[fam]
@@ -409,6 +440,7 @@ def main():
         "egrad_speedup_mixed_vs_fp64": None if (em is None or e64 is None) else round(e64 / em, 3),
         "accuracy": accuracy,
         "d9_chi100": d9,
+        "nested_vs_double_layer_d5_chi50": dl,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

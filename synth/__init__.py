@@ -63,6 +63,23 @@ def heisenberg_bond() -> np.ndarray:
     return np.kron(sx, sx) - np.kron(isy, isy) + np.kron(sz, sz)
 
 
+def heisenberg_bond_rotated() -> np.ndarray:
+    """S_a . S_b with site b rotated by pi about the y axis (Sx -> -Sx, Sy -> Sy,
+    Sz -> -Sz): -SxSx + SySy - SzSz, real.  With every nearest-neighbour bond of
+    the square lattice joining the two sublattices, this one bond term on all
+    bonds describes the Heisenberg model after the local rotation -i sigma_y of
+    one sublattice (Discussion), so a Neel-ordered checkerboard state becomes
+    translation invariant and fits a 1x1 cell."""
+    sx, isy, sz = spin_half_ops()
+    return -np.kron(sx, sx) - np.kron(isy, isy) - np.kron(sz, sz)
+
+
+def rotate_physical(A: np.ndarray) -> np.ndarray:
+    """Site tensors with -i sigma_y = [[0, -1], [1, 0]] (real) applied to the physical index."""
+    U = np.array([[0.0, -1.0], [1.0, 0.0]])
+    return np.einsum("st,ntlurd->nslurd", U, A)
+
+
 def heisenberg_terms(Lx: int, Ly: int, J: float = 1.0):
     """Nearest-neighbour terms of H = J sum S_i.S_j on an Lx x Ly cell.
 
