@@ -45,15 +45,15 @@ BOUND = {"fp64": "mfma", "fp32": "mfma", "bf16": "mfma", "jacobi": "alu", "qr_pa
 # HBM traffic per launch of the Jacobi kernel (one launch runs the whole
 # iteration of one batched SVD) from two rocprofv3 --pmc passes over this
 # workload's sweeps (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged
-# over the 16 dispatches of the event-timed sweep: dispatches 113-128 after the
+# over the 16 dispatches of the event-timed sweep, the last 16 of the 128 after the
 # default 2 warm-up and 5 timed sweeps), each scaled by what the counter reads
 # for a copy of known size
 # (bench.py --copy-probe 256: FETCH_SIZE reads half of the bytes copied, so x2;
 # WRITE_SIZE reads them exactly, x1).  Valid for the kernel source it was taken
 # on (hash of the kernel's text), else reported as null.
 TRAFFIC = {"jacobi": {"workload": "ssm_d6_chi72", "precision": "bf16",
-                      "fetch_kib": 2759505.9, "fetch_scale": 2.0, "write_kib": 4929495.3, "write_scale": 1.0,
-                      "source_sha256": "e05ea28b394c17fd4130431c55999845cfc69bc3510d2fd0410744b26dc47cb2",
+                      "fetch_kib": 2776533.9, "fetch_scale": 2.0, "write_kib": 4943883.5, "write_scale": 1.0,
+                      "source_sha256": "364311c3c9921eddbc0bd4fa11f7203f0e24b63a74cf220e7f887c896cc86d9c",
                       "source": ("paper_2512_14414_amd/csrc/kernels.hip", "constexpr int BJ_BW = 8;",
                                  "hipError_t launch_bjac_round(")}}
 KERNEL = {"fp64": "contract_kernel<MODE_F64> (FP64 MFMA)", "fp32": "contract_kernel<MODE_F32> (FP32 MFMA)",
