@@ -237,6 +237,13 @@ int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
  *                 test on the host.  Both give identical results.  No
  *                 convergence, or a wait between rounds that runs out (waits
  *                 are bounded), fails the call with CTM_ESOLVER when it returns.
+ *   "proj_cache"  1 (default): in ctm_energy_grad with n > 1, the forward sweeps
+ *                 that the checkpointed reverse pass recomputes keep their
+ *                 projector blocks (projectors, singular vectors of N S^T,
+ *                 singular values and weights of every cut: about 0.45 GB per
+ *                 sweep at D=6, chi=72), and the recomputation takes them
+ *                 instead of repeating the QR and SVD (same results bit for
+ *                 bit); 0 recomputes them.
  *   "conv_env"    1 to take the delta of ctm_sweep as max|env_new - env_old| /
  *                 max|env_old| over all environment entries (meaningful because
  *                 the gauge rules make a converged environment a fixed point

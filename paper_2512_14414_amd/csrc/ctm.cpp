@@ -63,6 +63,26 @@ struct Labels {
   }
 };
 
+// Saved state of one row's projector block for the reverse pass.
+struct ProjRow {
+  int64_t kd = 0, mn = 0;
+  std::shared_ptr<DBuf> N, S, Ur, Vr, s, w;   // N, S row-major mn x kd; Ur, Vr column-major mn x r
+  void* Nadj = nullptr;                        // forward address of N and S (their adjoints are looked up)
+  void* Sadj = nullptr;
+  double* P = nullptr;                         // forward address of P_I and Q_I (kd x chi row-major)
+  double* Q = nullptr;
+};
+
+// Projector block of one column step of a forward sweep that the reverse
+// pass recomputes: the projectors of every row (as column_projectors writes
+// them) and what the row's adjoint needs besides N and S (U_rho, V_rho, s, w).
+struct ProjCacheStep {
+  int rows = 0;
+  int64_t maxkd = 0;
+  DBuf P, Q;
+  std::vector<ProjRow> saved;
+};
+
 }  // namespace
 
 struct ctm_ctx {
@@ -92,6 +112,14 @@ struct ctm_ctx {
   int svd_method = 0;              // projector SVD of sweeps that are not differentiated: 0 exact, 1 randomized
   int conv_env = 0;                // delta of ctm_sweep: 0 corner spectra, 1 largest change of the (gauge-fixed) entries
   DBuf env_prev;                   // environment before the sweep (conv_env)
+  // Checkpointed reverse pass: the forward sweeps that are recomputed keep
+  // their projector blocks (pc_fill), and the recomputation takes them
+  // instead of factorising again (pc_use, consumed in order from pc_pos);
+  // the recomputed half systems, QR and SVD would give the same bits.
+  int proj_cache = 1;
+  std::vector<ProjCacheStep>* pc_fill = nullptr;
+  std::vector<ProjCacheStep>* pc_use = nullptr;
+  size_t pc_pos = 0;
   int rsvd_oversample = 8, rsvd_power = 2;
   uint64_t rsvd_seed = 0;
   int64_t sweep_capacity = -1;     // workgroups of that launch the device holds at once (-1: not yet asked)
@@ -798,15 +826,6 @@ void randomized_svd(ctm_ctx* c, const double* M, int64_t r, int batch, int64_t k
 // cut carries no weight (rounding alone leaves about 1e-16).
 constexpr double kEmptyCut = 1e-12;
 
-struct ProjRow {
-  int64_t kd = 0, mn = 0;
-  std::shared_ptr<DBuf> N, S, Ur, Vr, s, w;   // N, S row-major mn x kd; Ur, Vr column-major mn x r
-  void* Nadj = nullptr;                        // forward address of N and S (their adjoints are looked up)
-  void* Sadj = nullptr;
-  double* P = nullptr;                         // forward address of P_I and Q_I (kd x chi row-major)
-  double* Q = nullptr;
-};
-
 void proj_backward(ctm_ctx* c, const ProjRow& R, int64_t r);
 
 void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64_t maxkd) {
@@ -832,11 +851,16 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     if (cnt[p]) NS[p] = DBuf(&dev, (size_t)2 * cnt[p] * kd[p] * mn[p] * 8);
   auto Nptr = [&](int p, int b) { return (double*)NS[p].p + (size_t)b * kd[p] * mn[p]; };
   auto Sptr = [&](int p, int b) { return (double*)NS[p].p + (size_t)(cnt[p] + b) * kd[p] * mn[p]; };
-  const int64_t kk = rec ? r : chi;   // singular vectors kept per row
+  // a recomputed sweep takes its projector block from the forward pass
+  // (recorded, so one device stream); a forward sweep that will be
+  // recomputed keeps all r triplets and U_rho, V_rho as a recorded one does
+  std::vector<ProjCacheStep>* use = rec ? c->pc_use : nullptr;
+  std::vector<ProjCacheStep>* keep = rec ? nullptr : c->pc_fill;
+  const int64_t kk = (rec || keep) ? r : chi;   // singular vectors kept per row
   HQR qr[2];
   DBuf L[2];   // R^T of N (first cnt) and S (next cnt): column-major kd x r
   DBuf Mb, sv, Uk, Vk, w;
-  {
+  if (!use) {
     TapePause hold(dev);   // workspaces of the projector block, not recorded buffers
     Mb = DBuf(&dev, (size_t)a * r * r * 8);
     sv = DBuf(&dev, (size_t)a * r * 8);
@@ -859,7 +883,7 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     half_systems(c, p ? pdev1 : dev, f, I, J, Nptr(p, b), Sptr(p, b));
   }
   TapePause pause(dev);   // the block below is one recorded operation
-  std::vector<ProjRow> rows(rec ? a : 0);
+  std::vector<ProjRow> rows((rec || keep) ? a : 0);
   if (rec)
     for (int I = 0; I < a; ++I) {
       int p = I & 1, b = I >> 1;
@@ -875,6 +899,24 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
       R.P = P64 + (size_t)I * maxkd * chi;
       R.Q = Q64 + (size_t)I * maxkd * chi;
     }
+  if (use) {
+    if (c->pc_pos >= use->size()) throw Error(CTM_EINVAL, "projector cache: recomputed sweep out of step");
+    const ProjCacheStep& st = (*use)[c->pc_pos++];
+    if (st.rows != a || st.maxkd != maxkd) throw Error(CTM_EINVAL, "projector cache: recomputed sweep out of step");
+    const size_t pb = (size_t)a * maxkd * chi * 8;
+    HIP_CHECK(hipMemcpyAsync(P64, st.P.p, pb, hipMemcpyDeviceToDevice, dev.stream));
+    HIP_CHECK(hipMemcpyAsync(Q64, st.Q.p, pb, hipMemcpyDeviceToDevice, dev.stream));
+    for (int I = 0; I < a; ++I) {
+      rows[I].Ur = st.saved[I].Ur;
+      rows[I].Vr = st.saved[I].Vr;
+      rows[I].s = st.saved[I].s;
+      rows[I].w = st.saved[I].w;
+    }
+    c->tape.custom([c, rows, r]() {
+      for (const ProjRow& R : rows) proj_backward(c, R, r);
+    });
+    return;
+  }
   {
     Dev* fdev[2];
     HQR* fq[2];
@@ -902,8 +944,8 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
   }
   side_scope.join();
   // rows are interleaved by parity in Mb: row I at I*r*r (p + 2b)
-  if (!rec && c->svd_method == 1) randomized_svd(c, (const double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p,
-                                                 (double*)Vk.p);
+  if (!rec && !keep && c->svd_method == 1)
+    randomized_svd(c, (const double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
   else jacobi_svd(c, (double*)Mb.p, r, a, kk, (double*)sv.p, (double*)Uk.p, (double*)Vk.p);
   {
     // a cut whose bond density matrix vanishes to working precision has no
@@ -950,7 +992,7 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     }
     HIP_CHECK(ctmk::launch_proj_signs(sl, a, std::min<int64_t>(chi, r), r, dev.stream));
   }
-  if (!rec) return;
+  if (!rec && !keep) return;
   // singular vectors of rho = N S^T: U_rho = Q_n [U; 0], V_rho = Q_s [V; 0]
   for (int p = 0; p < 2; ++p) {
     if (!cnt[p]) continue;
@@ -981,6 +1023,19 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
     R.w = std::make_shared<DBuf>(&dev, (size_t)chi * 8);
     HIP_CHECK(hipMemcpyAsync(R.s->p, (double*)sv.p + (size_t)I * r, r * 8, hipMemcpyDeviceToDevice, dev.stream));
     HIP_CHECK(hipMemcpyAsync(R.w->p, (double*)w.p + (size_t)I * chi, chi * 8, hipMemcpyDeviceToDevice, dev.stream));
+  }
+  if (keep) {
+    keep->emplace_back();
+    ProjCacheStep& st = keep->back();
+    st.rows = a;
+    st.maxkd = maxkd;
+    const size_t pb = (size_t)a * maxkd * chi * 8;
+    st.P = DBuf(&dev, pb);
+    st.Q = DBuf(&dev, pb);
+    HIP_CHECK(hipMemcpyAsync(st.P.p, P64, pb, hipMemcpyDeviceToDevice, dev.stream));
+    HIP_CHECK(hipMemcpyAsync(st.Q.p, Q64, pb, hipMemcpyDeviceToDevice, dev.stream));
+    st.saved = std::move(rows);
+    return;
   }
   c->tape.custom([c, rows, r]() {
     for (const ProjRow& R : rows) proj_backward(c, R, r);
@@ -1566,15 +1621,31 @@ void sites_adjoint_to_A(ctm_ctx* c, const void* site_adj, double* grad) {
 // sweep's tape takes a few GB at D = 6, chi = 72); the sweeps before it are run
 // without a tape from snapshots of their starting environments and recomputed
 // under the tape in reverse order (checkpointing at sweep granularity).
+// Clears the context's projector-cache pointers when the scope ends (the
+// caches are locals of the caller).
+struct ProjCacheScope {
+  ctm_ctx* c;
+  ~ProjCacheScope() {
+    c->pc_fill = nullptr;
+    c->pc_use = nullptr;
+    c->pc_pos = 0;
+  }
+};
+
 double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, const ctm_term* terms, double* grad) {
   Dev& dev = c->dev;
   const size_t eb = (size_t)c->env_elems * type_size(c->st);
   const size_t es = type_size(c->st);
   std::vector<DBuf> snap;
+  // projector blocks of the sweeps the reverse pass recomputes (option proj_cache)
+  std::vector<std::vector<ProjCacheStep>> pcache(c->proj_cache && n > 1 ? n - 1 : 0);
+  ProjCacheScope pc_scope{c};
   for (int i = 0; i + 1 < n; ++i) {
     snap.emplace_back(&dev, eb);
     HIP_CHECK(hipMemcpyAsync(snap.back().p, c->env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
+    c->pc_fill = pcache.empty() ? nullptr : &pcache[i];
     for (int f : MOVE_FRAMES) left_move(c, f);
+    c->pc_fill = nullptr;
   }
   DBuf final_env(&dev, eb);
   DBuf site_adj(&dev, c->site_buf.bytes), env_adj(&dev, eb), env_adj2(&dev, eb);
@@ -1608,7 +1679,10 @@ double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, co
     c->tape.begin(&dev);
     c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
     c->tape.reg(c->env.p, eb, env_adj2.p);
+    c->pc_use = pcache.empty() ? nullptr : &pcache[i];
+    c->pc_pos = 0;
     for (int f : MOVE_FRAMES) left_move(c, f);
+    c->pc_use = nullptr;
     // seed: the adjoint of the environment after this sweep
     TapePause pause(dev);
     for (size_t idx = 0; idx < c->slot_ptr.size(); ++idx) {
@@ -1618,6 +1692,7 @@ double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, co
     }
     c->tape.backward();
     c->tape.clear();
+    if (!pcache.empty()) pcache[i].clear();
     std::swap(env_adj, env_adj2);
     c->reset_slot_ptrs();
   }
@@ -1972,6 +2047,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   if (!c || !key) return CTM_EINVAL;
   std::string k(key);
   if (k == "svd_cutoff" && value >= 0) c->cutoff = value;
+  else if (k == "proj_cache" && (value == 0 || value == 1)) c->proj_cache = (int)value;
   else if (k == "lorentz_eta" && value >= 0) c->eta = value;
   else if (k == "check_finite") c->check_finite = value != 0;
   else if (k == "streams" && (value == 1 || value == 2)) c->streams = (int)value;

@@ -260,3 +260,34 @@ def test_rowmajor_mfma_products_in_the_gradient(ctm_mod, precision, key):
     print(f"{key} in E&grad: |dE| {abs(E1 - E0):.2e}, max |d grad| {(g1 - g0).abs().max().item():.2e} of {scale:.2e}")
     assert E1 == E0
     assert torch.equal(g1, g0)
+
+
+@pytest.mark.parametrize("name,n", [("ssm_d3_chi12", 3), ("ssm_d6_chi72", 2)])
+def test_projector_cache_gives_identical_gradients(ctm_mod, name, n):
+    """Option proj_cache: the reverse pass of ctm_energy_grad takes the
+    projector blocks of the forward sweeps it recomputes instead of
+    factorising again.  Energy and gradient equal, bit for bit, those of the
+    run that recomputes them (n - 1 recomputed sweeps), and the environment the
+    call leaves behind is the same."""
+    if name == "ssm_d3_chi12":
+        A = synth.near_product_tensors(4, 2, 3, 5, 0.3)
+        pattern, chi = [[0, 1], [2, 3]], 12
+        env0 = synth.random_env_flat(chi, 3, 2, 2, 2, 3)
+    else:
+        cfg = synth.CONFIGS[name]
+        A = synth.near_product_tensors(cfg["n_tensors"], 2, cfg["D"], 5, 0.3)
+        pattern, chi = cfg["pattern"], cfg["chi"]
+        env0 = synth.random_env_flat(chi, cfg["D"], 2, 2, 2, 7)
+    terms = synth.shastry_sutherland_terms(0.8, 1.0)
+    out = []
+    for cache in (0, 1):
+        g = ctm_mod.CTM(A, pattern, chi)
+        g.set_option("svd_cutoff", CUT)
+        g.set_option("proj_cache", cache)
+        g.set_env(torch.tensor(env0))
+        E, grad = g.energy_grad(n, H, terms)
+        out.append((E, grad.cpu(), g.get_env().cpu()))
+        g.close()
+    assert out[0][0] == out[1][0]
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][2], out[1][2])
