@@ -961,7 +961,8 @@ void column_projectors(ctm_ctx* c, int f, int J, double* P64, double* Q64, int64
       cl.s1[I] = (const double*)sv.p + (size_t)I * r;
       cl.n[I] = (int64_t)lfs;
     }
-    HIP_CHECK(ctmk::launch_cut_check(cl, a, kEmptyCut, (int*)c->flag.p + 2, dev.stream));
+    DBuf cw(&dev, (size_t)a * ctmk::CUT_CHUNKS * 2 * 8);
+    HIP_CHECK(ctmk::launch_cut_check(cl, a, kEmptyCut, (double*)cw.p, (int*)c->flag.p + 2, dev.stream));
   }
   HIP_CHECK(ctmk::launch_svd_weights((const double*)sv.p, r, r, (double*)w.p, chi, c->cutoff, a, dev.stream));
   for (int I = 0; I < a; ++I) {

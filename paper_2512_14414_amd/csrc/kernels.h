@@ -50,6 +50,7 @@ struct NormList {
 
 // Rows of a column step checked for an empty cut (launch_cut_check).
 constexpr int CUT_MAX = 64;
+constexpr int CUT_CHUNKS = 64;   // workgroups per row for the factors' norms
 struct CutList {
   const double* Ln[CUT_MAX];   // R_n^T of the row (any layout, n entries)
   const double* Ls[CUT_MAX];   // R_s^T of the row
@@ -89,7 +90,8 @@ struct SignList {
 // P[:, k] within a relative 1e-9 of the column's largest magnitude is negative.
 hipError_t launch_proj_signs(const SignList& L, int count, int64_t chi, int64_t r, hipStream_t s);
 // Adds one to *flag for every row whose s_1 <= tau |N|_F |S|_F.
-hipError_t launch_cut_check(const CutList& L, int count, double tau, int* flag, hipStream_t s);
+// work: count * CUT_CHUNKS * 2 doubles of device scratch (partial sums of squares).
+hipError_t launch_cut_check(const CutList& L, int count, double tau, double* work, int* flag, hipStream_t s);
 hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,
                                 int64_t stride_l, int batch, hipStream_t s);
 hipError_t launch_observables(const double* rho, int64_t rho_stride, int n, double* out, hipStream_t s);

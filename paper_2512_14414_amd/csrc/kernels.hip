@@ -898,12 +898,16 @@ hipError_t launch_proj_signs(const SignList& L, int count, int64_t chi, int64_t 
 // norms those of N and S) and the largest singular value s_1 of M = R_n R_s^T,
 // count the row in *flag when s_1 <= tau |N|_F |S|_F (the bond density matrix
 // N S^T vanishes to working precision and Lambda~^(-1/2) is undefined).
-__global__ __launch_bounds__(256) void cut_check_kernel(CutList L, double tau, int* flag) {
-  const int t = blockIdx.x;
+// First pass: workgroup (c, t) sums the squares of its chunk c of both
+// factors of row t into part[(t * CUT_CHUNKS + c) * 2 + {0, 1}].
+__global__ __launch_bounds__(256) void cut_norms_kernel(CutList L, double* part) {
+  const int c = blockIdx.x, t = blockIdx.y;
+  const int64_t n = L.n[t], len = (n + CUT_CHUNKS - 1) / CUT_CHUNKS;
+  const int64_t lo = (int64_t)c * len, hi = lo + len < n ? lo + len : n;
   const double* a = L.Ln[t];
   const double* b = L.Ls[t];
   double sa = 0.0, sb = 0.0;
-  for (int64_t i = threadIdx.x; i < L.n[t]; i += 256) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
     sa += a[i] * a[i];
     sb += b[i] * b[i];
   }
@@ -918,13 +922,29 @@ __global__ __launch_bounds__(256) void cut_check_kernel(CutList L, double tau, i
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && !(*L.s1[t] > tau * sqrt(ra[0]) * sqrt(rb[0]))) atomicAdd(flag, 1);
+  if (threadIdx.x == 0) {
+    part[((int64_t)t * CUT_CHUNKS + c) * 2] = ra[0];
+    part[((int64_t)t * CUT_CHUNKS + c) * 2 + 1] = rb[0];
+  }
 }
 
-hipError_t launch_cut_check(const CutList& L, int count, double tau, int* flag, hipStream_t s) {
+// Second pass: thread t adds up row t's chunks in order and tests the cut.
+__global__ void cut_check_kernel(CutList L, int count, double tau, const double* part, int* flag) {
+  const int t = threadIdx.x;
+  if (t >= count) return;
+  double na = 0.0, nb = 0.0;
+  for (int c = 0; c < CUT_CHUNKS; ++c) {
+    na += part[((int64_t)t * CUT_CHUNKS + c) * 2];
+    nb += part[((int64_t)t * CUT_CHUNKS + c) * 2 + 1];
+  }
+  if (!(*L.s1[t] > tau * sqrt(na) * sqrt(nb))) atomicAdd(flag, 1);
+}
+
+hipError_t launch_cut_check(const CutList& L, int count, double tau, double* work, int* flag, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (count > CUT_MAX) return hipErrorInvalidValue;
-  cut_check_kernel<<<count, 256, 0, s>>>(L, tau, flag);
+  cut_norms_kernel<<<dim3(CUT_CHUNKS, (unsigned)count), 256, 0, s>>>(L, work);
+  cut_check_kernel<<<1, CUT_MAX, 0, s>>>(L, count, tau, work, flag);
   return hipGetLastError();
 }
 
