@@ -253,8 +253,9 @@ int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
  *   "svd_method"  0 (default) exact projector SVD; 1 randomized partial SVD
  *                 (range finder with "svd_oversample" extra columns, default 8,
  *                 "svd_power" subspace passes, default 2, test matrix from
- *                 SplitMix64 with "svd_seed", default 0) in sweeps that are not
- *                 differentiated.
+ *                 SplitMix64 with "svd_seed", default 0) in ctm_sweep; the
+ *                 sweeps of ctm_energy_grad (also those the reverse pass
+ *                 recomputes) and of ctm_energy_grad_fp take the exact SVD.
  *   "energy_precision" CTM_FP64, CTM_FP32 or CTM_BF16: the precision of the
  *                 energy's density-matrix contractions (and their adjoints) alone,
  *                 whatever the sweep's (default: that of the context's precision).

@@ -1623,13 +1623,19 @@ void sites_adjoint_to_A(ctm_ctx* c, const void* site_adj, double* grad) {
 // without a tape from snapshots of their starting environments and recomputed
 // under the tape in reverse order (checkpointing at sweep granularity).
 // Clears the context's projector-cache pointers when the scope ends (the
-// caches are locals of the caller).
+// caches are locals of the caller) and restores the projector SVD method:
+// every sweep of a differentiated chain, the forward ones that the reverse
+// pass recomputes included, takes the exact SVD, so that the recomputation
+// follows the forward pass.
 struct ProjCacheScope {
   ctm_ctx* c;
+  int svd_method;
+  explicit ProjCacheScope(ctm_ctx* cc) : c(cc), svd_method(cc->svd_method) { c->svd_method = 0; }
   ~ProjCacheScope() {
     c->pc_fill = nullptr;
     c->pc_use = nullptr;
     c->pc_pos = 0;
+    c->svd_method = svd_method;
   }
 };
 
@@ -1640,7 +1646,7 @@ double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, co
   std::vector<DBuf> snap;
   // projector blocks of the sweeps the reverse pass recomputes (option proj_cache)
   std::vector<std::vector<ProjCacheStep>> pcache(c->proj_cache && n > 1 ? n - 1 : 0);
-  ProjCacheScope pc_scope{c};
+  ProjCacheScope pc_scope(c);
   for (int i = 0; i + 1 < n; ++i) {
     snap.emplace_back(&dev, eb);
     HIP_CHECK(hipMemcpyAsync(snap.back().p, c->env.p, eb, hipMemcpyDeviceToDevice, dev.stream));

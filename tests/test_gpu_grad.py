@@ -291,3 +291,31 @@ def test_projector_cache_gives_identical_gradients(ctm_mod, name, n):
     assert out[0][0] == out[1][0]
     assert torch.equal(out[0][1], out[1][1])
     assert torch.equal(out[0][2], out[1][2])
+
+
+def test_gradient_chain_takes_the_exact_svd(ctm_mod):
+    """With the randomized projector SVD selected for plain sweeps, a
+    differentiated chain of 2 sweeps (its forward sweep recomputed in the
+    reverse pass) still takes the exact SVD in every sweep: E and dE/dA equal
+    those of a context on the exact SVD bit for bit, with and without the
+    projector cache, and the option is back in force afterwards."""
+    A = synth.near_product_tensors(4, 2, 3, 5, 0.3)
+    pattern, chi = [[0, 1], [2, 3]], 12
+    env0 = torch.tensor(synth.random_env_flat(chi, 3, 2, 2, 2, 3))
+    terms = synth.shastry_sutherland_terms(0.8, 1.0)
+    out = []
+    for method, cache in ((0, 1), (1, 1), (1, 0)):
+        g = ctm_mod.CTM(A, pattern, chi)
+        g.set_option("svd_cutoff", CUT)
+        g.set_option("svd_method", method)
+        g.set_option("proj_cache", cache)
+        g.set_env(env0)
+        E, grad = g.energy_grad(2, H, terms)
+        g.set_env(env0)
+        g.sweep(1)
+        out.append((E, grad.cpu(), g.get_env().cpu()))
+        g.close()
+    for E, grad, _ in out[1:]:
+        assert E == out[0][0] and torch.equal(grad, out[0][1])
+    # the plain sweep afterwards follows the selected method again
+    assert not torch.equal(out[1][2], out[0][2])
