@@ -104,9 +104,11 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int 
  * The sweep, its options, the projectors (now of (chi D^2) x chi; the
  * randomized partial SVD of option "svd_method" suits these larger cuts), the
  * convergence measures and the environment layout (Lx*Ly positions, T legs
- * of dimension D^2) are those of the nested context; ctm_energy, ctm_last_rdms
- * and ctm_observables contract each plaquette quadrant with the ket and then
- * the bra tensor of its site, without forming the open reduced tensor.
+ * of dimension D^2) are those of the nested context; the sweep absorbs every
+ * site layer by layer (its D^2 legs split into ket and bra halves: A, then A*),
+ * and ctm_energy, ctm_last_rdms and ctm_observables contract each plaquette
+ * quadrant with the ket and then the bra tensor of its site, without forming
+ * the open reduced tensor.
  * ctm_energy_grad and ctm_energy_grad_fp return CTM_EINVAL on such a context.
  * Requires chi >= D*D. */
 int ctm_init_double_layer(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,

@@ -93,6 +93,7 @@ struct ctm_ctx {
   // 1: the double-layer network of reduced tensors a = sum_s A A* with legs of
   //    dimension D^2 on the Ly x Lx cell (Eq. Tred)
   int layout = 0;
+  DBuf a_frames;                  // double layout: A of every tensor in every frame (legs rotated), d*D^4 each
   std::vector<int> pattern;
   int st = T_F64;                 // storage type of sites and environment
   int mode = ctmk::MODE_F64;      // matrix-core path of the sweep's contractions
@@ -269,6 +270,18 @@ void build_sites_double(ctm_ctx* c) {
       copy_into(dev, view(dst, c->st, {D2, D2, D2, D2}, rl), view(a8.buf.p, T_F64, {D2, D2, D2, D2}, lurd));
     }
   }
+  // the site tensors themselves per frame (legs rotated like the reduced
+  // tensors', physical index first), for the layered absorption of the sweep
+  if (!c->a_frames.p) c->a_frames = DBuf(&dev, (size_t)(4 * c->nt * nk) * es);
+  for (int t = 0; t < c->nt; ++t) {
+    double* At = (double*)c->A64.p + t * nk;
+    for (int f = 0; f < 4; ++f) {
+      std::string rl = "s";
+      for (int i = 0; i < 4; ++i) rl += lurd[(i + f) % 4];
+      void* dst = (char*)c->a_frames.p + (size_t)(f * c->nt + t) * nk * es;
+      copy_into(dev, view(dst, c->st, {d, D, D, D, D}, rl), view(At, T_F64, {d, D, D, D, D}, "slurd"));
+    }
+  }
   for (int f = 0; f < 4; ++f) {
     int a = c->ny(f), b = c->nx(f);
     c->frames[f].assign((size_t)a * b, SiteRef());
@@ -440,6 +453,61 @@ struct SideScope {
   }
 };
 
+// out = X . s for the site s at frame-f position (I, J) with its legs
+// (l, u, r, d) labelled ``lab``: the legs X shares with s are summed.  On the
+// nested network s is the dense nested site.  On the double-layer network s
+// is the reduced tensor a = sum_sigma A A* (legs of D^2, ket index major),
+// and it is absorbed one layer at a time: the shared legs of X and the free
+// legs of out are split into ket and bra halves, X is contracted with A over
+// the ket halves, then with A* over sigma and the bra halves (Eq. Tred
+// without forming a: 2 chi^2 D^6 d flops per quadrant instead of chi^2 D^8).
+void absorb_site(ctm_ctx* c, Dev& dev, int m, const TRef& out, const TRef& X, int f, int I, int J,
+                 const std::string& lab) {
+  if (!c->layout) {
+    contract(dev, m, out, X, c->site_t(f, I, J, lab));
+    return;
+  }
+  const int64_t D = c->D, d = c->d, nk = d * D * D * D * D;
+  std::string used = X.lab + out.lab + lab;
+  auto fresh = [&]() {
+    for (int ch = 33; ch < 127; ++ch)
+      if (used.find((char)ch) == std::string::npos) {
+        used += (char)ch;
+        return (char)ch;
+      }
+    throw Error(CTM_EINVAL, "absorb_site: label pool exhausted");
+  };
+  const char sg = fresh();
+  std::string kl, bl;
+  TRef Xs = X, Os = out;
+  for (char L : lab) {
+    const char k = fresh(), b = fresh();
+    kl += k;
+    bl += b;
+    if (Xs.lab.find(L) != std::string::npos) Xs = split_axis(Xs, L, D, D, k, b);
+    else if (Os.lab.find(L) != std::string::npos) Os = split_axis(Os, L, D, D, k, b);
+    else throw Error(CTM_EINVAL, "absorb_site: a site leg on neither side");
+  }
+  const int ii = ((I % c->ny(f)) + c->ny(f)) % c->ny(f), jj = ((J % c->nx(f)) + c->nx(f)) % c->nx(f);
+  int oi, oj;
+  c->to_orig(f, ii, jj, oi, oj);
+  const int t = c->pattern[(size_t)oi * c->Lx + oj];
+  void* Ap = (char*)c->a_frames.p + (size_t)(f * c->nt + t) * nk * type_size(c->st);
+  TRef Ak = view(Ap, c->st, {d, D, D, D, D}, std::string(1, sg) + kl);
+  TRef Ab = view(Ap, c->st, {d, D, D, D, D}, std::string(1, sg) + bl);
+  // X . A over the ket halves of the shared legs
+  std::string tl;
+  std::vector<int64_t> td;
+  for (size_t q = 0; q < Xs.lab.size(); ++q)
+    if (kl.find(Xs.lab[q]) == std::string::npos) { tl += Xs.lab[q]; td.push_back(Xs.dim[q]); }
+  for (size_t q = 0; q < Ak.lab.size(); ++q)
+    if (Xs.lab.find(Ak.lab[q]) == std::string::npos) { tl += Ak.lab[q]; td.push_back(Ak.dim[q]); }
+  Tmp T1(&dev, c->st, td, tl);
+  contract(dev, m, T1.t, Xs, Ak);
+  // then A* over sigma and the bra halves
+  contract(dev, m, Os, T1.t, Ab);
+}
+
 void half_systems(ctm_ctx* c, Dev& dev, int f, int I, int J, double* Nout, double* Sout) {
   const int64_t chi = c->chi;
   const int m = c->mode;
@@ -450,7 +518,7 @@ void half_systems(ctm_ctx* c, Dev& dev, int f, int I, int J, double* Nout, doubl
   Tmp X2(&dev, c->st, {chi, sUL.dim[0], sUL.dim[1], chi}, "eyxc");
   contract(dev, m, X2.t, c->slot(f, I, J, 7, "eya"), X1.t);
   Tmp UL(&dev, c->st, {chi, sUL.dim[2], chi, sUL.dim[3]}, "crez");
-  contract(dev, m, UL.t, X2.t, sUL);
+  absorb_site(c, dev, m, UL.t, X2.t, f, I, J, "yxrz");
   // upper-right quadrant: T1 C2 T2 s at (I, J+1)  ->  UR[c, h, l, w]
   TRef sUR = c->site_t(f, I, J + 1, "lxyw");
   Tmp Y1(&dev, c->st, {chi, sUR.dim[1], chi}, "cxg");
@@ -458,7 +526,7 @@ void half_systems(ctm_ctx* c, Dev& dev, int f, int I, int J, double* Nout, doubl
   Tmp Y2(&dev, c->st, {chi, sUR.dim[1], sUR.dim[2], chi}, "cxyh");
   contract(dev, m, Y2.t, Y1.t, c->slot(f, I, J + 1, 5, "gyh"));
   Tmp UR(&dev, c->st, {chi, chi, sUR.dim[0], sUR.dim[3]}, "chlw");
-  contract(dev, m, UR.t, Y2.t, sUR);
+  absorb_site(c, dev, m, UR.t, Y2.t, f, I, J + 1, "lxyw");
   // lower-left quadrant: T4 C4 T3 s at (I+1, J)  ->  DL[c, e, x, r]
   TRef sDL = c->site_t(f, I + 1, J, "yxrw");
   Tmp Z1(&dev, c->st, {chi, sDL.dim[0], chi}, "bye");
@@ -466,7 +534,7 @@ void half_systems(ctm_ctx* c, Dev& dev, int f, int I, int J, double* Nout, doubl
   Tmp Z2(&dev, c->st, {chi, sDL.dim[3], sDL.dim[0], chi}, "cwye");
   contract(dev, m, Z2.t, c->slot(f, I + 1, J, 6, "cwb"), Z1.t);
   Tmp DL(&dev, c->st, {chi, chi, sDL.dim[1], sDL.dim[2]}, "cexr");
-  contract(dev, m, DL.t, Z2.t, sDL);
+  absorb_site(c, dev, m, DL.t, Z2.t, f, I + 1, J, "yxrw");
   // lower-right quadrant: T2 C3 T3 s at (I+1, J+1)  ->  DR[h, c, l, v]
   TRef sDR = c->site_t(f, I + 1, J + 1, "lvyw");
   Tmp W1(&dev, c->st, {chi, sDR.dim[2], chi}, "hyf");
@@ -474,7 +542,7 @@ void half_systems(ctm_ctx* c, Dev& dev, int f, int I, int J, double* Nout, doubl
   Tmp W2(&dev, c->st, {chi, sDR.dim[2], sDR.dim[3], chi}, "hywc");
   contract(dev, m, W2.t, W1.t, c->slot(f, I + 1, J + 1, 6, "fwc"));
   Tmp DR(&dev, c->st, {chi, chi, sDR.dim[0], sDR.dim[1]}, "hclv");
-  contract(dev, m, DR.t, W2.t, sDR);
+  absorb_site(c, dev, m, DR.t, W2.t, f, I + 1, J + 1, "lvyw");
 
   const int64_t zdim = sUL.dim[3], wdim = sUR.dim[3], vdim = sDR.dim[1], xdim = sDL.dim[1];
   if (zdim != xdim || wdim != vdim) throw Error(CTM_EINVAL, "inconsistent nested bond dimensions");
@@ -1204,7 +1272,7 @@ void left_move(ctm_ctx* c, int f) {
       contract(rd, m, C1n, PQ(P64, Pst, I - 1, "axk"), X1.t);
       // T4' = Q_{I-1}^T [T4 s] P_I
       Tmp G1(&rd, c->st, {chi, chi, s.dim[1], s.dim[2], s.dim[3]}, "eaxrz");
-      contract(rd, m, G1.t, c->slot(f, I, J, 7, "eya"), s);
+      absorb_site(c, rd, m, G1.t, c->slot(f, I, J, 7, "eya"), f, I, J, "yxrz");
       Tmp G2(&rd, c->st, {chi, chi, s.dim[2], s.dim[3]}, "emrz");
       contract(rd, m, G2.t, PQ(Q64, Qst, I - 1, "axm"), G1.t);
       TRef T4n = c->out_slot(f, I, J + 1, 7, "krm");
@@ -2113,7 +2181,7 @@ void ctm_free(ctm_ctx* c) {
   {
     ctm_ctx* t = c;
     t->A64.reset(); t->site_buf.reset(); t->env.reset(); t->spec_prev.reset(); t->spec_cur.reset();
-    t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset(); t->env_prev.reset();
+    t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset(); t->env_prev.reset(); t->a_frames.reset();
   }
   c->tape.clear();
   c->dev.release();
