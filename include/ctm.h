@@ -141,10 +141,11 @@ int ctm_get_env(ctm_ctx* ctx, double* env);
 int ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done, double* delta);
 
 /* Corner spectra of the current environment (the quantity whose convergence
- * ends the iteration, Sec. II C): for every nested position (I, J) in row-major
- * order and each corner C1..C4, the singular values of the chi x chi corner in
- * descending order, divided by their sum and zero-padded to chi.  out (host)
- * receives 4 * (2Lx) * (2Ly) * chi float64 values, capacity is its length in
+ * ends the iteration, Sec. II C): for every position (I, J) of the cell in
+ * row-major order (2Ly x 2Lx nested positions; Ly x Lx on a double-layer
+ * context) and each corner C1..C4, the singular values of the chi x chi corner
+ * in descending order, divided by their sum and zero-padded to chi.  out (host)
+ * receives 4 * (positions) * chi float64 values, capacity is its length in
  * values; with out == NULL only *n_written (host, may be NULL otherwise) is
  * set to the required length.  CTM_EINVAL if capacity is too small;
  * CTM_ESOLVER if a corner SVD fails.  The sweep's own convergence state is not

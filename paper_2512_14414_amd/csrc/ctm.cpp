@@ -2022,7 +2022,7 @@ int ctm_corner_spectra(ctm_ctx* c, double* out, int64_t capacity, int64_t* n_wri
     if (n_written) *n_written = total;
     return CTM_OK;
   }
-  if (capacity < total) return fail(c, Error(CTM_EINVAL, "capacity below 4 * (2Lx) * (2Ly) * chi values"));
+  if (capacity < total) return fail(c, Error(CTM_EINVAL, "capacity below the number of corner spectrum values (4 chi per cell position)"));
   try {
     DBuf sv, norm(&c->dev, (size_t)total * 8);
     corner_svals(c, sv);
