@@ -108,8 +108,9 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int 
  * site layer by layer (its D^2 legs split into ket and bra halves: A, then A*),
  * and ctm_energy, ctm_last_rdms and ctm_observables contract each plaquette
  * quadrant with the ket and then the bra tensor of its site, without forming
- * the open reduced tensor.
- * ctm_energy_grad and ctm_energy_grad_fp return CTM_EINVAL on such a context.
+ * the open reduced tensor.  ctm_energy_grad and ctm_energy_grad_fp
+ * differentiate this network the same way (the adjoints of the per-frame
+ * copies of A and of the density matrices' A are added up into dE/dA).
  * Requires chi >= D*D. */
 int ctm_init_double_layer(ctm_ctx** out, const double* A, int d, int D, int chi, int Lx, int Ly, const int* pattern,
                           int n_tensors, int precision, void* stream);

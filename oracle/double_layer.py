@@ -26,6 +26,8 @@ from __future__ import annotations
 
 import torch
 
+from types import SimpleNamespace
+
 from .ctmrg import corner_spectra, env_from_flat, init_env, spectra_delta, sweep
 from .network import LT, as_t, contract_all, site_frames
 from .rdm import ORDER, energy_from_rdms
@@ -127,3 +129,30 @@ def energy(ctm: DoubleLayerCTM, H, terms):
     needed = sorted({(t[0], t[1]) for t in terms})
     rdms = {p: plaquette_rdm(ctm, p[0], p[1]) for p in needed}
     return energy_from_rdms(rdms, H, terms, Lx * Ly)
+
+
+def energy_after_sweeps(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-10, eta=1e-12):
+    """E(A) after ``n_sweeps`` double-layer sweeps from the constant environment
+    ``env0``, differentiable in A (Eq. AD on the network of Eq. Tred): the
+    reduced tensors are formed by einsum from A, the sweep is the generic one
+    with the projector block of ``adjoint.projector_fn`` (hand-written
+    derivative, Lorentzian width eta), the energy that of ``energy`` above.
+    Returns (E, env_final)."""
+    from .adjoint import projector_fn
+    A = as_t(A) if not torch.is_tensor(A) else A
+    frames = site_frames(double_cell(A, pattern))
+    proj = projector_fn(eta)
+    env = env0
+    for _ in range(n_sweeps):
+        env = sweep(frames, env, chi, cutoff, proj=proj)
+    E = energy(SimpleNamespace(A=A, pattern=pattern, env=env), H, terms)
+    return E, env
+
+
+def energy_and_grad(A, pattern, chi, env0, n_sweeps, H, terms, cutoff=1e-10, eta=1e-12):
+    """(E, dE/dA, final environment) for ``energy_after_sweeps``."""
+    A = torch.as_tensor(A, dtype=torch.float64).clone().requires_grad_(True)
+    env0 = [[{k: v.detach().clone() for k, v in e.items()} for e in row] for row in env0]
+    E, env = energy_after_sweeps(A, pattern, chi, env0, n_sweeps, H, terms, cutoff, eta)
+    (g,) = torch.autograd.grad(E, A)
+    return E.item(), g, [[{k: v.detach() for k, v in e.items()} for e in row] for row in env]

@@ -1707,6 +1707,51 @@ struct ProjCacheScope {
   }
 };
 
+// Adjoint buffers of the tensors the recorded sweeps and the energy read:
+// the nested sites, or on the double-layer network the per-frame copies of A
+// that the layered absorption reads and the float64 A of the density
+// matrices.  Zeroed once, registered with every tape of a reverse pass.
+struct SiteAdjoints {
+  DBuf a, b;
+  explicit SiteAdjoints(ctm_ctx* c) {
+    Dev& dev = c->dev;
+    const DBuf& src = c->layout ? c->a_frames : c->site_buf;
+    a = DBuf(&dev, src.bytes);
+    HIP_CHECK(hipMemsetAsync(a.p, 0, a.bytes, dev.stream));
+    if (c->layout) {
+      b = DBuf(&dev, c->A64.bytes);
+      HIP_CHECK(hipMemsetAsync(b.p, 0, b.bytes, dev.stream));
+    }
+  }
+  void reg(ctm_ctx* c) const {
+    if (!c->layout) {
+      c->tape.reg(c->site_buf.p, c->site_buf.bytes, a.p);
+    } else {
+      c->tape.reg(c->a_frames.p, c->a_frames.bytes, a.p);
+      c->tape.reg(c->A64.p, c->A64.bytes, b.p);
+    }
+  }
+  // dE/dA[t][s][l][u][r][d] (float64, overwritten)
+  void to_A(ctm_ctx* c, double* grad) const {
+    if (!c->layout) {
+      sites_adjoint_to_A(c, a.p, grad);
+      return;
+    }
+    Dev& dev = c->dev;
+    const int64_t d = c->d, D = c->D, nk = d * D * D * D * D;
+    const size_t es = type_size(c->st);
+    HIP_CHECK(hipMemcpyAsync(grad, b.p, (size_t)c->nt * nk * 8, hipMemcpyDeviceToDevice, dev.stream));
+    const std::string lurd = "lurd";
+    for (int f = 0; f < 4; ++f) {
+      std::string rl = "s";
+      for (int q = 0; q < 4; ++q) rl += lurd[(q + f) % 4];
+      for (int t = 0; t < c->nt; ++t)
+        copy_into(dev, view(grad + t * nk, T_F64, {d, D, D, D, D}, "slurd"),
+                  view((char*)a.p + (size_t)(f * c->nt + t) * nk * es, c->st, {d, D, D, D, D}, rl), true);
+    }
+  }
+};
+
 double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, const ctm_term* terms, double* grad) {
   Dev& dev = c->dev;
   const size_t eb = (size_t)c->env_elems * type_size(c->st);
@@ -1723,12 +1768,12 @@ double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, co
     c->pc_fill = nullptr;
   }
   DBuf final_env(&dev, eb);
-  DBuf site_adj(&dev, c->site_buf.bytes), env_adj(&dev, eb), env_adj2(&dev, eb);
-  HIP_CHECK(hipMemsetAsync(site_adj.p, 0, site_adj.bytes, dev.stream));
+  SiteAdjoints site_adj(c);
+  DBuf env_adj(&dev, eb), env_adj2(&dev, eb);
   HIP_CHECK(hipMemsetAsync(env_adj.p, 0, eb, dev.stream));
   // the last sweep and the energy at its environment, on one tape
   c->tape.begin(&dev);
-  c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
+  site_adj.reg(c);
   c->tape.reg(c->env.p, eb, env_adj.p);
   if (n > 0)
     for (int f : MOVE_FRAMES) left_move(c, f);
@@ -1752,7 +1797,7 @@ double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, co
     c->reset_slot_ptrs();
     HIP_CHECK(hipMemsetAsync(env_adj2.p, 0, eb, dev.stream));
     c->tape.begin(&dev);
-    c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
+    site_adj.reg(c);
     c->tape.reg(c->env.p, eb, env_adj2.p);
     c->pc_use = pcache.empty() ? nullptr : &pcache[i];
     c->pc_pos = 0;
@@ -1774,7 +1819,7 @@ double energy_grad_impl(ctm_ctx* c, int n, const double* H_bond, int n_terms, co
   HIP_CHECK(hipMemcpyAsync(c->env.p, final_env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
   c->reset_slot_ptrs();
   c->have_prev = false;
-  sites_adjoint_to_A(c, site_adj.p, grad);
+  site_adj.to_A(c, grad);
   HIP_CHECK(ctmk::launch_nonfinite(T_F64, grad, (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D, (int*)c->flag.p,
                                    dev.stream));
   HIP_CHECK(hipStreamSynchronize(dev.stream));
@@ -1806,11 +1851,11 @@ double energy_grad_fp_impl(ctm_ctx* c, const double* H_bond, int n_terms, const 
   const size_t eb = (size_t)c->env_elems * type_size(c->st);
   const size_t es = type_size(c->st);
   DBuf final_env(&dev, eb), mu(&dev, eb);
-  DBuf site_adj(&dev, c->site_buf.bytes), env_adj(&dev, eb);
-  HIP_CHECK(hipMemsetAsync(site_adj.p, 0, site_adj.bytes, dev.stream));
+  SiteAdjoints site_adj(c);
+  DBuf env_adj(&dev, eb);
   HIP_CHECK(hipMemsetAsync(env_adj.p, 0, eb, dev.stream));
   c->tape.begin(&dev);
-  c->tape.reg(c->site_buf.p, c->site_buf.bytes, site_adj.p);
+  site_adj.reg(c);
   c->tape.reg(c->env.p, eb, env_adj.p);
   for (int f : MOVE_FRAMES) left_move(c, f);
   const size_t n_sweep_ops = c->tape.ops.size();
@@ -1851,7 +1896,7 @@ double energy_grad_fp_impl(ctm_ctx* c, const double* H_bond, int n_terms, const 
   HIP_CHECK(hipMemcpyAsync(c->env.p, final_env.p, eb, hipMemcpyDeviceToDevice, dev.stream));
   c->reset_slot_ptrs();
   c->have_prev = false;
-  sites_adjoint_to_A(c, site_adj.p, grad);
+  site_adj.to_A(c, grad);
   HIP_CHECK(ctmk::launch_nonfinite(T_F64, grad, (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D, (int*)c->flag.p,
                                    dev.stream));
   HIP_CHECK(hipStreamSynchronize(dev.stream));
@@ -2048,7 +2093,6 @@ int ctm_energy_grad(ctm_ctx* c, const double* A, int n_sweeps, const double* H_b
                     const ctm_term* terms, double* E, double* dEdA) {
   if (!c || !H_bond || (n_terms > 0 && !terms) || !E || !dEdA || n_sweeps < 0) return CTM_EINVAL;
   try {
-    if (c->layout) throw Error(CTM_EINVAL, "gradients are implemented for the nested network only");
     if (A) {
       int64_t nA = (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D;
       HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
@@ -2068,7 +2112,6 @@ int ctm_energy_grad_fp(ctm_ctx* c, const double* A, double tol, int max_iter, co
                        const ctm_term* terms, double* E, double* dEdA, int* iters, double* gap) {
   if (!c || !H_bond || (n_terms > 0 && !terms) || !E || !dEdA || !(tol >= 0) || max_iter < 0) return CTM_EINVAL;
   try {
-    if (c->layout) throw Error(CTM_EINVAL, "gradients are implemented for the nested network only");
     if (A) {
       int64_t nA = (int64_t)c->nt * c->d * c->D * c->D * c->D * c->D;
       HIP_CHECK(hipMemcpyAsync(c->A64.p, A, (size_t)nA * 8, hipMemcpyDeviceToDevice, c->dev.stream));
