@@ -248,6 +248,13 @@ int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
  *                 sweep at D=6, chi=72), and the recomputation takes them
  *                 instead of repeating the QR and SVD (same results bit for
  *                 bit); 0 recomputes them.
+ *   "conv_rdm"    1 to take the delta of ctm_sweep as the largest change of any
+ *                 entry of the trace-normalised plaquette density matrices of
+ *                 all Lx*Ly plaquettes (the quantities the energy and the order
+ *                 parameters are made of), computed in the energy's precision
+ *                 after every sweep; on the nested network they settle in tens
+ *                 of sweeps where the corner spectra and the environment
+ *                 entries take hundreds.  Takes precedence over "conv_env".
  *   "conv_env"    1 to take the delta of ctm_sweep as max|env_new - env_old| /
  *                 max|env_old| over all environment entries (meaningful because
  *                 the gauge rules make a converged environment a fixed point

@@ -136,3 +136,20 @@ def energy(ctm, H, terms):
     needed = sorted({(t[0], t[1]) for t in terms})
     rdms = {p: plaquette_rdm(ctm.sites, ctm.env, p[0], p[1]) for p in needed}
     return energy_from_rdms(rdms, H, terms, Lx * Ly)
+
+
+def normalized_plaquette_rdms(sites, env, Lx, Ly):
+    """rho_p / Tr rho_p of every plaquette p = (x, y) of the Lx x Ly cell, in row-major order (y, then x)."""
+    out = []
+    for y in range(Ly):
+        for x in range(Lx):
+            r = plaquette_rdm(sites, env, x, y)
+            out.append(r / torch.trace(r))
+    return out
+
+
+def rdm_delta(new, old):
+    """Largest change of any entry of the normalised plaquette density matrices
+    between two environments: a convergence measure that sees only what the
+    energy and the order parameters are made of."""
+    return max((a - b).abs().max().item() for a, b in zip(new, old))

@@ -112,6 +112,8 @@ struct ctm_ctx {
   bool jacobi_coop = true;         // launch that kernel cooperatively (co-residency guaranteed by the runtime)
   int svd_method = 0;              // projector SVD of sweeps that are not differentiated: 0 exact, 1 randomized
   int conv_env = 0;                // delta of ctm_sweep: 0 corner spectra, 1 largest change of the (gauge-fixed) entries
+  int conv_rdm = 0;                // delta of ctm_sweep: largest change of the trace-normalised plaquette density matrices
+  DBuf rdm_a, rdm_b;               // those of the previous and the current environment (conv_rdm)
   DBuf env_prev;                   // environment before the sweep (conv_env)
   // Checkpointed reverse pass: the forward sweeps that are recomputed keep
   // their projector blocks (pc_fill), and the recomputation takes them
@@ -2031,17 +2033,34 @@ int ctm_sweep(ctm_ctx* c, int max_sweeps, double tol, int* sweeps_done, double* 
     double dl = -1.0;
     int n = 0;
     const size_t eb = (size_t)c->env_elems * type_size(c->st);
-    if (tol > 0 && c->conv_env && !c->env_prev.p) c->env_prev = DBuf(&c->dev, eb);
+    // conv_rdm: the plaquette density matrices of every plaquette of the cell,
+    // each divided by its trace, of the environment the call starts from and
+    // after every sweep
+    const bool by_rdm = tol > 0 && c->conv_rdm;
+    const int64_t d4 = (int64_t)c->d * c->d * c->d * c->d, rsz = d4 * d4, nplaq = (int64_t)c->Lx * c->Ly;
+    auto all_rdms = [&](DBuf& out) {
+      if (!out.p) out = DBuf(&c->dev, (size_t)nplaq * rsz * 8);
+      for (int py = 0; py < c->Ly; ++py)
+        for (int px = 0; px < c->Lx; ++px)
+          plaquette_rdm(c, px, py, (double*)out.p + ((int64_t)py * c->Lx + px) * rsz);
+      HIP_CHECK(ctmk::launch_rdm_normalize((double*)out.p, (int)nplaq, d4, c->dev.stream));
+    };
+    if (by_rdm) all_rdms(c->rdm_a);
+    if (tol > 0 && !by_rdm && c->conv_env && !c->env_prev.p) c->env_prev = DBuf(&c->dev, eb);
     // the first delta compares with the spectra of the environment the call starts from
-    if (tol > 0 && !c->conv_env && !c->have_prev) (void)spectra_delta(c);
+    if (tol > 0 && !by_rdm && !c->conv_env && !c->have_prev) (void)spectra_delta(c);
     for (n = 1; n <= max_sweeps; ++n) {
-      if (tol > 0 && c->conv_env)
+      if (tol > 0 && !by_rdm && c->conv_env)
         HIP_CHECK(hipMemcpyAsync(c->env_prev.p, c->env.p, eb, hipMemcpyDeviceToDevice, c->dev.stream));
       for (int f : MOVE_FRAMES) left_move(c, f);
       if (c->check_finite)
         HIP_CHECK(ctmk::launch_nonfinite(c->st, c->env.p, c->env_elems, (int*)c->flag.p, c->dev.stream));
       if (tol > 0) {
-        if (c->conv_env) {
+        if (by_rdm) {
+          all_rdms(c->rdm_b);
+          dl = device_max_abs(c, T_F64, c->rdm_b.p, c->rdm_a.p, nplaq * rsz);
+          std::swap(c->rdm_a, c->rdm_b);
+        } else if (c->conv_env) {
           const double mx = device_max_abs(c, c->st, c->env_prev.p, nullptr, c->env_elems);
           dl = mx > 0 ? device_max_abs(c, c->st, c->env.p, c->env_prev.p, c->env_elems) / mx : 1e300;
         } else {
@@ -2176,6 +2195,7 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   else if (k == "jacobi_cooperative") c->jacobi_coop = value != 0;
   else if (k == "svd_method" && (value == 0 || value == 1)) c->svd_method = (int)value;
   else if (k == "conv_env" && (value == 0 || value == 1)) c->conv_env = (int)value;
+  else if (k == "conv_rdm" && (value == 0 || value == 1)) c->conv_rdm = (int)value;
   else if (k == "svd_oversample" && value >= 0 && value <= 4096) c->rsvd_oversample = (int)value;
   else if (k == "svd_power" && value >= 0 && value <= 16) c->rsvd_power = (int)value;
   else if (k == "svd_seed" && value >= 0 && value < 9007199254740992.0) c->rsvd_seed = (uint64_t)value;
@@ -2224,7 +2244,7 @@ void ctm_free(ctm_ctx* c) {
   {
     ctm_ctx* t = c;
     t->A64.reset(); t->site_buf.reset(); t->env.reset(); t->spec_prev.reset(); t->spec_cur.reset();
-    t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset(); t->env_prev.reset(); t->a_frames.reset();
+    t->dscal.reset(); t->rdm_buf.reset(); t->flag.reset(); t->env_prev.reset(); t->a_frames.reset(); t->rdm_a.reset(); t->rdm_b.reset();
   }
   c->tape.clear();
   c->dev.release();

@@ -90,6 +90,8 @@ struct SignList {
 // P[:, k] within a relative 1e-9 of the column's largest magnitude is negative.
 hipError_t launch_proj_signs(const SignList& L, int count, int64_t chi, int64_t r, hipStream_t s);
 // Adds one to *flag for every row whose s_1 <= tau |N|_F |S|_F.
+// Divides each of the count dim x dim row-major matrices at rho (contiguous) by its trace.
+hipError_t launch_rdm_normalize(double* rho, int count, int64_t dim, hipStream_t s);
 // work: count * CUT_CHUNKS * 2 doubles of device scratch (partial sums of squares).
 hipError_t launch_cut_check(const CutList& L, int count, double tau, double* work, int* flag, hipStream_t s);
 hipError_t launch_extract_lower(const double* a, int64_t rows, int64_t lda, int64_t stride_a, double* l, int64_t rcols,

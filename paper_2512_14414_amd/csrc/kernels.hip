@@ -894,6 +894,23 @@ hipError_t launch_proj_signs(const SignList& L, int count, int64_t chi, int64_t 
   return hipGetLastError();
 }
 
+// Density matrices rho_b (dim x dim, row-major, b < count, contiguous) divided
+// by their traces, one workgroup each.
+__global__ void rdm_normalize_kernel(double* rho, int64_t dim) {
+  double* r = rho + (int64_t)blockIdx.x * dim * dim;
+  double tr = 0.0;
+  for (int64_t i = 0; i < dim; ++i) tr += r[i * dim + i];
+  __syncthreads();   // every thread has read the diagonal before any is rescaled
+  const double inv = 1.0 / tr;
+  for (int64_t e = threadIdx.x; e < dim * dim; e += blockDim.x) r[e] *= inv;
+}
+
+hipError_t launch_rdm_normalize(double* rho, int count, int64_t dim, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  rdm_normalize_kernel<<<count, 256, 0, s>>>(rho, dim);
+  return hipGetLastError();
+}
+
 // Empty cuts: for row t, with R_n^T and R_s^T of its half systems (Frobenius
 // norms those of N and S) and the largest singular value s_1 of M = R_n R_s^T,
 // count the row in *flag when s_1 <= tau |N|_F |S|_F (the bond density matrix
