@@ -8,6 +8,7 @@ ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/kernels.hip", "csrc/qr_kernels.hip", "csrc/opt_kernels.hip", "csrc/sur_noalloc.hip", "csrc/engine.cpp",
            "csrc/ctm.cpp", "csrc/surrogate.cpp", "csrc/lbfgs.cpp"]
 OUT = os.path.join(HERE, "libctm.so")
+C_CHECK = os.path.join(HERE, "c_abi_check")
 
 
 def build(verbose: bool = False) -> str:
@@ -32,6 +33,17 @@ def build(verbose: bool = False) -> str:
     if verbose and msgs.strip():
         print(msgs)
     os.replace(OUT + ".tmp", OUT)
+    # a plain C program on the C ABI (no Python), run by the GPU tests
+    cc = os.environ.get("CC", "gcc")
+    cmd = [cc, "-O2", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", os.path.join(HERE, "csrc", "c_abi_check.c"), "-L", HERE, "-lctm",
+           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath,/opt/rocm/lib", "-lm",
+           "-o", C_CHECK]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("building the C ABI check failed:\n" + r.stdout + r.stderr)
     return OUT
 
 

@@ -45,6 +45,12 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu():
     assert rc == -1 and b"pattern" in lib.ctm_last_error(None)
 
 
+def test_c_program_is_built_next_to_the_library():
+    """build() also links a plain C program against the library (run by the GPU tests)."""
+    path = os.path.join(ROOT, "paper_2512_14414_amd", "c_abi_check")
+    assert os.access(path, os.X_OK)
+
+
 def test_bench_refuses_more_than_one_gpu():
     """The benchmark has no multi-GPU path: asked for two GPUs it prints one
     JSON line naming the reason and exits with status 2, before any device work."""
