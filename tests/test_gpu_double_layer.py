@@ -213,3 +213,26 @@ def test_double_layer_fixed_point_gradient_against_differences(ctm_mod):
         fd = (vals[0] - 8 * vals[1] + 8 * vals[2] - vals[3]) / (12 * h)
         print(f"entry {idx}: fixed point {grad[idx].item():.12f}, differences {fd:.12f} ({it} series terms, gap {gap:.1e})")
         assert abs(grad[idx].item() - fd) < 1e-8
+
+
+def test_double_layer_observables_against_oracle(ctm_mod):
+    """Order-parameter inputs (moments and bond correlations, Eqs. Mag1 and
+    Mag2) of the double-layer context's density matrices against the oracle's
+    double-layer density matrices after the same sweeps: 1e-12."""
+    from oracle.observables import plaquette_observables
+    name, A, chi, pattern, sweeps = CASES[1]
+    terms = _terms(pattern)
+    g = ctm_mod.CTM(A, pattern, chi, layout="double")
+    g.sweep(sweeps)
+    g.energy(H, terms)
+    obs = g.observables()
+    o = DoubleLayerCTM(A, pattern, chi)
+    o.run(sweeps)
+    order = []
+    for t in terms:
+        if (t[0], t[1]) not in order:
+            order.append((t[0], t[1]))
+    for q, (px, py) in enumerate(order):
+        ref = plaquette_observables(dl_rdm(o, px, py))
+        err = (torch.as_tensor(obs[q]) - torch.as_tensor(ref)).abs().max().item()
+        assert err < 1e-12, (px, py, err)
