@@ -252,9 +252,11 @@ int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
  *                 entry of the trace-normalised plaquette density matrices of
  *                 all Lx*Ly plaquettes (the quantities the energy and the order
  *                 parameters are made of), computed in the energy's precision
- *                 after every sweep; on the nested network they settle in tens
+ *                 after every sweep (FP32 in the mixed mode: deltas level off
+ *                 near 1e-7 there); on the nested network they settle in tens
  *                 of sweeps where the corner spectra and the environment
- *                 entries take hundreds.  Takes precedence over "conv_env".
+ *                 entries take hundreds.  Takes precedence over "conv_env";
+ *                 default 0.
  *   "conv_env"    1 to take the delta of ctm_sweep as max|env_new - env_old| /
  *                 max|env_old| over all environment entries (meaningful because
  *                 the gauge rules make a converged environment a fixed point
