@@ -16,7 +16,7 @@ C4->C3, C1->C4 and T2->T1, T3->T2, T4->T3, T1->T4 with unchanged arrays, so
 the right, up and down moves are the left move in a turned frame ("performed
 one by one similarly", Sec. II C).
 
-Readings of points the paper leaves open (all stated in the design doc as well):
+Readings of points the paper leaves open:
 * start: by default every environment tensor is the neighbouring nested site
   with its outward legs summed against all-ones vectors; a caller may pass
   any starting environment instead (fine-tuned states such as products of
