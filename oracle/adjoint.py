@@ -6,9 +6,9 @@ The differentiated function is
 
     E(A) = energy after n sweeps started from a given environment env0,
 
-with env0 held constant.  This is the shortened chain that Sec. IV proposes
-("a checkpoint or a fixed-point technique ... calculating the gradient from a
-given or an approximate fixed-point environment").  Starting from the fixed
+with env0 held constant: the shortened chain of Sec. IV, where the paper
+suggests taking the gradient from a supplied or nearly converged environment
+instead of differentiating the whole iteration.  Starting from the fixed
 sites-only environment instead makes E_n a chaotic function of A on random
 tensors (a 1e-13 change of A reaches order one within a few sweeps), so its
 derivative would carry no information; from a converged env0 the iteration is

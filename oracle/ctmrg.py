@@ -13,8 +13,8 @@ around the site (this makes the labels invariant under quarter turns):
 
 Turning the lattice a quarter turn counter-clockwise maps C2->C1, C3->C2,
 C4->C3, C1->C4 and T2->T1, T3->T2, T4->T3, T1->T4 with unchanged arrays, so
-the right, up and down moves are the left move in a turned frame ("performed
-one by one similarly", Sec. II C).
+the right, up and down moves are the left move in a turned frame (Sec. II C
+treats them as the left move repeated in the other directions).
 
 Readings of points the paper leaves open:
 * start: by default every environment tensor is the neighbouring nested site
