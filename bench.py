@@ -124,6 +124,8 @@ def main():
                          "matrices settle (conv_rdm, 1e-10, at most --lbfgs-max-sweeps), then the fixed-point "
                          "gradient of the converged energy")
     ap.add_argument("--lbfgs-max-sweeps", type=int, default=50)
+    ap.add_argument("--lbfgs-D", type=int, default=None, help="bond dimension of the L-BFGS workload (default 5)")
+    ap.add_argument("--lbfgs-chi", type=int, default=None, help="environment dimension of the L-BFGS workload (default 50)")
     ap.add_argument("--lbfgs-sur-start", type=int, default=51, help="first L-BFGS iteration the surrogate screens")
     ap.add_argument("--lbfgs-runs", default="all",
                     help="comma-separated subset of plain_fp64,mixed,mixed_surrogate (runs of about ten minutes "
@@ -497,7 +499,13 @@ def lbfgs_time_to_target(args, torch, synth, ctm):
     exact evaluations of the iterations before --lbfgs-sur-start, default 51, then screening 8
     trial steps per line search, every accepted step confirmed by an exact evaluation)."""
     name = "ssm_d5_chi50"
-    cfg = synth.CONFIGS[name]
+    cfg = dict(synth.CONFIGS[name])
+    if args.lbfgs_D is not None or args.lbfgs_chi is not None:
+        # the same model and cell at another bond dimension (a smaller one lets the run reach the
+        # surrogate's start within minutes); the surrogate's input width follows d * D^4 per tensor
+        cfg["D"] = args.lbfgs_D or cfg["D"]
+        cfg["chi"] = args.lbfgs_chi or cfg["chi"]
+        name = f"ssm_d{cfg['D']}_chi{cfg['chi']}"
     A0 = torch.tensor(synth.near_product_tensors(cfg["n_tensors"], 2, cfg["D"], 0, 0.3))
     env0 = torch.tensor(synth.random_env_flat(cfg["chi"], cfg["D"], 2, cfg["Lx"], cfg["Ly"], 7))
     H = synth.heisenberg_bond()
@@ -580,8 +588,9 @@ def lbfgs_time_to_target(args, torch, synth, ctm):
     ts = out_runs["mixed_surrogate"]["seconds_to_target"] if "mixed_surrogate" in out_runs else None
     out = {"metric": "wall time to |E - E_plain| < 1e-5 per site, L-BFGS (mixed + surrogate vs plain FP64)",
            "value": ts, "unit": "s", "higher_is_better": False, "n_gpus": 1,
-           "config": {"workload": f"{name}: Shastry-Sutherland J_dimer=1 J_nn=0.7, 2x2 cell of 4 tensors, d=2 D=5 "
-                                  f"chi=50, start: product + 0.3 noise (seed 0), normalised; pseudo-inverse cutoff "
+           "config": {"workload": f"{name}: Shastry-Sutherland J_dimer=1 J_nn=0.7, 2x2 cell of 4 tensors, d=2 "
+                                  f"D={cfg['D']} chi={cfg['chi']}, start: product + 0.3 noise (seed 0), normalised; "
+                                  f"pseudo-inverse cutoff "
                                   f"1e-6; L-BFGS {args.lbfgs_iters} iterations, m = 10, strong Wolfe, surrogate from "
                                   f"iteration {args.lbfgs_sur_start}; an evaluation: "
                                   + (f"E and dE/dA after {nsw} differentiated sweeps from a fixed seeded random "
