@@ -733,7 +733,9 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   hqr_factor(dev, qm);
   HIP_CHECK(ctmk::launch_rt_from_qr(A, (double*)X.p, r, stride, batch, dev.stream));
   HIP_CHECK(ctmk::launch_identity((double*)W.p, r, stride, batch, dev.stream));
-  HIP_CHECK(ctmk::launch_frob_tiny((const double*)X.p, stride, stride, batch, 2.2e-16, (double*)tiny2.p, dev.stream));
+  DBuf fwork(&dev, (size_t)std::max(ctmk::frob_tiny_work_doubles(batch), ctmk::jacobi_finish_work_doubles(r, batch)) * 8);
+  HIP_CHECK(ctmk::launch_frob_tiny((const double*)X.p, stride, stride, batch, 2.2e-16, (double*)tiny2.p,
+                                   (double*)fwork.p, dev.stream));
   const double tol = std::max(1e-15, 2.2e-16 * std::sqrt((double)r));
   // The method converges quadratically at the end: once the largest |cos| of
   // a pair rotated in a whole sweep is at most sqrt(tol), what that sweep left
@@ -805,7 +807,7 @@ int jacobi_svd(ctm_ctx* c, double* A, int64_t r, int batch, int64_t kmax, double
   }
   // normalised columns of X W are the right vectors of A; the columns of W, times Q, the left ones
   HIP_CHECK(ctmk::launch_jacobi_finish((const double*)X.p, (const double*)W.p, r, stride, batch, kmax, sv, Vk, U,
-                                       dev.stream));
+                                       (double*)fwork.p, dev.stream));
   hqr_apply(dev, qm, U, 1, r, r * kmax, kmax, false);
   return sweep;
 }
@@ -1193,6 +1195,11 @@ void normalize_all(ctm_ctx* c, const std::vector<TRef>& ts) {
     TapePause pause(dev);
     norms = std::make_shared<DBuf>(&dev, std::max<size_t>(ts.size(), 1) * 8);
   }
+  DBuf work;   // the kernels' partial sums: not part of the recorded computation
+  {
+    TapePause pause(dev);
+    work = DBuf(&dev, (size_t)ctmk::normalize_work_doubles(ctmk::NORM_MAX) * 8);
+  }
   for (size_t s0 = 0; s0 < ts.size(); s0 += ctmk::NORM_MAX) {
     ctmk::NormList L;
     std::memset(&L, 0, sizeof(L));
@@ -1203,7 +1210,7 @@ void normalize_all(ctm_ctx* c, const std::vector<TRef>& ts) {
     }
     if (rec) L.norm_out = (double*)norms->p + s0;
     L.zero_flag = (int*)c->flag.p + 3;
-    HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, dev.stream));
+    HIP_CHECK(ctmk::launch_normalize(c->st, L, cnt, (double*)work.p, dev.stream));
   }
   if (!rec) return;
   std::vector<TRef> keep = ts;

@@ -75,7 +75,10 @@ hipError_t launch_contract(int mode, const GemmArgs& g, hipStream_t s);
 hipError_t launch_permute(const PermArgs& p, int in_type, const void* in, int out_type, void* out, hipStream_t s);
 hipError_t launch_fill(int type, void* p, double v, int64_t n, hipStream_t s);
 hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
-hipError_t launch_normalize(int type, const NormList& L, int count, hipStream_t s);
+// Workspace of launch_normalize: normalize_work_doubles(count) doubles.
+constexpr int NORM_CHUNKS = 64;   // workgroups per tensor for its sums and its scaling
+int64_t normalize_work_doubles(int count);
+hipError_t launch_normalize(int type, const NormList& L, int count, double* work, hipStream_t s);
 hipError_t launch_svd_weights(const double* s, int64_t r, int64_t stride_s, double* w, int64_t chi, double cutoff,
                               int batch, hipStream_t st);
 // Rows of a column step whose projector signs are fixed (launch_proj_signs).
@@ -109,12 +112,16 @@ hipError_t launch_max_abs(int type, const void* a, const void* b, int64_t n, dou
 
 hipError_t launch_jacobi_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
                                const double* tiny2, int* rot, hipStream_t s);
+// work: frob_tiny_work_doubles(batch) doubles
+int64_t frob_tiny_work_doubles(int batch);
 hipError_t launch_frob_tiny(const double* A, int64_t len, int64_t stride, int batch, double eps, double* tiny2,
-                            hipStream_t s);
+                            double* work, hipStream_t s);
 hipError_t launch_identity(double* V, int64_t n, int64_t stride, int batch, hipStream_t s);
 hipError_t launch_rt_from_qr(const double* A, double* X, int64_t n, int64_t stride, int batch, hipStream_t s);
+// work: jacobi_finish_work_doubles(n, batch) doubles
+int64_t jacobi_finish_work_doubles(int64_t n, int batch);
 hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int64_t stride, int batch, int64_t kmax,
-                                double* sv, double* U, double* Vk, hipStream_t s);
+                                double* sv, double* U, double* Vk, double* work, hipStream_t s);
 
 hipError_t launch_bjac_round(double* A, double* V, int64_t n, int64_t stride, int batch, int round, double tol,
                              const double* tiny2, int inner, int* rot, double* ovl_max, hipStream_t s);

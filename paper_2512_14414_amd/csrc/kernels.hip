@@ -802,41 +802,122 @@ __device__ int64_t sign_entry_256(const T* x, int64_t n, int64_t stride, double*
   return r;
 }
 
-// Frobenius normalisation of a list of tensors, one workgroup per tensor,
-// sums of squares accumulated in FP64, and the sign that makes the entry
-// chosen by sign_entry_256 positive: x <- sign * x / |x|.
-// Optionally stores the signed norm sign * |x| (its reciprocal is the factor
-// the adjoint needs).
+// Frobenius normalisation of a list of tensors with the sign that makes the
+// entry chosen by the gauge rule positive: x <- sign * x / |x|, the sums of
+// squares accumulated in FP64.  Three launches, so that a tensor is read by
+// NORM_CHUNKS workgroups instead of one:
+//  * norm_parts_kernel: per chunk of a tensor, the sum of squares and the
+//    largest magnitude (fixed-order trees);
+//  * norm_sign_kernel, one workgroup per tensor: the norm (chunk sums added in
+//    chunk order), the largest magnitude m, and the sign-deciding entry, the
+//    first with |x| >= (1 - kGaugeTie) m: it lies in the first chunk whose
+//    largest magnitude reaches that threshold (every earlier chunk stays
+//    below it), which is scanned alone; the factor sign / |x| goes to
+//    factor[t], and optionally the signed norm sign * |x| (its reciprocal is
+//    the factor the adjoint needs) to norm_out;
+//  * norm_scale_kernel: x <- factor * x.
+// The chosen entry is the one a scan of the whole tensor would choose.
 template <typename T>
-__global__ __launch_bounds__(256) void normalize_kernel(NormList L) {
-  int t = blockIdx.x;
-  T* x = (T*)L.ptr[t];
-  int64_t n = L.n[t];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) { double v = (double)x[i]; s += v * v; }
-  __shared__ double red[256];
-  __shared__ int64_t idx[256];
-  red[threadIdx.x] = s;
+__global__ __launch_bounds__(256) void norm_parts_kernel(NormList L, double* part) {
+  const int ch = blockIdx.x, t = blockIdx.y;
+  const T* x = (const T*)L.ptr[t];
+  const int64_t n = L.n[t], len = (n + NORM_CHUNKS - 1) / NORM_CHUNKS;
+  const int64_t i0 = (int64_t)ch * len, i1 = i0 + len < n ? i0 + len : n;
+  double s = 0.0, m = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double v = (double)x[i];
+    s += v * v;
+    m = fmax(m, fabs(v));
+  }
+  __shared__ double rs[256], rm[256];
+  rs[threadIdx.x] = s;
+  rm[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
+    }
     __syncthreads();
   }
-  const double nrm = sqrt(red[0]);
-  __syncthreads();
-  const int64_t im = sign_entry_256(x, n, 1, red, idx);
-  const double sg = (n > 0 && (double)x[im] < 0.0) ? -1.0 : 1.0;
-  if (threadIdx.x == 0 && L.norm_out) L.norm_out[t] = sg * nrm;
-  // an updated environment tensor that is zero has lost the whole environment
-  if (threadIdx.x == 0 && L.zero_flag && !(nrm > 0.0)) atomicAdd(L.zero_flag, 1);
-  double inv = nrm > 0.0 ? sg / nrm : 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) x[i] = (T)((double)x[i] * inv);
+  if (threadIdx.x == 0) {
+    part[((int64_t)t * NORM_CHUNKS + ch) * 2] = rs[0];
+    part[((int64_t)t * NORM_CHUNKS + ch) * 2 + 1] = rm[0];
+  }
 }
 
-hipError_t launch_normalize(int type, const NormList& L, int count, hipStream_t s) {
+template <typename T>
+__global__ __launch_bounds__(256) void norm_sign_kernel(NormList L, const double* part, double* factor) {
+  static_assert(NORM_CHUNKS <= 256, "one thread per chunk");
+  const int t = blockIdx.x;
+  const T* x = (const T*)L.ptr[t];
+  const int64_t n = L.n[t], len = (n + NORM_CHUNKS - 1) / NORM_CHUNKS;
+  const double* pt = part + (int64_t)t * NORM_CHUNKS * 2;
+  __shared__ double m_s, thr_s;
+  __shared__ int64_t first[256];
+  __shared__ int chunk_s;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int ch = 0; ch < NORM_CHUNKS; ++ch) m = fmax(m, pt[2 * ch + 1]);
+    const double thr = m * (1.0 - kGaugeTie);
+    int c0 = 0;
+    while (c0 < NORM_CHUNKS - 1 && !(pt[2 * c0 + 1] >= thr)) ++c0;
+    m_s = m;
+    thr_s = thr;
+    chunk_s = c0;
+  }
+  __syncthreads();
+  const double thr = thr_s;
+  const int64_t i0 = (int64_t)chunk_s * len, i1 = i0 + len < n ? i0 + len : n;
+  int64_t bi = n;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256)
+    if (fabs((double)x[i]) >= thr) { bi = i; break; }
+  first[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w && first[threadIdx.x + w] < first[threadIdx.x]) first[threadIdx.x] = first[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int ch = 0; ch < NORM_CHUNKS; ++ch) s += pt[2 * ch];
+    const double nrm = sqrt(s);
+    const int64_t im = first[0] < n ? first[0] : 0;
+    const double sg = (n > 0 && (double)x[im] < 0.0) ? -1.0 : 1.0;
+    if (L.norm_out) L.norm_out[t] = sg * nrm;
+    // an updated environment tensor that is zero has lost the whole environment
+    if (L.zero_flag && !(nrm > 0.0)) atomicAdd(L.zero_flag, 1);
+    factor[t] = nrm > 0.0 ? sg / nrm : 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void norm_scale_kernel(NormList L, const double* factor) {
+  const int ch = blockIdx.x, t = blockIdx.y;
+  T* x = (T*)L.ptr[t];
+  const int64_t n = L.n[t], len = (n + NORM_CHUNKS - 1) / NORM_CHUNKS;
+  const int64_t i0 = (int64_t)ch * len, i1 = i0 + len < n ? i0 + len : n;
+  const double f = factor[t];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) x[i] = (T)((double)x[i] * f);
+}
+
+int64_t normalize_work_doubles(int count) { return (int64_t)count * (2 * NORM_CHUNKS + 1); }
+
+hipError_t launch_normalize(int type, const NormList& L, int count, double* work, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (type == 0) normalize_kernel<double><<<count, 256, 0, s>>>(L);
-  else normalize_kernel<float><<<count, 256, 0, s>>>(L);
+  if (count > NORM_MAX) return hipErrorInvalidValue;
+  double* part = work;
+  double* factor = work + (int64_t)count * 2 * NORM_CHUNKS;
+  const dim3 grid(NORM_CHUNKS, (unsigned)count);
+  if (type == 0) {
+    norm_parts_kernel<double><<<grid, 256, 0, s>>>(L, part);
+    norm_sign_kernel<double><<<count, 256, 0, s>>>(L, part, factor);
+    norm_scale_kernel<double><<<grid, 256, 0, s>>>(L, factor);
+  } else {
+    norm_parts_kernel<float><<<grid, 256, 0, s>>>(L, part);
+    norm_sign_kernel<float><<<count, 256, 0, s>>>(L, part, factor);
+    norm_scale_kernel<float><<<grid, 256, 0, s>>>(L, factor);
+  }
   return hipGetLastError();
 }
 
@@ -1252,26 +1333,42 @@ hipError_t launch_jacobi_round(double* A, double* V, int64_t n, int64_t stride, 
   return hipGetLastError();
 }
 
-// tiny2[b] = (eps * |A_b|_F)^2, one workgroup of 1024 threads per matrix
-// (float64 partial sums per thread, then a fixed-order tree)
-__global__ __launch_bounds__(1024) void frob_tiny_kernel(const double* A, int64_t len, int64_t stride, double eps,
-                                                         double* tiny2) {
-  __shared__ double red[1024];
-  const double* Ab = A + (int64_t)blockIdx.x * stride;
+// tiny2[b] = (eps * |A_b|_F)^2: FROB_CHUNKS workgroups per matrix sum the
+// squares of a chunk each (float64, fixed-order tree), then one thread per
+// matrix adds the chunk sums in chunk order.
+constexpr int FROB_CHUNKS = 64;
+__global__ __launch_bounds__(256) void frob_parts_kernel(const double* A, int64_t len, int64_t stride, double* part) {
+  __shared__ double red[256];
+  const int ch = blockIdx.x, b = blockIdx.y;
+  const double* Ab = A + (int64_t)b * stride;
+  const int64_t cl = (len + FROB_CHUNKS - 1) / FROB_CHUNKS;
+  const int64_t i0 = (int64_t)ch * cl, i1 = i0 + cl < len ? i0 + cl : len;
   double s = 0;
-  for (int64_t i = threadIdx.x; i < len; i += 1024) s += Ab[i] * Ab[i];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += Ab[i] * Ab[i];
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) tiny2[blockIdx.x] = eps * eps * red[0];
+  if (threadIdx.x == 0) part[(int64_t)b * FROB_CHUNKS + ch] = red[0];
 }
 
+__global__ void frob_tiny_kernel(const double* part, int batch, double eps, double* tiny2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double s = 0;
+  for (int ch = 0; ch < FROB_CHUNKS; ++ch) s += part[(int64_t)b * FROB_CHUNKS + ch];
+  tiny2[b] = eps * eps * s;
+}
+
+int64_t frob_tiny_work_doubles(int batch) { return (int64_t)batch * FROB_CHUNKS; }
+
 hipError_t launch_frob_tiny(const double* A, int64_t len, int64_t stride, int batch, double eps, double* tiny2,
-                            hipStream_t s) {
-  frob_tiny_kernel<<<batch, 1024, 0, s>>>(A, len, stride, eps, tiny2);
+                            double* work, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  frob_parts_kernel<<<dim3(FROB_CHUNKS, (unsigned)batch), 256, 0, s>>>(A, len, stride, work);
+  frob_tiny_kernel<<<(batch + 63) / 64, 64, 0, s>>>(work, batch, eps, tiny2);
   return hipGetLastError();
 }
 
@@ -1307,27 +1404,34 @@ hipError_t launch_identity(double* V, int64_t n, int64_t stride, int batch, hipS
 // After convergence: s_j = |a_j|; the k largest (k <= kmax) in descending
 // order go to sv[b][k], their left vectors a_j / s_j to U[b] (n x kmax,
 // column-major) and right vectors to Vk[b] (n x kmax); all n sorted values are
-// written to sv (length n per matrix).  One workgroup of 1024 threads per
-// matrix: a wave per column for the norms (rows across the lanes), ranks by
-// counting (n <= 4096), ties broken by column index, then the selected columns
-// copied with the rows across the threads.
-__global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* A, const double* V, int64_t n, int64_t stride,
-                                                             int64_t kmax, double* sv, double* U, double* Vk) {
-  extern __shared__ double nrm[];             // n norms, then n column indices by rank (as int)
-  int* by_rank = (int*)(nrm + n);
-  const int b = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// written to sv (length n per matrix).  Three launches:
+//  * col_norms_kernel: one wave per column (rows across the lanes, then a
+//    butterfly over the wave), four columns per workgroup;
+//  * rank_kernel, one workgroup of 1024 threads per matrix: ranks by counting
+//    (ties broken by column index), the sorted values and the column of each
+//    rank;
+//  * gather_kernel: the selected columns, scaled, with the elements across
+//    the whole grid.
+// work holds n norms and then n ranks (as int) per matrix.
+__global__ __launch_bounds__(256) void col_norms_kernel(const double* A, int64_t n, int64_t stride, double* nrm) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.y;
+  if (j >= n) return;
   const double* Ab = A + (int64_t)b * stride;
-  const double* Vb = V + (int64_t)b * stride;
-  for (int64_t j = wave; j < n; j += 16) {
-    double s = 0;
-    for (int64_t i = lane; i < n; i += 64) { const double x = Ab[j * n + i]; s += x * x; }
+  double s = 0;
+  for (int64_t i = lane; i < n; i += 64) { const double x = Ab[j * n + i]; s += x * x; }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) nrm[j] = sqrt(s);
-  }
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) nrm[(int64_t)b * n + j] = sqrt(s);
+}
+
+__global__ __launch_bounds__(1024) void rank_kernel(const double* nrm_g, int64_t n, double* sv, int* by_rank_g) {
+  extern __shared__ double nrm[];
+  const int b = blockIdx.x;
+  for (int64_t j = threadIdx.x; j < n; j += 1024) nrm[j] = nrm_g[(int64_t)b * n + j];
   __syncthreads();
-  for (int64_t j = tid; j < n; j += 1024) {
+  for (int64_t j = threadIdx.x; j < n; j += 1024) {
     const double v = nrm[j];
     int64_t rank = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -1335,24 +1439,37 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* A, co
       rank += (w > v) || (w == v && i < j);
     }
     sv[(int64_t)b * n + rank] = v;
-    by_rank[rank] = (int)j;
-  }
-  __syncthreads();
-  const int64_t kk = kmax < n ? kmax : n;
-  for (int64_t e = tid; e < kk * n; e += 1024) {
-    const int64_t r = e / n, i = e - r * n;
-    const int64_t j = by_rank[r];
-    const double v = nrm[j];
-    const double inv = v > 0 ? 1.0 / v : 0.0;
-    U[(int64_t)b * n * kmax + r * n + i] = Ab[j * n + i] * inv;
-    Vk[(int64_t)b * n * kmax + r * n + i] = Vb[j * n + i];
+    by_rank_g[(int64_t)b * n + rank] = (int)j;
   }
 }
 
+__global__ void gather_kernel(const double* __restrict__ A, const double* __restrict__ V, int64_t n, int64_t stride,
+                              int64_t kk, int64_t kmax, const double* __restrict__ nrm, const int* __restrict__ by_rank,
+                              int batch, double* __restrict__ U, double* __restrict__ Vk) {
+  const int64_t total = kk * n * batch;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / (kk * n), e = t - b * kk * n;
+    const int64_t r = e / n, i = e - r * n;
+    const int64_t j = by_rank[b * n + r];
+    const double v = nrm[b * n + j];
+    const double inv = v > 0 ? 1.0 / v : 0.0;
+    U[b * n * kmax + r * n + i] = A[b * stride + j * n + i] * inv;
+    Vk[b * n * kmax + r * n + i] = V[b * stride + j * n + i];
+  }
+}
+
+int64_t jacobi_finish_work_doubles(int64_t n, int batch) { return 2 * n * batch; }
+
 hipError_t launch_jacobi_finish(const double* A, const double* V, int64_t n, int64_t stride, int batch, int64_t kmax,
-                                double* sv, double* U, double* Vk, hipStream_t s) {
+                                double* sv, double* U, double* Vk, double* work, hipStream_t s) {
   if (n > 4096) return hipErrorInvalidValue;
-  jacobi_finish_kernel<<<batch, 1024, n * (sizeof(double) + sizeof(int)), s>>>(A, V, n, stride, kmax, sv, U, Vk);
+  if (batch <= 0 || n <= 0) return hipSuccess;
+  double* nrm = work;
+  int* by_rank = (int*)(work + n * batch);
+  col_norms_kernel<<<dim3((unsigned)((n + 3) / 4), (unsigned)batch), 256, 0, s>>>(A, n, stride, nrm);
+  rank_kernel<<<batch, 1024, n * sizeof(double), s>>>(nrm, n, sv, by_rank);
+  const int64_t kk = kmax < n ? kmax : n;
+  if (kk > 0) gather_kernel<<<grid_for(kk * n * batch), 256, 0, s>>>(A, V, n, stride, kk, kmax, nrm, by_rank, batch, U, Vk);
   return hipGetLastError();
 }
 

@@ -239,22 +239,31 @@ __global__ __launch_bounds__(NTT) void panel_kernel(double* A, int64_t rs, int64
   // T of the block reflector (LAPACK's larft, forward, columnwise) from
   // G = V^T V (upper triangle, gathered above): T_cc = tau_c,
   // T[i][c] = -tau_c sum_{l=i}^{c-1} T[i][l] G[l][c]; thread i < NB computes
-  // row i (it depends on that row only)
+  // row i (it depends on that row only).  The row stays in registers (the
+  // loops are unrolled), so the chain of sums waits on arithmetic, not on
+  // LDS round trips; the terms are added in the same order, l = i, ..., c - 1.
   __syncthreads();
   if (tid < NB) {
     const int i = tid;
     double* Tb = T + (int64_t)b * T_stride;
-#pragma unroll 1
+    double trow[NB];
+#pragma unroll
     for (int c = 0; c < NB; ++c) {
       double v = 0.0;
       if (c < nbp && c == i) v = taus_s[c];
       else if (c < nbp && c > i) {
         double s = 0.0;
-        for (int l = i; l < c; ++l) s += Tr[i][l] * Gs[l][c];
+#pragma unroll
+        for (int l = 0; l < c; ++l)
+          if (l >= i) s += trow[l] * Gs[l][c];
         v = -taus_s[c] * s;
       }
-      Tr[i][c] = v;
-      Tb[i * NB + c] = v;
+      trow[c] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      Tr[i][c] = trow[c];
+      Tb[i * NB + c] = trow[c];
     }
     if (i < nbp) tau[(int64_t)b * tau_stride + j0 + i] = taus_s[i];
   }

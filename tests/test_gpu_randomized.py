@@ -7,9 +7,11 @@ matrix (Halko, Martinsson, Tropp 2011, Algorithms 4.4 and 5.1), with the test
 matrix drawn from SplitMix64 by a counter rule that both sides implement.
 The library must follow that oracle (same test matrix, same passes): after
 several sweeps of weakly entangled states the environments (gauge-fixed, so
-entry by entry) and energies agree; against the exact SVD the randomized
+entry by entry, to 1e-6 or to ten times their own sensitivity to rounding,
+whichever is larger) and energies agree; against the exact SVD the randomized
 sweep differs by the truncation of the range finder, reported here.
 """
+import numpy as np
 import pytest
 import torch
 
@@ -52,16 +54,24 @@ def test_randomized_sweeps_match_oracle(ctm_mod, name, nt, D, chi, pattern, swee
     g.sweep(sweeps)
     o = OCTM(A, pattern, chi)
     o.run(sweeps, proj=projector_fn(8, power, 3))
-    env_err = (g.get_env().cpu() - env_to_flat(o.env, o.sites, chi)).abs().max().item()
+    ref = env_to_flat(o.env, o.sites, chi)
+    env_err = (g.get_env().cpu() - ref).abs().max().item()
+    # the environment's own sensitivity to rounding: the oracle's change when
+    # every entry of A moves by a relative 1e-15
+    Ap = A * (1 + 1e-15 * np.random.default_rng(1).standard_normal(A.shape))
+    op = OCTM(Ap, pattern, chi)
+    op.run(sweeps, proj=projector_fn(8, power, 3))
+    sens = (env_to_flat(op.env, op.sites, chi) - ref).abs().max().item()
     E, Eo = g.energy(H, terms), oenergy(o, H, terms).item()
     ex = OCTM(A, pattern, chi)
     ex.run(sweeps)
     Eex = oenergy(ex, H, terms).item()
-    print(f"{name} q={power}: max |env_gpu - env_oracle| {env_err:.2e}; E {E:.14f} |dE| {abs(E - Eo):.2e}; "
-          f"randomized vs exact SVD: |dE| {abs(Eo - Eex):.2e}")
+    print(f"{name} q={power}: max |env_gpu - env_oracle| {env_err:.2e} (rounding sensitivity {sens:.1e}); "
+          f"E {E:.14f} |dE| {abs(E - Eo):.2e}; randomized vs exact SVD: |dE| {abs(Eo - Eex):.2e}")
     # kept directions with small singular values carry weights s^(-1/2) and
-    # amplify rounding in their entries (the energy does not see it)
-    assert env_err < 1e-6
+    # amplify rounding in their entries (the energy does not see it): the bar
+    # is 1e-6 or ten times the measured sensitivity, whichever is larger
+    assert env_err < max(1e-6, 10 * sens)
     assert abs(E - Eo) < 1e-10
 
 
