@@ -96,15 +96,47 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // other half to the partner lane and adds what it receives, so lane l ends
 // with the wave total of value l / (64 / NV).  x is overwritten.  The levels
 // are template recursion so that every index is a compile-time constant.
+// At the levels of masks 32 and 16, gfx950's lane swaps do the exchange of a
+// pair (x[i], x[i + H]) in place: v_permlane32_swap(a, b) exchanges the upper
+// half of the wave's a with the lower half of its b, so that afterwards a + b
+// is, in the lower half, a's sum over the two halves and, in the upper half,
+// b's (v_permlane16_swap likewise for the odd and even rows of 16 lanes).
+// The sums are the ones the select-and-exchange form computes (own value plus
+// partner's value, in either order).
+template <int MASK>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+  const unsigned alo = (unsigned)__double_as_longlong(a), ahi = (unsigned)((unsigned long long)__double_as_longlong(a) >> 32);
+  const unsigned blo = (unsigned)__double_as_longlong(b), bhi = (unsigned)((unsigned long long)__double_as_longlong(b) >> 32);
+  unsigned rlo[2], rhi[2];
+  if constexpr (MASK == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    rlo[0] = l[0]; rlo[1] = l[1]; rhi[0] = h[0]; rhi[1] = h[1];
+  } else {
+    static_assert(MASK == 16, "lane mask");
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    rlo[0] = l[0]; rlo[1] = l[1]; rhi[0] = h[0]; rhi[1] = h[1];
+  }
+  const double a2 = __longlong_as_double((long long)(((unsigned long long)rhi[0] << 32) | rlo[0]));
+  const double b2 = __longlong_as_double((long long)(((unsigned long long)rhi[1] << 32) | rlo[1]));
+  return a2 + b2;
+}
+
 template <int H, int MASK>
 __device__ __forceinline__ void halving(double* x, int lane) {
   if constexpr (H >= 1) {
-    const bool hi = lane & MASK;
+    if constexpr (MASK == 32 || MASK == 16) {
 #pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const double send = hi ? x[i] : x[i + H];
-      const double keep = hi ? x[i + H] : x[i];
-      x[i] = keep + xor_lane<MASK>(send, lane);
+      for (int i = 0; i < H; ++i) x[i] = swap_sum<MASK>(x[i], x[i + H]);
+    } else {
+      const bool hi = lane & MASK;
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        const double send = hi ? x[i] : x[i + H];
+        const double keep = hi ? x[i + H] : x[i];
+        x[i] = keep + xor_lane<MASK>(send, lane);
+      }
     }
     halving<H / 2, MASK / 2>(x, lane);
   }
@@ -239,26 +271,27 @@ __global__ __launch_bounds__(NTT) void panel_kernel(double* A, int64_t rs, int64
   // T of the block reflector (LAPACK's larft, forward, columnwise) from
   // G = V^T V (upper triangle, gathered above): T_cc = tau_c,
   // T[i][c] = -tau_c sum_{l=i}^{c-1} T[i][l] G[l][c]; thread i < NB computes
-  // row i (it depends on that row only).  The row stays in registers (the
-  // loops are unrolled), so the chain of sums waits on arithmetic, not on
-  // LDS round trips; the terms are added in the same order, l = i, ..., c - 1.
+  // row i (it depends on that row only).  The sums are formed term by term as
+  // the row's entries become known (entry l adds its terms to the sums of all
+  // later columns), each in the order l = i, ..., c - 1, so that the chain
+  // from one entry to the next is one product and one sum; the row and the
+  // sums stay in registers.  The entries left of the diagonal are zero and
+  // add exact zeros (the sums start at +0 and never become -0), so every
+  // step runs the same instructions, without branches.
   __syncthreads();
   if (tid < NB) {
     const int i = tid;
     double* Tb = T + (int64_t)b * T_stride;
-    double trow[NB];
+    double trow[NB], sum[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      double v = 0.0;
-      if (c < nbp && c == i) v = taus_s[c];
-      else if (c < nbp && c > i) {
-        double s = 0.0;
+    for (int c = 0; c < NB; ++c) sum[c] = 0.0;
 #pragma unroll
-        for (int l = 0; l < c; ++l)
-          if (l >= i) s += trow[l] * Gs[l][c];
-        v = -taus_s[c] * s;
-      }
-      trow[c] = v;
+    for (int l = 0; l < NB; ++l) {
+      const double tl = taus_s[l];
+      const double v = (l < nbp && l == i) ? tl : ((l < nbp && l > i) ? -tl * sum[l] : 0.0);
+      trow[l] = v;
+#pragma unroll
+      for (int c = l + 1; c < NB; ++c) sum[c] += v * Gs[l][c];
     }
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
@@ -281,14 +314,18 @@ __global__ __launch_bounds__(NTT) void panel_kernel(double* A, int64_t rs, int64
     double* Yr = Y + ((int64_t)b * L + r) * NB;
 #pragma unroll
     for (int c = 0; c < NB; ++c) Vr[c] = v[c];
-    // the sums of build_vy_kernel, in its order
-#pragma unroll 1
-    for (int c = 0; c < NB; ++c) {
-      double y = 0.0;
+    // the sums of build_vy_kernel, in its order (l = 0, ..., NB - 1 for every
+    // column), all columns at once: one row of T per step
+    // (T is upper triangular: the terms l > c are exact zeros and left out)
+    double y[NB];
 #pragma unroll
-      for (int l = 0; l < NB; ++l) y += v[l] * Tr[l][c];
-      Yr[c] = y;
-    }
+    for (int c = 0; c < NB; ++c) y[c] = 0.0;
+#pragma unroll
+    for (int l = 0; l < NB; ++l)
+#pragma unroll
+      for (int c = l; c < NB; ++c) y[c] += v[l] * Tr[l][c];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Yr[c] = y[c];
   }
 }
 
