@@ -292,6 +292,26 @@ int ctm_observables(ctm_ctx* ctx, double* out, int capacity, int* n);
  *                 of partial sums. */
 int ctm_set_option(ctm_ctx* ctx, const char* key, double value);
 
+/* Device memory from the caller's allocator (the boundary's ownership rule:
+ * the context owns its memory, and a framework's caching allocator, such as
+ * PyTorch's, may back it).  From this call on, every new block the context
+ * needs comes from alloc(bytes, stream, user), which returns a device pointer
+ * aligned to 256 bytes, or NULL when it has no memory (the library then
+ * returns the cached blocks of all its contexts and asks once more; if that
+ * fails too, the call that needed the block fails with CTM_ENOMEM).  stream is the context's stream that will use
+ * the block (a hipStream_t as void*: the stream given to ctm_init, or the
+ * context's second stream).  The context keeps freed blocks for reuse and
+ * hands each back with free(ptr, stream, user), to the allocator that made
+ * it and with the stream it was made for, when it releases its cache: at
+ * ctm_free at the latest, or earlier when an allocation fails.  Blocks made
+ * before the call keep their allocator (the device's stream-ordered pool by
+ * default).  Both callbacks run on the thread that calls into the context.
+ * alloc = free = NULL restores the default for new blocks; CTM_EINVAL when
+ * exactly one of them is NULL. */
+typedef void* (*ctm_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*ctm_free_fn)(void* ptr, void* stream, void* user);
+int ctm_set_allocator(ctm_ctx* ctx, ctm_alloc_fn alloc, ctm_free_fn free, void* user);
+
 /* Live timing of the library's main kernel families.  Between
  * ctm_profile_begin and ctm_profile_end every launch of a timed family, by
  * any context of the process, is bracketed by two HIP events on its stream.

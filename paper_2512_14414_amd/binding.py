@@ -29,6 +29,11 @@ class Term(ctypes.Structure):
                 ("coef", ctypes.c_double)]
 
 
+# ctm_alloc_fn / ctm_free_fn of include/ctm.h
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2512_14414_amd.build")
@@ -51,6 +56,7 @@ def _load():
         "ctm_observables": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
         "ctm_corner_spectra": (I, [P, ctypes.POINTER(D), I64, ctypes.POINTER(I64)]),
         "ctm_set_option": (I, [P, ctypes.c_char_p, D]),
+        "ctm_set_allocator": (I, [P, ALLOC_FN, FREE_FN, P]),
         "ctm_profile_begin": (I, [P]),
         "ctm_profile_end": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "ctm_last_error": (ctypes.c_char_p, [P]),
@@ -66,7 +72,7 @@ LIB = _load()
 EXPORTED = ("ctm_init", "ctm_init_double_layer", "ctm_set_tensors", "ctm_reset_env", "ctm_env_size", "ctm_set_env", "ctm_get_env",
             "ctm_sweep", "ctm_corner_spectra", "ctm_energy", "ctm_energy_grad", "ctm_energy_grad_fp", "ctm_last_rdms",
             "ctm_observables",
-            "ctm_set_option", "ctm_profile_begin", "ctm_profile_end",
+            "ctm_set_option", "ctm_set_allocator", "ctm_profile_begin", "ctm_profile_end",
             "ctm_last_error", "ctm_free")
 
 
@@ -80,6 +86,24 @@ def _terms(terms):
 def _hbond(H):
     vals = torch.as_tensor(H, dtype=torch.float64).reshape(-1).tolist()
     return (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+
+
+def torch_allocator(device=None):
+    """(alloc, free) for CTM.set_allocator backed by PyTorch's caching allocator:
+    alloc(nbytes, stream) -> device pointer (0 when it has no memory),
+    free(ptr, stream)."""
+    dev = torch.cuda.current_device() if device is None else device
+
+    def alloc(nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(nbytes, device=dev, stream=stream)
+        except RuntimeError:
+            return 0
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
 
 
 def _dptr(t: torch.Tensor, dtype=torch.float64):
@@ -128,6 +152,24 @@ class CTM:
             self.close()
         except Exception:
             pass
+
+    def set_allocator(self, alloc=None, free=None):
+        """ctm_set_allocator: new device blocks of the context from alloc(nbytes,
+        stream) -> pointer (0 for none) and back through free(ptr, stream), with
+        stream the integer hipStream_t of the context's stream that uses the
+        block; torch_allocator() gives PyTorch's caching allocator.  No
+        arguments restore the default for new blocks."""
+        if (alloc is None) != (free is None):
+            raise ValueError("alloc and free must both be given or both be None")
+        if alloc is None:
+            cbs = (ALLOC_FN(), FREE_FN())
+        else:
+            cbs = (ALLOC_FN(lambda n, st, u: alloc(int(n), st or 0) or None),
+                   FREE_FN(lambda ptr, st, u: free(ptr, st or 0)))
+        self._check(LIB.ctm_set_allocator(self._h, cbs[0], cbs[1], None))
+        # every pair stays referenced as long as the object: blocks are handed
+        # back through the callbacks that made them, inside ctm_free at the latest
+        self._alloc_keep = getattr(self, "_alloc_keep", []) + [cbs]
 
     def set_tensors(self, A):
         self.A = torch.as_tensor(A, dtype=torch.float64).cuda().contiguous()

@@ -2217,6 +2217,21 @@ int ctm_set_option(ctm_ctx* c, const char* key, double value) {
   return CTM_OK;
 }
 
+int ctm_set_allocator(ctm_ctx* c, ctm_alloc_fn alloc, ctm_free_fn free_fn, void* user) {
+  if (!c) return CTM_EINVAL;
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    c->err = "ctm_set_allocator: alloc and free must both be given or both be NULL";
+    return CTM_EINVAL;
+  }
+  Dev::UserAlloc ua;
+  ua.alloc = alloc;
+  ua.free = free_fn;
+  ua.user = user;
+  c->dev.ua = ua;
+  c->side.ua = ua;
+  return CTM_OK;
+}
+
 int ctm_profile_begin(ctm_ctx* c) {
   if (!c) return CTM_EINVAL;
   try {

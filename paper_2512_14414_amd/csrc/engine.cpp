@@ -128,8 +128,12 @@ Dev::~Dev() {
   devs().erase(this);
 }
 
-// Every cache of the process back to the pool, then wait until the frees are done.
+// Every cache of the process back to the pool (or to the caller allocator
+// that made the block), then wait until the frees are done.  The device is
+// synchronised first: a cached block may have been used last on another
+// stream than the one it is freed on.
 static void release_all_caches() {
+  (void)hipDeviceSynchronize();
   {
     std::lock_guard<std::mutex> lock(devs_mu());
     for (Dev* d : devs()) d->release();
@@ -160,6 +164,17 @@ void* Dev::take(size_t bytes) {
     return p;
   }
   void* p = nullptr;
+  if (ua.alloc) {
+    p = ua.alloc(sz, (void*)stream, ua.user);
+    if (!p) {
+      release_all_caches();
+      p = ua.alloc(sz, (void*)stream, ua.user);
+    }
+    if (!p) throw Error(-2, "the caller's allocator returned no block of " + std::to_string(sz) + " bytes");
+    user_blocks[p] = ua;
+    live[p] = sz;
+    return p;
+  }
   hipError_t e = hipMallocAsync(&p, sz, stream);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
@@ -184,7 +199,16 @@ void Dev::give(void* p) {
 
 void Dev::release() {
   for (auto& kv : cached)
-    for (void* p : kv.second) (void)hipFreeAsync(p, stream);
+    for (void* p : kv.second) {
+      auto u = user_blocks.find(p);
+      if (u != user_blocks.end()) {
+        const UserAlloc a = u->second;
+        user_blocks.erase(u);
+        a.free(p, (void*)stream, a.user);
+      } else {
+        (void)hipFreeAsync(p, stream);
+      }
+    }
   cached.clear();
 }
 

@@ -75,6 +75,16 @@ struct Dev {
   size_t arena_bytes = 0, arena_used = 0;
   std::unordered_map<void*, size_t> live;                    // block -> size class
   std::unordered_map<size_t, std::vector<void*>> cached;     // size class -> free blocks
+  // Optional caller allocator (ctm_set_allocator): while set, new blocks come
+  // from it; every block goes back to the allocator that made it when the
+  // cache is released.
+  struct UserAlloc {
+    void* (*alloc)(size_t bytes, void* stream, void* user) = nullptr;
+    void (*free)(void* ptr, void* stream, void* user) = nullptr;
+    void* user = nullptr;
+  };
+  UserAlloc ua;
+  std::unordered_map<void*, UserAlloc> user_blocks;
   Dev();
   Dev(const Dev&) = delete;
   Dev& operator=(const Dev&) = delete;

@@ -6,7 +6,9 @@
 * no energy terms (E = 0, gradient 0), zero sweeps, a chain of 0
   differentiated sweeps (the energy's own derivative at a fixed environment);
 * invalid terms and a too small corner-spectra buffer are refused with
-  CTM_EINVAL and leave the context usable.
+  CTM_EINVAL and leave the context usable;
+* a caller allocator behind a context (ctm_set_allocator) gives the default
+  allocator's results and gets every block back.
 """
 import ctypes
 
@@ -102,3 +104,61 @@ def test_invalid_terms_and_small_buffers_are_refused(ctm_mod):
     # the context still works
     g.sweep(2)
     assert np.isfinite(g.energy(H, synth.heisenberg_terms(1, 1)))
+
+
+def test_caller_allocator_backs_the_context(ctm_mod):
+    """ctm_set_allocator: with PyTorch's caching allocator behind a context
+    (through counting wrappers), sweeps, the energy and E&grad give the
+    default allocator's results bit for bit, the new blocks come from the
+    caller's allocator, and every one of them is handed back, with the stream
+    it was made for, by ctm_free at the latest."""
+    A = synth.near_product_tensors(4, 2, 3, 11, 0.3)
+    pattern, chi = [[0, 1], [2, 3]], 12
+    terms = synth.shastry_sutherland_terms(0.7, 1.0)
+
+    def run(g):
+        g.set_option("svd_cutoff", 1e-6)
+        g.sweep(4)
+        E = g.energy(H, terms)
+        Eg, grad = g.energy_grad(2, H, terms)
+        return g.get_env().cpu().clone(), E, Eg, grad.cpu().clone()
+
+    g0 = ctm_mod.CTM(A, pattern, chi)
+    ref = run(g0)
+    g0.close()
+    talloc, tfree = ctm_mod.torch_allocator()
+    live = {}
+    counts = {"alloc": 0, "free": 0}
+
+    def alloc(n, stream):
+        p = talloc(n, stream)
+        if p:
+            live[p] = stream
+            counts["alloc"] += 1
+        return p
+
+    def free(p, stream):
+        assert live.pop(p) == stream
+        counts["free"] += 1
+        tfree(p, stream)
+
+    g1 = ctm_mod.CTM(A, pattern, chi)
+    g1.set_allocator(alloc, free)
+    out = run(g1)
+    assert counts["alloc"] > 0
+    g1.close()
+    print(f"caller allocator: {counts['alloc']} blocks made, {counts['free']} handed back")
+    assert not live and counts["free"] == counts["alloc"]
+    for a, b in zip(ref, out):
+        if isinstance(a, torch.Tensor):
+            assert torch.equal(a, b)
+        else:
+            assert a == b
+    # exactly one of the two callbacks: refused by the binding and by the library
+    g2 = ctm_mod.CTM(A, pattern, chi)
+    with pytest.raises(ValueError):
+        g2.set_allocator(alloc, None)
+    from paper_2512_14414_amd.binding import ALLOC_FN, FREE_FN
+    only_free = FREE_FN(lambda p, st, u: None)
+    assert ctm_mod.LIB.ctm_set_allocator(g2._h, ALLOC_FN(), only_free, None) == -1
+    g2.sweep(1)
