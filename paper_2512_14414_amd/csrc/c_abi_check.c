@@ -5,8 +5,10 @@
  * the Heisenberg model against its closed form, -1/4 per bond, two bonds per
  * site: -1/2.  Also checks that an invalid chi is refused before any device
  * work with CTM_EINVAL and a message.  Device memory for the site tensors is
- * allocated with the HIP runtime, as any C caller would.  Exit status 0 on
- * success. */
+ * allocated with the HIP runtime, as any C caller would; a second context
+ * takes its own device memory from the caller's allocator (ctm_set_allocator,
+ * hipMalloc/hipFree with a count of the live blocks) and must hand every
+ * block back by ctm_free.  Exit status 0 on success. */
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -23,6 +25,45 @@
       return 1;                           \
     }                                     \
   } while (0)
+
+/* caller allocator: hipMalloc / hipFree with a count of the live blocks */
+static int g_live = 0, g_made = 0;
+static void* my_alloc(size_t bytes, void* stream, void* user) {
+  (void)stream;
+  (void)user;
+  void* p = NULL;
+  if (hipMalloc(&p, bytes) != hipSuccess) return NULL;
+  ++g_live;
+  ++g_made;
+  return p;
+}
+static void my_free(void* p, void* stream, void* user) {
+  (void)stream;
+  (void)user;
+  if (hipFree(p) == hipSuccess) --g_live;
+}
+
+/* the Neel state's energy per site after 4 sweeps, with or without the caller allocator */
+static int neel_energy(const double* dA, const int* pattern, const double* H, const ctm_term* terms, int nterm,
+                       int caller_alloc, double* E, int* sweeps) {
+  enum { d = 2, D = 1, chi = 2, Lx = 2, Ly = 2, nt = 2 };
+  ctm_ctx* ctx = NULL;
+  int rc = ctm_init(&ctx, dA, d, D, chi, Lx, Ly, pattern, nt, CTM_FP64, NULL);
+  CHECK(rc == CTM_OK, "ctm_init: %d %s", rc, ctm_last_error(NULL));
+  if (caller_alloc) {
+    rc = ctm_set_allocator(ctx, my_alloc, NULL, NULL);
+    CHECK(rc == CTM_EINVAL, "ctm_set_allocator with one callback not refused (rc %d)", rc);
+    rc = ctm_set_allocator(ctx, my_alloc, my_free, NULL);
+    CHECK(rc == CTM_OK, "ctm_set_allocator: %d %s", rc, ctm_last_error(ctx));
+  }
+  double delta = 0.0;
+  rc = ctm_sweep(ctx, 4, 0.0, sweeps, &delta);
+  CHECK(rc == CTM_OK && *sweeps == 4, "ctm_sweep: %d %s", rc, ctm_last_error(ctx));
+  rc = ctm_energy(ctx, H, nterm, terms, E);
+  CHECK(rc == CTM_OK, "ctm_energy: %d %s", rc, ctm_last_error(ctx));
+  ctm_free(ctx);
+  return 0;
+}
 
 int main(void) {
   enum { d = 2, D = 1, chi = 2, Lx = 2, Ly = 2, nt = 2 };
@@ -54,18 +95,15 @@ int main(void) {
   double* dA = NULL;
   CHECK(hipMalloc((void**)&dA, sizeof hA) == hipSuccess, "hipMalloc failed");
   CHECK(hipMemcpy(dA, hA, sizeof hA, hipMemcpyHostToDevice) == hipSuccess, "hipMemcpy failed");
-  ctm_ctx* ctx = NULL;
-  rc = ctm_init(&ctx, dA, d, D, chi, Lx, Ly, pattern, nt, CTM_FP64, NULL);
-  CHECK(rc == CTM_OK, "ctm_init: %d %s", rc, ctm_last_error(NULL));
   int sweeps = 0;
-  double delta = 0.0, E = 0.0;
-  rc = ctm_sweep(ctx, 4, 0.0, &sweeps, &delta);
-  CHECK(rc == CTM_OK && sweeps == 4, "ctm_sweep: %d %s", rc, ctm_last_error(ctx));
-  rc = ctm_energy(ctx, H, nterm, terms, &E);
-  CHECK(rc == CTM_OK, "ctm_energy: %d %s", rc, ctm_last_error(ctx));
+  double E = 0.0, E2 = 0.0;
+  if (neel_energy(dA, pattern, H, terms, nterm, 0, &E, &sweeps)) return 1;
   CHECK(fabs(E + 0.5) < 1e-12, "Neel energy %.15f, expected -0.5", E);
-  ctm_free(ctx);
+  if (neel_energy(dA, pattern, H, terms, nterm, 1, &E2, &sweeps)) return 1;
+  CHECK(E2 == E, "caller allocator: energy %.17g, default allocator %.17g", E2, E);
+  CHECK(g_made > 0 && g_live == 0, "caller allocator: %d blocks made, %d not handed back", g_made, g_live);
   CHECK(hipFree(dA) == hipSuccess, "hipFree failed");
-  printf("c_abi_check: Neel state, E = %.15f per site after %d sweeps\n", E, sweeps);
+  printf("c_abi_check: Neel state, E = %.15f per site after %d sweeps; caller allocator %d blocks, all back\n", E,
+         sweeps, g_made);
   return 0;
 }

@@ -1,7 +1,8 @@
 """The C ABI from a plain C program (paper_2512_14414_amd/csrc/c_abi_check.c,
 built by build.py next to the library): the Neel state's energy per site,
--1/2, and an invalid chi refused with CTM_EINVAL, without Python in the
-process."""
+-1/2, an invalid chi refused with CTM_EINVAL, and a second context on a
+caller allocator (hipMalloc/hipFree) with the same energy and every block
+handed back, without Python in the process."""
 import os
 import subprocess
 
@@ -22,3 +23,4 @@ def test_c_program_on_the_c_abi():
     print(r.stdout, r.stderr)
     assert r.returncode == 0, r.stderr
     assert "E = -0.500000000000000" in r.stdout
+    assert "all back" in r.stdout
