@@ -1676,10 +1676,12 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 constexpr int BJ_GS = BJ_C + 1;   // padded row stride of G and R (column accesses spread over banks)
+constexpr int BJ_SR = 4 * BJ_GK;   // rows of a wave's Gram block (GK k-steps of 4)
 struct BjacShared {
   double part[BJ_NW][BJ_C * BJ_C];   // per-wave Gram partials
   double G[BJ_C * BJ_GS];
   double R[BJ_C * BJ_GS];
+  double stage[BJ_NW][BJ_SR * BJ_GS];   // per-wave Gram block, [row][column], padded rows
   int nrot;
 };
 
@@ -1743,18 +1745,30 @@ __device__ __forceinline__ void bjac_round(BjacShared& sh, double* A, double* V,
   const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lq = lane >> 4;
 
   // ---- Gram matrix: wave w takes the k-steps [w GK, (w + 1) GK) + j NW GK;
-  // lane (lr, lq) holds X[4 k + lq][lr]
+  // lane (lr, lq) holds X[4 k + lq][lr].  The block of 4 GK rows x C columns
+  // is loaded with 32 lanes per column (consecutive rows, so that a load
+  // instruction reads two 256-byte column segments instead of C 32-byte
+  // pieces) into the wave's LDS stage, and read back in the operand layout.
   {
     d4_t gacc = {0.0, 0.0, 0.0, 0.0};
     const int64_t nks = (n + 3) / 4;
-    const int64_t gl = gcol(lr);
+    double* stg = sh.stage[wave];
+    const int sr = lane & 31, sc = lane >> 5;
+    static_assert(BJ_SR == 32 && BJ_C % 2 == 0, "two columns of 32 rows per load instruction");
     for (int64_t kb = (int64_t)wave * BJ_GK; kb < nks; kb += (int64_t)BJ_GK * BJ_NW) {
+      double y[BJ_C / 2];
+#pragma unroll
+      for (int i = 0; i < BJ_C / 2; ++i) {
+        const int64_t g = gcol(2 * i + sc), row = kb * 4 + sr;
+        y[i] = (g >= 0 && row < n) ? col_load<COH>(Ab + g * n + row) : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < BJ_C / 2; ++i) stg[sr * BJ_GS + 2 * i + sc] = y[i];
+      wave_sync();
       double x[BJ_GK];
 #pragma unroll
-      for (int u = 0; u < BJ_GK; ++u) {
-        const int64_t row = (kb + u) * 4 + lq;
-        x[u] = (gl >= 0 && row < n) ? col_load<COH>(Ab + gl * n + row) : 0.0;
-      }
+      for (int u = 0; u < BJ_GK; ++u) x[u] = stg[(4 * u + lq) * BJ_GS + lr];
+      wave_sync();   // the reads are done before the next block's writes
 #pragma unroll
       for (int u = 0; u < BJ_GK; ++u) gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], gacc, 0, 0, 0);
     }
