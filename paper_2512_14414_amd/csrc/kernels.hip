@@ -695,8 +695,61 @@ static unsigned grid_for(int64_t total) {
   return (unsigned)b;
 }
 
+// A permutation whose fastest output axis X is not the fastest input axis Y
+// (in-stride 1) is a batch of 2-D transposes: 32 x 32 tiles go through LDS,
+// read along Y and written along X, so that both sides are coalesced (the
+// element loop above reads one element per cache line).  The other axes form
+// the batch (blockIdx.y, decomposed over them in order).  Every element is
+// converted and stored or added once, as above.
+constexpr int TR_T = 32;
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void transpose_kernel(PermArgs p, int ax, const TI* __restrict__ in,
+                                                        TO* __restrict__ out) {
+  __shared__ TO tile[TR_T][TR_T + 1];
+  const int X = p.ndim - 1;
+  const int64_t dx = p.dims[X], dy = p.dims[ax];
+  const int64_t tiles_x = (dx + TR_T - 1) / TR_T;
+  const int64_t x0 = ((int64_t)blockIdx.x % tiles_x) * TR_T, y0 = ((int64_t)blockIdx.x / tiles_x) * TR_T;
+  int64_t b = blockIdx.y, off_in = 0, off_out = 0;
+  for (int i = X - 1; i >= 0; --i) {
+    if (i == ax) continue;
+    const int64_t q = b / p.dims[i], idx = b - q * p.dims[i];
+    b = q;
+    off_in += idx * p.in_strides[i];
+    off_out += idx * p.out_strides[i];
+  }
+  const int tx = threadIdx.x % TR_T, ty = threadIdx.x / TR_T;
+  // rows of the tile: x; columns: y (the input's unit stride along the lanes)
+  for (int r = ty; r < TR_T; r += 256 / TR_T) {
+    const int64_t x = x0 + r, y = y0 + tx;
+    if (x < dx && y < dy) tile[r][tx] = (TO)in[off_in + x * p.in_strides[X] + y * p.in_strides[ax]];
+  }
+  __syncthreads();
+  for (int r = ty; r < TR_T; r += 256 / TR_T) {
+    const int64_t y = y0 + r, x = x0 + tx;
+    if (x < dx && y < dy) {
+      TO* o = out + off_out + y * p.out_strides[ax] + x * p.out_strides[X];
+      if (p.accumulate) *o += tile[tx][r]; else *o = tile[tx][r];
+    }
+  }
+}
+
 template <typename TI, typename TO>
 static void permute_launch(const PermArgs& p, const void* in, void* out, int64_t total, bool narrow, hipStream_t s) {
+  if (p.ndim >= 2) {
+    const int X = p.ndim - 1;
+    int ax = -1;
+    for (int i = 0; i < X; ++i)
+      if (p.in_strides[i] == 1) ax = i;
+    if (ax >= 0 && p.out_strides[X] == 1 && p.in_strides[X] != 1 && p.dims[X] >= 8 && p.dims[ax] >= 8) {
+      const int64_t tiles = ((p.dims[X] + TR_T - 1) / TR_T) * ((p.dims[ax] + TR_T - 1) / TR_T);
+      const int64_t nbatch = total / (p.dims[X] * p.dims[ax]);
+      if (tiles <= 2147483647LL && nbatch <= 65535) {
+        transpose_kernel<TI, TO><<<dim3((unsigned)tiles, (unsigned)nbatch), 256, 0, s>>>(p, ax, (const TI*)in, (TO*)out);
+        return;
+      }
+    }
+  }
   const unsigned gb = grid_for(total);
   if (narrow)
     permute_kernel<TI, TO, uint32_t><<<gb, 256, 0, s>>>(p, (const TI*)in, (TO*)out, (uint32_t)total);
