@@ -1991,7 +1991,7 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
 // Ordering of the rounds inside one launch.  Round t + 1 of a pair needs
 // only its two blocks as round t left them, each rotated by one other
 // workgroup of the same matrix, so the workgroups synchronise per block, not
-// per round: ver[b * np + B] counts the rounds finished on block B of matrix b
+// per round: ver[(b * np + B) * BJ_VS] counts the rounds finished on block B of matrix b
 // (across sweeps: round t of sweep s is number s * rounds + t).  A workgroup
 // publishes a round by waiting until every wave's stores are acknowledged and
 // then raising the counters of its two blocks; it starts round number g once
@@ -2002,6 +2002,9 @@ __global__ __launch_bounds__(BJ_NT) void bjac_round_kernel(double* A, double* V,
 // finish).  The wait is bounded: a workgroup that polls more than BAR_SPINS
 // times sets *abort and every workgroup then leaves the kernel.
 constexpr unsigned BAR_SPINS = 1u << 21;
+// The block counters sit BJ_VS words apart (one 128-byte line each), so that
+// the workgroups polling and raising them do not contend for shared lines.
+constexpr int64_t BJ_VS = 32;
 
 __device__ __forceinline__ void publish_blocks(unsigned* ver, int64_t P, int64_t Q, int64_t nblk, unsigned done) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -2010,8 +2013,8 @@ __device__ __forceinline__ void publish_blocks(unsigned* ver, int64_t P, int64_t
     // the workgroup's column stores (ordered before this point by the
     // barrier) happen before the counters' new values at agent scope
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (P < nblk) __hip_atomic_store(ver + P, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (Q < nblk) __hip_atomic_store(ver + Q, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (P < nblk) __hip_atomic_store(ver + P * BJ_VS, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (Q < nblk) __hip_atomic_store(ver + Q * BJ_VS, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -2021,8 +2024,8 @@ __device__ __forceinline__ bool wait_blocks(const unsigned* ver, int64_t P, int6
     int ok = 1;
     unsigned spins = 0;
     for (;;) {
-      const bool p_ready = P >= nblk || __hip_atomic_load(ver + P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
-      const bool q_ready = Q >= nblk || __hip_atomic_load(ver + Q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+      const bool p_ready = P >= nblk || __hip_atomic_load(ver + P * BJ_VS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+      const bool q_ready = Q >= nblk || __hip_atomic_load(ver + Q * BJ_VS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
       if (p_ready && q_ready) break;
       if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { ok = 0; break; }
       if (++spins > BAR_SPINS) {
@@ -2072,8 +2075,9 @@ __device__ __forceinline__ bool sweep_barrier(unsigned* count, unsigned target, 
 // rotated or the largest rotated |cos| is at most `stop`, the same decision,
 // from the same sums, as a host loop over per-round launches.  rot and ovl
 // hold one slot per sweep ([sweep][batch]).  sync[0] is the abort flag,
-// sync[1 + b * np + B] the round counters of the blocks (counting across
-// sweeps), then one arrival counter per sweep; everything zero at launch.
+// sync[BJ_VS + (b * np + B) * BJ_VS] the round counters of the blocks
+// (counting across sweeps), then one arrival counter per sweep; everything
+// zero at launch.
 // *sweeps receives the number of sweeps run.  No convergence within
 // max_sweeps, or a wait that ran out, adds one to *fail.  Every workgroup
 // must be resident at once: the host launches it cooperatively (the runtime
@@ -2088,8 +2092,8 @@ __global__ __launch_bounds__(BJ_NT) void bjac_svd_kernel(double* A, double* V, i
   __shared__ int ok_s, go_s;
   const int batch = (int)gridDim.y;
   const unsigned wgs = gridDim.x * gridDim.y;
-  unsigned* ver = sync + 1 + (int64_t)blockIdx.y * np;
-  unsigned* arrive = sync + 1 + (int64_t)batch * np;
+  unsigned* ver = sync + BJ_VS + (int64_t)blockIdx.y * np * BJ_VS;
+  unsigned* arrive = sync + BJ_VS + (int64_t)batch * np * BJ_VS;
   const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     int* rot_s = rot + (int64_t)sw * batch;
@@ -2157,7 +2161,7 @@ int64_t bjac_grid(int64_t n, int batch) {
 
 int64_t bjac_sync_words(int64_t n, int batch, int max_sweeps) {
   const int64_t nblk = (n + BJ_BW - 1) / BJ_BW;
-  return 1 + (nblk + (nblk & 1)) * batch + max_sweeps;
+  return BJ_VS + (nblk + (nblk & 1)) * batch * BJ_VS + max_sweeps;
 }
 
 hipError_t launch_bjac_svd(double* A, double* V, int64_t n, int64_t stride, int batch, int max_sweeps, double tol,
