@@ -52,8 +52,8 @@ BOUND = {"fp64": "mfma", "fp32": "mfma", "bf16": "mfma", "jacobi": "alu", "qr_pa
 # WRITE_SIZE reads them exactly, x1).  Valid for the kernel source it was taken
 # on (hash of the kernel's text), else reported as null.
 TRAFFIC = {"jacobi": {"workload": "ssm_d6_chi72", "precision": "bf16",
-                      "fetch_kib": 2776086.8, "fetch_scale": 2.0, "write_kib": 4943883.5, "write_scale": 1.0,
-                      "source_sha256": "a849cd6da73b53680c9fc64b0322d03d732d3a33bb20adbbddbc207e2d50f087",
+                      "fetch_kib": 2776636.3, "fetch_scale": 2.0, "write_kib": 4943883.5, "write_scale": 1.0,
+                      "source_sha256": "28f137f25291d48796d5e8bd2394262b3ab9b71e71f09e193c65ce0894d1e2e5",
                       "source": ("paper_2512_14414_amd/csrc/kernels.hip", "constexpr int BJ_BW = 8;",
                                  "hipError_t launch_bjac_round(")}}
 KERNEL = {"fp64": "contract_kernel<MODE_F64> (FP64 MFMA)", "fp32": "contract_kernel<MODE_F32> (FP32 MFMA)",
